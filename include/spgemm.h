@@ -1,0 +1,214 @@
+/*
+ * spgemm.h -- C ABI of the MI355X (gfx950) column-wise sparse matrix product.
+ *
+ * Operation (Gustavson column method, paper Section 2.1): for sparse A
+ * (m x k) and B (k x n), both in compressed sparse column (CSC) form,
+ *
+ *     C(:,j) = sum over the stored B(k,j) of B(k,j) * A(:,k),
+ *
+ * returned as CSC C (m x n). The structure of C is the boolean product of the
+ * stored patterns: a row touched by any product is a stored entry, even when
+ * its value cancels to zero (the SPA flags of Algorithm 1 ignore values).
+ *
+ * Storage (Section 2.1): colptr[ncols + 1] with colptr[0] = 0 and
+ * colptr[ncols] = nnz, rowidx[nnz], val[nnz]. Indices are int32. Rows inside
+ * an input column may be stored in any order; rows inside every output column
+ * are ascending.
+ *
+ * Arithmetic: every product A(i,k)*B(k,j) is rounded on its own (no fused
+ * multiply-add) and added to the running value of row i in the storage order
+ * of B(:,j), starting from zero, exactly as the sequential SPA of Algorithm 1.
+ * The result is therefore bit-identical run to run and independent of how the
+ * library splits the work.
+ *
+ * Pointers: every array argument is a DEVICE pointer (memory of the current
+ * HIP device) unless its name ends in _host. The caller owns all A, B, C, G,
+ * dA and dB arrays. `stream` is a hipStream_t (NULL = the default stream).
+ *
+ * Plans: spgemm_symbolic creates (or refreshes) a plan. The plan borrows the
+ * A and B pattern arrays (colptr/rowidx) and the C colptr array: they must stay
+ * allocated and unchanged while the plan is used. The plan owns its device
+ * workspace and frees it in spgemm_plan_destroy.
+ *
+ * Errors: every call returns a status code; nothing aborts or throws across
+ * the ABI. On error, outputs are unspecified. Input checks that keep every
+ * memory access in bounds always run on the device (column pointers monotone
+ * and within nnz, row indices inside their range); a failure gives
+ * SPGEMM_ERR_CSC. Repeated rows inside one input column are only detected with
+ * SPGEMM_VALIDATE (host-side check); without it they are summed in storage
+ * order like distinct products.
+ *
+ * Synchronisation: spgemm_symbolic and the size-query form of spgemm_batched
+ * block the host until the output sizes are known. Every other call is
+ * stream-ordered and returns immediately.
+ */
+#ifndef SPGEMM_H
+#define SPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPGEMM_OK = 0,
+    SPGEMM_ERR_NULL = 1,           /* a required pointer is NULL */
+    SPGEMM_ERR_SHAPE = 2,          /* A.ncols != B.nrows, or negative sizes */
+    SPGEMM_ERR_CSC = 3,            /* malformed CSC input (see above) */
+    SPGEMM_ERR_DTYPE = 4,          /* unknown value type */
+    SPGEMM_ERR_INDEX_OVERFLOW = 5, /* nnz(C) of one problem, or a column's product count, exceeds INT32_MAX */
+    SPGEMM_ERR_NO_MEMORY = 6,      /* device or host allocation failed */
+    SPGEMM_ERR_HIP = 7,            /* a HIP runtime call failed */
+    SPGEMM_ERR_PLAN = 8,           /* plan missing, of the wrong kind, or not in the needed state */
+    SPGEMM_ERR_INVALID = 9         /* invalid option value or argument combination */
+} spgemm_status;
+
+typedef enum { SPGEMM_F32 = 0, SPGEMM_F64 = 1 } spgemm_dtype;
+
+/* One CSC matrix (Section 2.1). colptr/rowidx/val are device pointers; val
+ * may be NULL where only the pattern is needed (symbolic phase). */
+typedef struct {
+    int32_t nrows, ncols, nnz;
+    const int32_t *colptr; /* [ncols + 1] */
+    const int32_t *rowidx; /* [nnz] */
+    const void *val;       /* [nnz] float or double, or NULL */
+} spgemm_csc;
+
+typedef struct spgemm_plan_s *spgemm_plan;
+
+/* flags */
+#define SPGEMM_VALIDATE 1u /* host-side check of both inputs, including repeated rows per column */
+
+/*
+ * Tuning options. Results never depend on them: they only choose which
+ * accumulator handles a column (the role of the paper's switch threshold t,
+ * Section 3.3, and of its hash-size adaptation, Section 3.2). A zero field
+ * takes the library default.
+ *   t_esc       columns with at most this many products (and stored B
+ *               entries) go to the wavefront sort-merge (ESC, Section 4)
+ *               accumulator; 4..256, rounded up to a power of two; default 256.
+ *   t_dense     columns above t_esc with at least this many products go to
+ *               the dense LDS accumulator (SPA, Section 2.2) when A has at
+ *               most dense_rows rows; default 512.
+ *   dense_rows  row limit of the dense LDS accumulator, 64..4096; default 4096.
+ *   hash_cap    planned distinct rows per LDS hash-table window, 128..2048;
+ *               default 2048. Columns with more products are split into
+ *               row windows.
+ */
+typedef struct {
+    int32_t t_esc;
+    int32_t t_dense;
+    int32_t dense_rows;
+    int32_t hash_cap;
+    uint32_t flags;
+} spgemm_options;
+
+/* Work statistics of a plan, for reports and tests. */
+typedef struct {
+    int64_t total_products;     /* sum of Op_j (Section 3.1) */
+    int64_t nnz_c;              /* total stored entries of C */
+    int32_t ncols;              /* columns of C (summed over problems) */
+    int32_t cols_empty;         /* columns with no product */
+    int32_t cols_esc;           /* columns in the sort-merge accumulator */
+    int32_t cols_dense;         /* columns in the dense accumulator */
+    int32_t cols_hash;          /* columns in the hash accumulator */
+    int32_t hash_items;         /* row windows of hash columns */
+    int32_t esc_groups;         /* wavefront groups of sort-merge columns */
+    int32_t nprob;              /* problems in the plan */
+} spgemm_plan_stats;
+
+/*
+ * Symbolic phase of C = A x B (structure only).
+ *   A, B        host pointers to descriptors of device arrays; values unused.
+ *   dt          value type the later numeric call will use.
+ *   opt         tuning options or NULL for defaults.
+ *   plan_inout  on entry NULL or an existing plan (its workspace is reused);
+ *               on success the plan for this pattern pair.
+ *   C_colptr    device array [B.ncols + 1], filled with C's column pointers.
+ *   nnzC_host   host pointer, receives nnz(C).
+ * Blocks until nnz(C) is known.
+ */
+spgemm_status spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, spgemm_dtype dt,
+                              const spgemm_options *opt, void *stream,
+                              spgemm_plan *plan_inout, int32_t *C_colptr, int64_t *nnzC_host);
+
+/*
+ * Numeric phase: fills C's row indices (ascending in every column) and values
+ * for the pattern pair of `plan`, with the value arrays given here (same
+ * sparsity patterns as at symbolic time; values may differ call to call).
+ *   A_val [A.nnz], B_val [B.nnz]   device, type of the plan's dtype.
+ *   C_rowidx [nnz(C)], C_val [nnz(C)]  device, caller-allocated.
+ * Stream-ordered; does not allocate.
+ */
+spgemm_status spgemm_numeric(spgemm_plan plan, const void *A_val, const void *B_val,
+                             int32_t *C_rowidx, void *C_val, void *stream);
+
+/*
+ * Gradients of a loss L with dL/dC = G (given on C's stored entries) with
+ * respect to the stored values of A and B, sparsity patterns fixed:
+ *   dA(i,k) = sum_j G(i,j) B(k,j)  over stored B(k,j), j ascending   (G B^T on A's pattern)
+ *   dB(k,j) = sum_i A(i,k) G(i,j)  over stored A(i,k), A's order     (A^T G on B's pattern)
+ * C_rowidx is the array spgemm_numeric filled. dA_val or dB_val may be NULL
+ * to skip that gradient. Single-problem plans only. The first call builds and
+ * caches a row view of B's pattern inside the plan (may allocate).
+ */
+spgemm_status spgemm_backward(spgemm_plan plan, const void *A_val, const void *B_val,
+                              const int32_t *C_rowidx, const void *G_val,
+                              void *dA_val, void *dB_val, void *stream);
+
+/*
+ * Batched products C_i = A_i x B_i, i < count, of independent problems of any
+ * sizes, run together: every phase is one set of launches over all problems.
+ * Two-call convention:
+ *   C_rowidx_host == NULL: size query. Builds the plan (plan_inout as in
+ *     spgemm_symbolic), fills every C_colptr_host[i] (device array of
+ *     B_i.ncols + 1) and nnzC_host[i]. Blocks.
+ *   C_rowidx_host != NULL: numeric. Uses the plan of the size query, the value
+ *     arrays in A_host[i].val / B_host[i].val, and writes C_rowidx_host[i] /
+ *     C_val_host[i] (device arrays of nnzC_host[i] entries). Stream-ordered;
+ *     does not allocate and may be captured in a HIP graph once the same
+ *     pointers have been passed once (the plan caches the pointer table on the
+ *     device and uploads it only when a pointer changes).
+ * Arrays ending in _host are host arrays of `count` entries (of device
+ * pointers where stated).
+ */
+spgemm_status spgemm_batched(int32_t count, const spgemm_csc *A_host, const spgemm_csc *B_host,
+                             spgemm_dtype dt, const spgemm_options *opt, void *stream,
+                             spgemm_plan *plan_inout, int32_t *const *C_colptr_host,
+                             int64_t *nnzC_host, int32_t *const *C_rowidx_host,
+                             void *const *C_val_host);
+
+/* Per-kernel timing, for measurement tools. When enabled, every launch the
+ * library makes is bracketed by HIP events on its own stream; reading
+ * synchronises those events and sums their durations per kernel name. */
+typedef struct {
+    char name[32];       /* kernel (or launch group) name */
+    int32_t launches;    /* launches recorded since enabling */
+    double total_ms;     /* summed event-measured duration */
+} spgemm_kernel_time;
+
+/* on != 0 starts recording (and clears earlier records); on == 0 stops. */
+spgemm_status spgemm_profile_enable(int32_t on);
+
+/* Copies up to `max` records into out_host and their number into n_host
+ * (host pointers). Waits for the recorded events. */
+spgemm_status spgemm_profile_read(spgemm_kernel_time *out_host, int32_t max, int32_t *n_host);
+
+/* Statistics of a plan after its symbolic phase. */
+spgemm_status spgemm_plan_get_stats(spgemm_plan plan, spgemm_plan_stats *out);
+
+/* Frees the plan and its workspace (synchronises with the plan's last stream). */
+void spgemm_plan_destroy(spgemm_plan plan);
+
+/* Static text for a status code. */
+const char *spgemm_status_string(spgemm_status s);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t spgemm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPGEMM_H */

@@ -1,0 +1,271 @@
+"""Python surface of the HIP library: torch tensors in, torch tensors out.
+
+PyTorch only provides device memory and the current stream; every step of the
+product runs in the library's HIP kernels, reached through the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+__all__ = [
+    "CscTensor", "Plan", "options", "symbolic", "numeric", "matmul", "backward",
+    "SpGEMMFunction", "batched_symbolic", "batched_numeric", "batched_matmul",
+    "profile_enable", "profile_read",
+]
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (and clear) or stop per-kernel event timing inside the library."""
+    _lib.check(_lib.lib().spgemm_profile_enable(1 if on else 0), "profile_enable")
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} recorded since profile_enable(True)."""
+    buf = (_lib.KernelTime * 64)()
+    n = C.c_int32(0)
+    _lib.check(_lib.lib().spgemm_profile_read(buf, 64, C.byref(n)), "profile_read")
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
+            for i in range(n.value)}
+
+
+@dataclass
+class CscTensor:
+    """CSC matrix held in device tensors (int32 colptr/rowidx, float values)."""
+
+    nrows: int
+    ncols: int
+    colptr: torch.Tensor
+    rowidx: torch.Tensor
+    val: Optional[torch.Tensor] = None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowidx.numel())
+
+    @staticmethod
+    def from_host(m, device="cuda", dtype=None) -> "CscTensor":
+        """From any object with nrows/ncols/colptr/rowidx/val numpy arrays."""
+        val = None
+        if getattr(m, "val", None) is not None:
+            v = np.asarray(m.val)
+            if dtype is not None:
+                v = v.astype(dtype)
+            val = torch.from_numpy(np.ascontiguousarray(v)).to(device)
+        return CscTensor(int(m.nrows), int(m.ncols),
+                         torch.from_numpy(np.ascontiguousarray(m.colptr, dtype=np.int32)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(m.rowidx, dtype=np.int32)).to(device),
+                         val)
+
+    def to_host(self):
+        return (self.colptr.cpu().numpy(), self.rowidx.cpu().numpy(),
+                None if self.val is None else self.val.cpu().numpy())
+
+
+def options(t_esc: int = 0, t_dense: int = 0, dense_rows: int = 0, hash_cap: int = 0,
+            validate: bool = False) -> _lib.Options:
+    """Tuning options (zero = library default). They never change results."""
+    return _lib.Options(t_esc, t_dense, dense_rows, hash_cap,
+                        _lib.SPGEMM_VALIDATE if validate else 0)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return t.data_ptr() if t.numel() else None
+
+
+def _desc(m: CscTensor, with_val: bool) -> _lib.Csc:
+    if m.colptr.dtype != torch.int32 or m.rowidx.dtype != torch.int32:
+        raise TypeError("colptr and rowidx must be int32")
+    if m.colptr.numel() != m.ncols + 1:
+        raise ValueError("colptr must hold ncols + 1 entries")
+    return _lib.Csc(m.nrows, m.ncols, m.nnz, _ptr(m.colptr), _ptr(m.rowidx),
+                    _ptr(m.val) if with_val else None)
+
+
+def _code(dtype: torch.dtype) -> int:
+    if dtype == torch.float64:
+        return _lib.SPGEMM_F64
+    if dtype == torch.float32:
+        return _lib.SPGEMM_F32
+    raise TypeError(f"unsupported value type {dtype}")
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+class Plan:
+    """Owns a library plan and keeps the arrays it borrows alive."""
+
+    def __init__(self):
+        self.handle = C.c_void_p()
+        self.keep = []
+        self.dtype = None
+        self.nnz = None
+
+    def stats(self) -> dict:
+        s = _lib.PlanStats()
+        _lib.check(_lib.lib().spgemm_plan_get_stats(self.handle, C.byref(s)), "plan stats")
+        return s.as_dict()
+
+    def close(self):
+        if self.handle:
+            _lib.lib().spgemm_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def symbolic(A: CscTensor, B: CscTensor, dtype=torch.float64, opts=None,
+             plan: Optional[Plan] = None, stream=None, out_colptr: Optional[torch.Tensor] = None):
+    """Structure of C = A x B. Returns (plan, C_colptr, nnz(C)).
+
+    Passing the previous plan (and its colptr as out_colptr) reuses the
+    plan's device workspace: nothing is allocated on repeated calls."""
+    plan = plan or Plan()
+    colptr = out_colptr if out_colptr is not None else torch.empty(
+        B.ncols + 1, dtype=torch.int32, device=A.colptr.device)
+    nnz = C.c_int64(0)
+    da, db = _desc(A, False), _desc(B, False)
+    st = _lib.lib().spgemm_symbolic(C.byref(da), C.byref(db), _code(dtype),
+                                    C.byref(opts) if opts is not None else None, _stream(stream),
+                                    C.byref(plan.handle), _ptr(colptr), C.byref(nnz))
+    _lib.check(st, "spgemm_symbolic")
+    plan.keep = [A.colptr, A.rowidx, B.colptr, B.rowidx, colptr]
+    plan.dtype = dtype
+    plan.nnz = int(nnz.value)
+    plan.shape = (A.nrows, B.ncols)
+    plan.colptr = colptr
+    return plan, colptr, int(nnz.value)
+
+
+def numeric(plan: Plan, A_val: torch.Tensor, B_val: torch.Tensor, C_rowidx: torch.Tensor,
+            C_val: torch.Tensor, stream=None) -> None:
+    for t in (A_val, B_val, C_val):
+        if t.dtype != plan.dtype:
+            raise TypeError("value tensors must have the plan's dtype")
+    st = _lib.lib().spgemm_numeric(plan.handle, _ptr(A_val), _ptr(B_val), _ptr(C_rowidx),
+                                   _ptr(C_val), _stream(stream))
+    _lib.check(st, "spgemm_numeric")
+
+
+def matmul(A: CscTensor, B: CscTensor, opts=None, return_plan: bool = False):
+    """C = A x B with sorted rows in every column."""
+    if A.val is None or B.val is None:
+        raise ValueError("values required")
+    dtype = A.val.dtype
+    if B.val.dtype != dtype:
+        raise TypeError("A and B values must share a dtype")
+    plan, colptr, nnz = symbolic(A, B, dtype, opts)
+    rowidx = torch.empty(nnz, dtype=torch.int32, device=A.val.device)
+    val = torch.empty(nnz, dtype=dtype, device=A.val.device)
+    numeric(plan, A.val, B.val, rowidx, val)
+    Cm = CscTensor(A.nrows, B.ncols, colptr, rowidx, val)
+    return (Cm, plan) if return_plan else Cm
+
+
+def backward(plan: Plan, A_val: torch.Tensor, B_val: torch.Tensor, C_rowidx: torch.Tensor,
+             G_val: torch.Tensor, need_a: bool = True, need_b: bool = True, stream=None):
+    """(dA, dB) of <G, A x B> with respect to the stored values (patterns fixed)."""
+    dA = torch.empty_like(A_val) if need_a else None
+    dB = torch.empty_like(B_val) if need_b else None
+    st = _lib.lib().spgemm_backward(plan.handle, _ptr(A_val), _ptr(B_val), _ptr(C_rowidx),
+                                    _ptr(G_val), _ptr(dA), _ptr(dB), _stream(stream))
+    _lib.check(st, "spgemm_backward")
+    return dA, dB
+
+
+class SpGEMMFunction(torch.autograd.Function):
+    """Differentiable C.val = (A x B).val with respect to A.val and B.val.
+
+    forward(A_val, B_val, A_pattern, B_pattern, plan=None) -> (C_val, C_rowidx, C_colptr);
+    only C_val carries a gradient. Sparsity patterns are fixed inputs.
+    """
+
+    @staticmethod
+    def forward(ctx, A_val, B_val, A: CscTensor, B: CscTensor, plan: Optional[Plan] = None):
+        dtype = A_val.dtype
+        if plan is None or plan.dtype != dtype:
+            plan, colptr, nnz = symbolic(A, B, dtype)
+        colptr, nnz = plan.colptr, plan.nnz
+        rowidx = torch.empty(nnz, dtype=torch.int32, device=A_val.device)
+        val = torch.empty(nnz, dtype=dtype, device=A_val.device)
+        numeric(plan, A_val.contiguous(), B_val.contiguous(), rowidx, val)
+        ctx.save_for_backward(A_val, B_val, rowidx)
+        ctx.plan = plan
+        ctx.mark_non_differentiable(rowidx, colptr)
+        return val, rowidx, colptr
+
+    @staticmethod
+    def backward(ctx, gC, _g_rowidx=None, _g_colptr=None):
+        A_val, B_val, rowidx = ctx.saved_tensors
+        need_a, need_b = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        dA = dB = None
+        if need_a or need_b:
+            dA, dB = backward(ctx.plan, A_val, B_val, rowidx, gC.contiguous(), need_a, need_b)
+        return dA, dB, None, None, None
+
+
+def batched_symbolic(pairs: Sequence[tuple], dtype=torch.float64, opts=None,
+                     plan: Optional[Plan] = None, stream=None):
+    """Size query of C_i = A_i x B_i for every pair. Returns (plan, colptrs, nnzs)."""
+    n = len(pairs)
+    plan = plan or Plan()
+    dev = pairs[0][0].colptr.device if n else torch.device("cuda")
+    colptrs = [torch.empty(b.ncols + 1, dtype=torch.int32, device=dev) for _, b in pairs]
+    As = (_lib.Csc * max(n, 1))(*[_desc(a, False) for a, _ in pairs])
+    Bs = (_lib.Csc * max(n, 1))(*[_desc(b, False) for _, b in pairs])
+    cps = (C.c_void_p * max(n, 1))(*[_ptr(c) for c in colptrs])
+    nnz = (C.c_int64 * max(n, 1))()
+    st = _lib.lib().spgemm_batched(n, As, Bs, _code(dtype),
+                                   C.byref(opts) if opts is not None else None, _stream(stream),
+                                   C.byref(plan.handle), cps, nnz, None, None)
+    _lib.check(st, "spgemm_batched (size query)")
+    plan.keep = [t for a, b in pairs for t in (a.colptr, a.rowidx, b.colptr, b.rowidx)] + colptrs
+    plan.dtype = dtype
+    plan.colptrs = colptrs
+    plan.nnzs = [int(nnz[i]) for i in range(n)]
+    return plan, colptrs, plan.nnzs
+
+
+def batched_numeric(plan: Plan, pairs: Sequence[tuple], rowidxs, vals, stream=None) -> None:
+    n = len(pairs)
+    As = (_lib.Csc * max(n, 1))(*[_desc(a, True) for a, _ in pairs])
+    Bs = (_lib.Csc * max(n, 1))(*[_desc(b, True) for _, b in pairs])
+    cps = (C.c_void_p * max(n, 1))(*[_ptr(c) for c in plan.colptrs])
+    nnz = (C.c_int64 * max(n, 1))(*plan.nnzs)
+    ris = (C.c_void_p * max(n, 1))(*[_ptr(r) for r in rowidxs])
+    vs = (C.c_void_p * max(n, 1))(*[_ptr(v) for v in vals])
+    st = _lib.lib().spgemm_batched(n, As, Bs, _code(plan.dtype), None, _stream(stream),
+                                   C.byref(plan.handle), cps, nnz, ris, vs)
+    _lib.check(st, "spgemm_batched (numeric)")
+
+
+def batched_matmul(pairs: Sequence[tuple], opts=None, return_plan: bool = False):
+    dtype = pairs[0][0].val.dtype
+    plan, colptrs, nnzs = batched_symbolic(pairs, dtype, opts)
+    dev = pairs[0][0].val.device
+    rowidxs = [torch.empty(z, dtype=torch.int32, device=dev) for z in nnzs]
+    vals = [torch.empty(z, dtype=dtype, device=dev) for z in nnzs]
+    batched_numeric(plan, pairs, rowidxs, vals)
+    out = [CscTensor(a.nrows, b.ncols, cp, ri, v)
+           for (a, b), cp, ri, v in zip(pairs, colptrs, rowidxs, vals)]
+    return (out, plan) if return_plan else out

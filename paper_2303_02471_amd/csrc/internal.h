@@ -1,0 +1,154 @@
+// Internal definitions shared by the HIP kernels and the host planner of the
+// column-wise sparse product C = A x B (CSC, Section 2.1 of the paper).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spg {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- bins
+// A column's accumulator is chosen from its product count Op_j (Section 3.1)
+// and its number of stored B entries nB_j:
+//   EMPTY      Op_j == 0: no output entries
+//   ESC_i      max(Op_j, nB_j) <= 4 << i: wavefront sort-merge (Section 4),
+//              64 >> i columns per wavefront group (at most 256 products)
+//   DENSE      dense LDS accumulator over all rows (SPA, Section 2.2)
+//   HASH       LDS hash table per row window (HASH, Section 3.2)
+enum Bin : int {
+    BIN_EMPTY = 0,
+    BIN_ESC0 = 1,  // w <= 4
+    BIN_ESC6 = 7,  // w <= 256
+    BIN_DENSE = 8,
+    BIN_HASH = 9,
+    NBINS = 10
+};
+constexpr int kEscBins = 7;
+constexpr int kEscMaxProducts = 256;  // products and B entries per wavefront group
+
+// dense accumulator: rows per LDS slice
+constexpr int kDenseRows = 4096;
+// hash accumulator: largest table, probe overrun area, threads per block
+constexpr int kHashMax = 4096;
+constexpr int kHashPad = 256;
+constexpr int kHashMin = 64;
+constexpr int kBlock = 256;
+// columns per classification tile
+constexpr int kTile = 512;
+
+// error bits gathered on the device
+enum ErrBits : int {
+    ERR_CSC = 1,        // malformed input seen by a kernel
+    ERR_OPOVF = 2,      // a column's product count exceeds INT32_MAX
+    ERR_ITEMCAP = 4,    // hash row windows exceed the workspace capacity
+    ERR_NNZOVF = 8,     // nnz(C) of a problem exceeds INT32_MAX
+    ERR_GROUP = 16      // a wavefront group exceeded its bounds (inputs changed)
+};
+
+// One problem of a (possibly single-problem) batch. All pointers are device
+// pointers. Column j of this problem is global column col0 + j.
+struct Prob {
+    int32_t m, k, n, col0;
+    int32_t nnza, nnzb, pad0, pad1;
+    const int32_t *acp, *ari;
+    const void *av;
+    const int32_t *bcp, *bri;
+    const void *bv;
+    int32_t *ccp, *cri;
+    void *cv;
+};
+
+// Device header written by the planning kernels.
+struct Hdr {
+    int32_t bin_count[NBINS];
+    int32_t bin_cursor[NBINS];
+    int32_t hash_cols;        // == bin_count[BIN_HASH]
+    int32_t item_count;       // row windows of hash columns
+    unsigned long long hash_cursor;  // (items << 32) | columns placed
+    int32_t err;
+    int32_t pad;
+    unsigned long long total_op;
+};
+
+// Resolved tuning values.
+struct Tune {
+    int32_t esc_bins;   // number of ESC sub-bins in use, 1..7 (t_esc = 4 << (esc_bins-1))
+    int32_t t_dense;
+    int32_t dense_rows;
+    int32_t hash_cap;
+};
+
+// Kernel arguments common to all planning / accumulation kernels.
+struct KArgs {
+    Prob single;            // used when nprob == 1
+    const Prob *table;      // device table when nprob > 1
+    const int32_t *col0s;   // device [nprob + 1] global column offsets (nprob > 1)
+    int32_t nprob;
+    int32_t ncols;          // total columns over all problems
+    int32_t ntiles;
+    int32_t item_cap;
+    const int4 *tiles;      // (pid, j0, j1, 0) when nprob > 1
+    Tune tune;
+    Hdr *hdr;
+    int32_t *op;            // [ncols]
+    int32_t *binw;          // [ncols] bin | (windows << 8)
+    int32_t *binlist;       // [ncols]
+    int32_t *gnnz;          // [ncols]
+    int32_t *firstitem;     // [ncols]: first window index of each hash column
+    int32_t *itemcnt;       // [item_cap]
+};
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+__device__ __forceinline__ int find_prob(const KArgs &a, int g) {
+    if (a.nprob == 1) return 0;
+    int lo = 0, hi = a.nprob;  // last p with col0s[p] <= g
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a.col0s[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ Prob get_prob(const KArgs &a, int pid) {
+    return a.nprob == 1 ? a.single : a.table[pid];
+}
+
+// Number of hash row windows of a column with `op` products.
+__host__ __device__ inline int hash_windows(int op, int cap) {
+    return op <= cap ? 1 : ceil_div(op, cap);
+}
+
+// Table size of one hash row window: a power of two at least twice the
+// planned distinct rows (load factor <= 1/2), within [kHashMin, kHashMax].
+__host__ __device__ inline int hash_table_size(int op, int windows) {
+    int per = ceil_div(op, windows);
+    int h = kHashMin;
+    while (h < 2 * per && h < kHashMax) h <<= 1;
+    return h;
+}
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.
+hipError_t launch_classify(const KArgs &a, hipStream_t s);
+hipError_t launch_place(const KArgs &a, hipStream_t s);
+hipError_t launch_esc(const KArgs &a, bool numeric, bool f64, int grid, hipStream_t s);
+hipError_t launch_window(const KArgs &a, bool numeric, bool f64, bool dense, int grid,
+                         hipStream_t s);
+hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk,
+                       long long *totals, hipStream_t s);
+hipError_t launch_btranspose(const Prob &p, int32_t *rowptr, int32_t *fill, int32_t *colj,
+                             int32_t *pos, long long *scratch, int nscratch, hipStream_t s);
+hipError_t launch_backward(const Prob &p, bool f64, const void *av, const void *bv,
+                           const int32_t *cri, const void *gv, void *da, void *db,
+                           const int32_t *rowptr, const int32_t *colj, const int32_t *pos,
+                           int *err, hipStream_t s);
+hipError_t launch_scan_i32(const int32_t *in, int n, long long *bsum, int nbsum, int32_t *out,
+                           hipStream_t s);
+
+constexpr int kScanBlock = 1024;  // elements per scan block
+
+}  // namespace spg

@@ -1,0 +1,420 @@
+// Planning kernels: per-column product count Op_j (Section 3.1), accumulator
+// choice (the role of the paper's sort + hybrid switch, Sections 3.1-3.3),
+// placement of columns into per-accumulator lists, and the column-pointer scan.
+#include "devutil.h"
+
+namespace spg {
+
+// ---------------------------------------------------------------- classify
+// One workgroup per tile of at most kTile columns of one problem. The tile's
+// stored B entries are contiguous; threads walk them flat (coalesced reads of
+// B.rowidx, gathers of A.colptr), and add Z^A_k to the owning column's count.
+// Every index read here is checked before it is used as an address.
+__global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
+    __shared__ int s_bcp[kTile + 1];
+    __shared__ unsigned long long s_op[kTile];
+    __shared__ int s_hist[NBINS];
+    __shared__ int s_items;
+    __shared__ int s_err;
+    __shared__ unsigned long long s_tot;
+
+    int pid, j0, j1;
+    if (a.nprob == 1) {
+        pid = 0;
+        j0 = blockIdx.x * kTile;
+        j1 = min(a.single.n, j0 + kTile);
+    } else {
+        int4 tl = a.tiles[blockIdx.x];
+        pid = tl.x; j0 = tl.y; j1 = tl.z;
+    }
+    const Prob d = get_prob(a, pid);
+    const int nt = j1 - j0;
+    const int tid = threadIdx.x;
+
+    for (int c = tid; c <= nt; c += kBlock) s_bcp[c] = d.bcp[j0 + c];
+    for (int c = tid; c < nt; c += kBlock) s_op[c] = 0;
+    if (tid < NBINS) s_hist[tid] = 0;
+    if (tid == 0) { s_items = 0; s_err = 0; s_tot = 0; }
+    __syncthreads();
+
+    // column pointers of B: monotone, inside [0, nnz], 0 first, nnz last
+    int err = 0;
+    for (int c = tid; c < nt; c += kBlock)
+        if (s_bcp[c + 1] < s_bcp[c]) err = ERR_CSC;
+    if (tid == 0) {
+        if (s_bcp[0] < 0 || s_bcp[nt] > d.nnzb) err = ERR_CSC;
+        if (j0 == 0 && s_bcp[0] != 0) err = ERR_CSC;
+        if (j1 == d.n && s_bcp[nt] != d.nnzb) err = ERR_CSC;
+        if (j0 == 0) {  // once per problem: A's first and last column pointer
+            if (d.acp[0] != 0 || d.acp[d.k] != d.nnza) err = ERR_CSC;
+        }
+    }
+    if (err) atomicOr(&s_err, err);
+    __syncthreads();
+    if (s_err) {
+        if (tid == 0) atomicOr(&a.hdr->err, s_err);
+        return;
+    }
+
+    const int pb = s_bcp[0], pe = s_bcp[nt];
+    err = 0;
+    for (int p0 = pb; p0 < pe; p0 += 4 * kBlock) {
+        int kk[4], z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int p = p0 + u * kBlock + tid;
+            kk[u] = p < pe ? d.bri[p] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            z[u] = 0;
+            int k = kk[u];
+            if (p0 + u * kBlock + tid < pe) {
+                if (k < 0 || k >= d.k) {
+                    err = ERR_CSC;
+                } else {
+                    int x0 = d.acp[k], x1 = d.acp[k + 1];
+                    if (x0 < 0 || x1 < x0 || x1 > d.nnza) err = ERR_CSC;
+                    else z[u] = x1 - x0;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int p = p0 + u * kBlock + tid;
+            if (z[u] > 0) {
+                int c = last_le(s_bcp, nt + 1, p);
+                // skip empty columns that share the pointer value
+                atomicAdd(&s_op[c], (unsigned long long)z[u]);
+            }
+        }
+    }
+    if (err) atomicOr(&s_err, err);
+    __syncthreads();
+    if (s_err) {
+        if (tid == 0) atomicOr(&a.hdr->err, s_err);
+        return;
+    }
+
+    const int esc_max = 4 << (a.tune.esc_bins - 1);
+    unsigned long long tot = 0;
+    err = 0;
+    for (int c = tid; c < nt; c += kBlock) {
+        const int g = d.col0 + j0 + c;
+        unsigned long long op64 = s_op[c];
+        const int nb = s_bcp[c + 1] - s_bcp[c];
+        if (op64 > 0x7fffffffull) { err = ERR_OPOVF; op64 = 0x7fffffffull; }
+        tot += op64;
+        const int op = (int)op64;
+        const int w = max(op, nb);
+        int bin, W = 0;
+        if (op == 0) bin = BIN_EMPTY;
+        else if (w <= esc_max) bin = BIN_ESC0 + max(ceil_log2(w), 2) - 2;
+        else if (d.m <= a.tune.dense_rows && op >= a.tune.t_dense) bin = BIN_DENSE;
+        else { bin = BIN_HASH; W = hash_windows(op, a.tune.hash_cap); }
+        a.op[g] = op;
+        a.binw[g] = bin | (W << 8);
+        a.gnnz[g] = 0;
+        atomicAdd(&s_hist[bin], 1);
+        if (W) atomicAdd(&s_items, W);
+    }
+    if (err) atomicOr(&s_err, err);
+    // tile total of products
+    atomicAdd(&s_tot, tot);
+    __syncthreads();
+    if (tid < NBINS && s_hist[tid]) atomicAdd(&a.hdr->bin_count[tid], s_hist[tid]);
+    if (tid == 0) {
+        if (s_items) atomicAdd(&a.hdr->item_count, s_items);
+        atomicAdd(&a.hdr->total_op, s_tot);
+        if (s_err) atomicOr(&a.hdr->err, s_err);
+    }
+}
+
+// ---------------------------------------------------------------- place
+// Same tiling. Each tile reserves a contiguous range in every bin list with
+// one global atomic per bin, then writes its columns there. Hash columns also
+// reserve their row windows; column and window cursors advance in one 64-bit
+// atomic so that window numbering follows the column order of the list.
+__global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
+    __shared__ int s_start[NBINS];
+    __shared__ int s_cnt[NBINS];
+    __shared__ int s_base[NBINS];
+    __shared__ unsigned long long s_hpack;
+    __shared__ unsigned long long s_hbase;
+
+    if (a.hdr->err & (ERR_CSC | ERR_OPOVF)) return;
+    int pid, j0, j1;
+    if (a.nprob == 1) {
+        pid = 0;
+        j0 = blockIdx.x * kTile;
+        j1 = min(a.single.n, j0 + kTile);
+    } else {
+        int4 tl = a.tiles[blockIdx.x];
+        pid = tl.x; j0 = tl.y; j1 = tl.z;
+    }
+    const int col0 = a.nprob == 1 ? 0 : a.table[pid].col0;
+    const int nt = j1 - j0;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int run = 0;
+        for (int b = 0; b < NBINS; ++b) {
+            s_start[b] = run;
+            run += a.hdr->bin_count[b];
+        }
+        s_hpack = 0;
+    }
+    if (tid < NBINS) s_cnt[tid] = 0;
+    __syncthreads();
+
+    constexpr int PER = kTile / kBlock;
+    int rank[PER], binv[PER];
+    unsigned long long hold[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        int c = tid + u * kBlock;
+        binv[u] = -1;
+        if (c < nt) {
+            int bw = a.binw[col0 + j0 + c];
+            int bin = bw & 255, W = bw >> 8;
+            binv[u] = bin;
+            if (bin == BIN_HASH)
+                hold[u] = atomicAdd(&s_hpack, ((unsigned long long)W << 32) | 1ull);
+            else
+                rank[u] = atomicAdd(&s_cnt[bin], 1);
+        }
+    }
+    __syncthreads();
+    if (tid < NBINS && tid != BIN_HASH && s_cnt[tid])
+        s_base[tid] = s_start[tid] + atomicAdd(&a.hdr->bin_cursor[tid], s_cnt[tid]);
+    if (tid == BIN_HASH && s_hpack) s_hbase = atomicAdd(&a.hdr->hash_cursor, s_hpack);
+    __syncthreads();
+    const int hstart = s_start[BIN_HASH];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        int c = tid + u * kBlock;
+        if (c >= nt) continue;
+        const int g = col0 + j0 + c;
+        if (binv[u] == BIN_HASH) {
+            unsigned long long pos = s_hbase + hold[u];
+            int hcol = (int)(pos & 0xffffffffull);
+            int item = (int)(pos >> 32);
+            a.binlist[hstart + hcol] = g;
+            a.firstitem[hcol] = item;
+        } else {
+            a.binlist[s_base[binv[u]] + rank[u]] = g;
+        }
+    }
+    if (tid == 0 && s_hpack) {
+        unsigned long long end = s_hbase + s_hpack;
+        if ((long long)(end >> 32) > (long long)a.item_cap) atomicOr(&a.hdr->err, ERR_ITEMCAP);
+    }
+}
+
+// ---------------------------------------------------------------- scan of nnz
+// Exclusive prefix sum of the per-column counts over all problems, in 64-bit,
+// in three launches: block sums, a scan of the block sums, and the final
+// per-block scan that writes every problem's column pointers.
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ in, int n,
+                                                        long long *__restrict__ bsum) {
+    __shared__ long long s[kBlock / 64];
+    const int base = blockIdx.x * kScanBlock;
+    long long v = 0;
+#pragma unroll
+    for (int u = 0; u < kScanBlock / kBlock; ++u) {
+        int i = base + u * kBlock + threadIdx.x;
+        if (i < n) v += in[i];
+    }
+    // wave reduction through 32-bit halves would overflow; reduce in LDS
+    for (int d = 32; d >= 1; d >>= 1) {
+        int lo = (int)(unsigned)v, hi = (int)(unsigned)((unsigned long long)v >> 32);
+        lo = __builtin_amdgcn_ds_bpermute((lane_id() ^ d) << 2, lo);
+        hi = __builtin_amdgcn_ds_bpermute((lane_id() ^ d) << 2, hi);
+        v += (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    }
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += s[w];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(long long *bsum, int nblk) {
+    __shared__ long long s[1024];
+    __shared__ long long carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblk; base += 1024) {
+        int i = base + threadIdx.x;
+        long long v = i < nblk ? bsum[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            long long t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nblk) bsum[i] = carry + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += s[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[nblk] = carry;
+}
+
+// Final pass. For one problem the int32 column pointers are written directly
+// (with an overflow check); for several problems the 64-bit global prefix is
+// kept in gcp and k_scan_finish cuts it per problem.
+__global__ __launch_bounds__(kBlock) void k_scan_down(KArgs a, long long *__restrict__ gcp,
+                                                      const long long *__restrict__ bsum,
+                                                      long long *__restrict__ totals) {
+    __shared__ long long s[kScanBlock];
+    const int n = a.ncols;
+    const int base = blockIdx.x * kScanBlock;
+    for (int u = 0; u < kScanBlock / kBlock; ++u) {
+        int i = base + u * kBlock + threadIdx.x;
+        s[u * kBlock + threadIdx.x] = i < n ? a.gnnz[i] : 0;
+    }
+    __syncthreads();
+    // thread t scans elements [4t, 4t+4), then a scan over threads
+    constexpr int PER = kScanBlock / kBlock;
+    long long loc[PER], run = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        loc[u] = run;
+        run += s[threadIdx.x * PER + u];
+    }
+    __syncthreads();
+    s[threadIdx.x] = run;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {
+        long long t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const long long off = bsum[blockIdx.x] + s[threadIdx.x] - run;
+    int err = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        int i = base + threadIdx.x * PER + u;
+        if (i >= n) break;
+        long long v = off + loc[u];
+        if (a.nprob == 1) {
+            if (v > 0x7fffffffll) err = ERR_NNZOVF;
+            a.single.ccp[i] = (int32_t)v;
+        } else {
+            gcp[i] = v;
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        long long total = bsum[gridDim.x];
+        if (a.nprob == 1) {
+            if (total > 0x7fffffffll) err = ERR_NNZOVF;
+            a.single.ccp[n] = (int32_t)total;
+            totals[0] = total;
+        } else {
+            gcp[n] = total;
+        }
+    }
+    if (err) atomicOr(&a.hdr->err, err);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_finish(KArgs a, const long long *__restrict__ gcp,
+                                                        long long *__restrict__ totals) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < a.ncols) {
+        const int pid = find_prob(a, i);
+        const Prob &d = a.table[pid];
+        long long v = gcp[i] - gcp[d.col0];
+        d.ccp[i - d.col0] = (int32_t)v;  // per-problem total checked below
+    }
+    if (i < a.nprob) {
+        const Prob &d = a.table[i];
+        long long t = gcp[d.col0 + d.n] - gcp[d.col0];
+        if (t > 0x7fffffffll) atomicOr(&a.hdr->err, ERR_NNZOVF);
+        d.ccp[d.n] = (int32_t)(t > 0x7fffffffll ? 0x7fffffffll : t);
+        totals[i] = t;
+    }
+}
+
+// generic exclusive scan of int32 values into int32 (in place allowed)
+__global__ __launch_bounds__(kBlock) void k_scan_down_i32(const int32_t *in, int n,
+                                                          const long long *__restrict__ bsum,
+                                                          int32_t *out) {
+    __shared__ long long s[kScanBlock];
+    const int base = blockIdx.x * kScanBlock;
+    for (int u = 0; u < kScanBlock / kBlock; ++u) {
+        int i = base + u * kBlock + threadIdx.x;
+        s[u * kBlock + threadIdx.x] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    constexpr int PER = kScanBlock / kBlock;
+    long long loc[PER], run = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        loc[u] = run;
+        run += s[threadIdx.x * PER + u];
+    }
+    __syncthreads();
+    s[threadIdx.x] = run;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {
+        long long t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const long long off = bsum[blockIdx.x] + s[threadIdx.x] - run;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        int i = base + threadIdx.x * PER + u;
+        if (i < n) out[i] = (int32_t)(off + loc[u]);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_scan_i32(const int32_t *in, int n, long long *bsum, int nbsum, int32_t *out,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nblk = ceil_div(n, kScanBlock);
+    if (nblk + 1 > nbsum) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kBlock), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nblk);
+    hipLaunchKernelGGL(k_scan_down_i32, dim3(nblk), dim3(kBlock), 0, s, in, n,
+                       (const long long *)bsum, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const KArgs &a, hipStream_t s) {
+    if (a.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_classify, dim3(a.ntiles), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(const KArgs &a, hipStream_t s) {
+    if (a.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_place, dim3(a.ntiles), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk,
+                       long long *totals, hipStream_t s) {
+    if (a.ncols > 0) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kBlock), 0, s,
+                           (const int32_t *)a.gnnz, a.ncols, bsum);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nblk);
+        hipLaunchKernelGGL(k_scan_down, dim3(nblk), dim3(kBlock), 0, s, a, gcp,
+                           (const long long *)bsum, totals);
+    }
+    if (a.nprob > 1) {
+        int n = a.ncols > a.nprob ? a.ncols : a.nprob;
+        hipLaunchKernelGGL(k_scan_finish, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, a,
+                           (const long long *)gcp, totals);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace spg

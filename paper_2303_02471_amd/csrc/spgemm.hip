@@ -1,0 +1,621 @@
+// Host side of the C ABI (include/spgemm.h): argument checks, plans, device
+// workspace, and the launch sequence of every phase.
+//
+// Symbolic:  classify (Op_j, accumulator bin) -> place (bin lists) ->
+//            ESC / dense / hash counts of distinct rows -> prefix scan into
+//            the column pointers -> one device-to-host copy of the totals.
+// Numeric:   ESC, dense and hash accumulators write rows and values.
+// Backward:  row view of B (once per plan) -> sampled products for dB, dA.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/spgemm.h"
+#include "internal.h"
+
+using namespace spg;
+
+struct spgemm_plan_s {
+    int device = -1;
+    spgemm_dtype dt = SPGEMM_F64;
+    bool batched = false;
+    int nprob = 0;
+    Tune tune{};
+    uint32_t flags = 0;
+    std::vector<Prob> probs;  // host copy of the problem table
+    int ncols = 0, ntiles = 0, item_cap = 0, nblk = 0;
+    bool symbolic_ok = false;
+
+    // device workspace (one allocation, carved)
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    Hdr *hdr = nullptr;
+    int32_t *op = nullptr, *binw = nullptr, *binlist = nullptr, *gnnz = nullptr,
+            *firstitem = nullptr, *itemcnt = nullptr, *col0s = nullptr;
+    long long *gcp = nullptr, *bsum = nullptr, *totals = nullptr;
+    Prob *table = nullptr;
+    int4 *tiles = nullptr;
+    int nbsum = 0;
+
+    // pinned host mirror of the header and totals
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    Hdr hdr_host{};
+    std::vector<long long> totals_host;
+
+    // table currently on the device (batched numeric uploads when it changes)
+    std::vector<Prob> table_dev_copy;
+    hipEvent_t upload_done = nullptr;
+
+    // backward: row view of B
+    void *bt = nullptr;
+    size_t bt_bytes = 0;
+    bool bt_ready = false;
+    int *bt_err = nullptr;
+
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+constexpr int32_t kVersion = 10000;  // 1.0.0
+
+// ---------------------------------------------------------------- profiling
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRec> recs;
+    size_t used = 0;
+} g_prof;
+
+struct ProfScope {
+    ProfRec *r = nullptr;
+    hipStream_t s;
+    ProfScope(const char *name, hipStream_t st) : s(st) {
+        if (!g_prof.on) return;
+        if (g_prof.used == g_prof.recs.size()) {
+            ProfRec nr{name, nullptr, nullptr};
+            if (hipEventCreate(&nr.a) != hipSuccess || hipEventCreate(&nr.b) != hipSuccess) return;
+            g_prof.recs.push_back(nr);
+        }
+        r = &g_prof.recs[g_prof.used++];
+        r->name = name;
+        (void)hipEventRecord(r->a, s);
+    }
+    ~ProfScope() {
+        if (r) (void)hipEventRecord(r->b, s);
+    }
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+spgemm_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return SPGEMM_OK;
+    if (e == hipErrorOutOfMemory) return SPGEMM_ERR_NO_MEMORY;
+    return SPGEMM_ERR_HIP;
+}
+
+#define SPG_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_status(e_);   \
+    } while (0)
+
+spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flags) {
+    int t_esc = 256, t_dense = 512, dense_rows = kDenseRows, cap = kHashMax / 2;
+    flags = 0;
+    if (opt) {
+        if (opt->t_esc) t_esc = opt->t_esc;
+        if (opt->t_dense) t_dense = opt->t_dense;
+        if (opt->dense_rows) dense_rows = opt->dense_rows;
+        if (opt->hash_cap) cap = opt->hash_cap;
+        flags = opt->flags;
+    }
+    if (t_esc < 4 || t_esc > kEscMaxProducts) return SPGEMM_ERR_INVALID;
+    if (t_dense < 1) return SPGEMM_ERR_INVALID;
+    if (dense_rows < 64 || dense_rows > kDenseRows) return SPGEMM_ERR_INVALID;
+    if (cap < 128 || cap > kHashMax / 2) return SPGEMM_ERR_INVALID;
+    int bins = 1;
+    while ((4 << (bins - 1)) < t_esc) ++bins;  // t_esc rounded up to a power of two
+    t.esc_bins = bins;
+    t.t_dense = t_dense;
+    t.dense_rows = dense_rows;
+    t.hash_cap = cap;
+    return SPGEMM_OK;
+}
+
+spgemm_status check_desc(const spgemm_csc *m, bool need_val) {
+    if (!m) return SPGEMM_ERR_NULL;
+    if (m->nrows < 0 || m->ncols < 0 || m->nnz < 0) return SPGEMM_ERR_SHAPE;
+    if (!m->colptr) return SPGEMM_ERR_NULL;
+    if (m->nnz > 0 && !m->rowidx) return SPGEMM_ERR_NULL;
+    if (need_val && m->nnz > 0 && !m->val) return SPGEMM_ERR_NULL;
+    return SPGEMM_OK;
+}
+
+// Host-side CSC check including repeated rows (SPGEMM_VALIDATE).
+spgemm_status validate_host(const spgemm_csc *m) {
+    std::vector<int32_t> cp((size_t)m->ncols + 1), ri((size_t)m->nnz);
+    if (hipMemcpy(cp.data(), m->colptr, cp.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return SPGEMM_ERR_HIP;
+    if (m->nnz && hipMemcpy(ri.data(), m->rowidx, ri.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return SPGEMM_ERR_HIP;
+    if (cp[0] != 0 || cp[m->ncols] != m->nnz) return SPGEMM_ERR_CSC;
+    std::vector<int32_t> stamp((size_t)std::max(m->nrows, 1), -1);
+    for (int32_t j = 0; j < m->ncols; ++j) {
+        if (cp[j + 1] < cp[j]) return SPGEMM_ERR_CSC;
+        for (int32_t p = cp[j]; p < cp[j + 1]; ++p) {
+            int32_t r = ri[p];
+            if (r < 0 || r >= m->nrows || stamp[r] == j) return SPGEMM_ERR_CSC;
+            stamp[r] = j;
+        }
+    }
+    return SPGEMM_OK;
+}
+
+// carve the workspace for the plan's current sizes; grows the allocation
+spgemm_status ensure_workspace(spgemm_plan p) {
+    const size_t n = (size_t)std::max(p->ncols, 1);
+    p->nblk = ceil_div(std::max(p->ncols, 1), kScanBlock);
+    p->nbsum = p->nblk + 2;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t o_hdr = take(sizeof(Hdr));
+    const size_t o_op = take(4 * n), o_binw = take(4 * n), o_binlist = take(4 * n),
+                 o_gnnz = take(4 * n), o_first = take(4 * n);
+    const size_t o_item = take(4 * (size_t)p->item_cap);
+    const size_t o_gcp = take(8 * (n + 1));
+    const size_t o_bsum = take(8 * (size_t)p->nbsum);
+    const size_t o_tot = take(8 * (size_t)std::max(p->nprob, 1));
+    const size_t o_tab = take(sizeof(Prob) * (size_t)std::max(p->nprob, 1));
+    const size_t o_c0 = take(4 * ((size_t)p->nprob + 1));
+    const size_t o_tiles = take(sizeof(int4) * (size_t)std::max(p->ntiles, 1));
+    const size_t need = off;
+    if (need > p->ws_bytes) {
+        if (p->ws) {
+            if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
+            (void)hipFree(p->ws);
+            p->ws = nullptr;
+            p->ws_bytes = 0;
+        }
+        if (hipMalloc(&p->ws, need) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
+        p->ws_bytes = need;
+        p->table_dev_copy.clear();
+    }
+    char *b = (char *)p->ws;
+    p->hdr = (Hdr *)(b + o_hdr);
+    p->op = (int32_t *)(b + o_op);
+    p->binw = (int32_t *)(b + o_binw);
+    p->binlist = (int32_t *)(b + o_binlist);
+    p->gnnz = (int32_t *)(b + o_gnnz);
+    p->firstitem = (int32_t *)(b + o_first);
+    p->itemcnt = (int32_t *)(b + o_item);
+    p->gcp = (long long *)(b + o_gcp);
+    p->bsum = (long long *)(b + o_bsum);
+    p->totals = (long long *)(b + o_tot);
+    p->table = (Prob *)(b + o_tab);
+    p->col0s = (int32_t *)(b + o_c0);
+    p->tiles = (int4 *)(b + o_tiles);
+
+    const size_t pin = sizeof(Hdr) + 8 * (size_t)std::max(p->nprob, 1);
+    if (pin > p->pinned_bytes) {
+        if (p->pinned) (void)hipHostFree(p->pinned);
+        p->pinned = nullptr;
+        if (hipHostMalloc(&p->pinned, pin, hipHostMallocDefault) != hipSuccess)
+            return SPGEMM_ERR_NO_MEMORY;
+        p->pinned_bytes = pin;
+    }
+    return SPGEMM_OK;
+}
+
+KArgs make_args(spgemm_plan p) {
+    KArgs a{};
+    a.single = p->probs.empty() ? Prob{} : p->probs[0];
+    a.table = p->table;
+    a.col0s = p->col0s;
+    a.nprob = p->nprob;
+    a.ncols = p->ncols;
+    a.ntiles = p->ntiles;
+    a.item_cap = p->item_cap;
+    a.tiles = p->tiles;
+    a.tune = p->tune;
+    a.hdr = p->hdr;
+    a.op = p->op;
+    a.binw = p->binw;
+    a.binlist = p->binlist;
+    a.gnnz = p->gnnz;
+    a.firstitem = p->firstitem;
+    a.itemcnt = p->itemcnt;
+    return a;
+}
+
+int esc_groups(const Hdr &h) {
+    int g = 0;
+    for (int i = 0; i < kEscBins; ++i) g += ceil_div(h.bin_count[BIN_ESC0 + i], 64 >> i);
+    return g;
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// Symbolic launch sequence; returns after the totals are on the host.
+spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4> &tiles_host) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        spgemm_status st = ensure_workspace(p);
+        if (st) return st;
+        if (p->nprob > 1) {
+            std::vector<int32_t> c0(p->nprob + 1);
+            for (int i = 0; i < p->nprob; ++i) c0[i] = p->probs[i].col0;
+            c0[p->nprob] = p->ncols;
+            SPG_TRY(hipMemcpyAsync(p->table, p->probs.data(), sizeof(Prob) * p->nprob,
+                                   hipMemcpyHostToDevice, s));
+            SPG_TRY(hipMemcpyAsync(p->col0s, c0.data(), 4 * c0.size(), hipMemcpyHostToDevice, s));
+            SPG_TRY(hipMemcpyAsync(p->tiles, tiles_host.data(), sizeof(int4) * tiles_host.size(),
+                                   hipMemcpyHostToDevice, s));
+            p->table_dev_copy = p->probs;
+        }
+        SPG_TRY(hipMemsetAsync(p->hdr, 0, sizeof(Hdr), s));
+        const KArgs a = make_args(p);
+        const bool f64 = p->dt == SPGEMM_F64;
+        const int cus = device_cus();
+        { ProfScope ps("classify", s); SPG_TRY(launch_classify(a, s)); }
+        { ProfScope ps("place", s); SPG_TRY(launch_place(a, s)); }
+        if (p->ncols > 0) {
+            { ProfScope ps("esc_symbolic", s);
+              SPG_TRY(launch_esc(a, false, f64, std::min(ceil_div(p->ncols, 4), cus * 16), s)); }
+            { ProfScope ps("dense_symbolic", s);
+              SPG_TRY(launch_window(a, false, f64, true, std::min(p->ncols, cus * 8), s)); }
+            { ProfScope ps("hash_symbolic", s);
+              SPG_TRY(launch_window(a, false, f64, false, std::min(p->item_cap, cus * 8), s)); }
+        }
+        if (p->ncols > 0) {
+            ProfScope ps("scan", s);
+            SPG_TRY(launch_scan(a, p->gcp, p->bsum, p->nblk, p->totals, s));
+        }
+        SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+        if (p->ncols > 0)
+            SPG_TRY(hipMemcpyAsync((char *)p->pinned + sizeof(Hdr), p->totals,
+                                   8 * (size_t)p->nprob, hipMemcpyDeviceToHost, s));
+        SPG_TRY(hipStreamSynchronize(s));
+        std::memcpy(&p->hdr_host, p->pinned, sizeof(Hdr));
+        p->totals_host.assign(p->nprob, 0);
+        if (p->ncols > 0)
+            std::memcpy(p->totals_host.data(), (char *)p->pinned + sizeof(Hdr), 8 * (size_t)p->nprob);
+        const int err = p->hdr_host.err;
+        if (err & ERR_ITEMCAP) {
+            // more hash row windows than planned: grow and redo once
+            p->item_cap = p->hdr_host.item_count + 1024;
+            continue;
+        }
+        if (err & (ERR_CSC | ERR_GROUP)) return SPGEMM_ERR_CSC;
+        if (err & (ERR_OPOVF | ERR_NNZOVF)) return SPGEMM_ERR_INDEX_OVERFLOW;
+        if (p->ncols == 0) {
+            // no columns at all: every problem's column pointer is {0}
+            for (int i = 0; i < p->nprob; ++i)
+                SPG_TRY(hipMemsetAsync(p->probs[i].ccp, 0, sizeof(int32_t), s));
+            SPG_TRY(hipStreamSynchronize(s));
+        }
+        p->symbolic_ok = true;
+        return SPGEMM_OK;
+    }
+    return SPGEMM_ERR_NO_MEMORY;
+}
+
+spgemm_status run_numeric(spgemm_plan p, hipStream_t s) {
+    const KArgs a = make_args(p);
+    const bool f64 = p->dt == SPGEMM_F64;
+    const Hdr &h = p->hdr_host;
+    const int cus = device_cus();
+    const int ng = esc_groups(h);
+    { ProfScope ps("esc_numeric", s);
+      SPG_TRY(launch_esc(a, true, f64, std::min(ceil_div(ng, 4), cus * 16), s)); }
+    { ProfScope ps("dense_numeric", s);
+      SPG_TRY(launch_window(a, true, f64, true, std::min(h.bin_count[BIN_DENSE], cus * 8), s)); }
+    { ProfScope ps("hash_numeric", s);
+      SPG_TRY(launch_window(a, true, f64, false, std::min(h.item_count, cus * 8), s)); }
+    p->last_stream = s;
+    return SPGEMM_OK;
+}
+
+spgemm_plan get_or_new_plan(spgemm_plan *inout) {
+    if (*inout) return *inout;
+    return new (std::nothrow) spgemm_plan_s();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *spgemm_status_string(spgemm_status s) {
+    switch (s) {
+        case SPGEMM_OK: return "ok";
+        case SPGEMM_ERR_NULL: return "null pointer";
+        case SPGEMM_ERR_SHAPE: return "shape mismatch";
+        case SPGEMM_ERR_CSC: return "malformed CSC input";
+        case SPGEMM_ERR_DTYPE: return "unknown value type";
+        case SPGEMM_ERR_INDEX_OVERFLOW: return "index overflow (int32)";
+        case SPGEMM_ERR_NO_MEMORY: return "out of memory";
+        case SPGEMM_ERR_HIP: return "HIP runtime error";
+        case SPGEMM_ERR_PLAN: return "invalid plan";
+        case SPGEMM_ERR_INVALID: return "invalid argument";
+    }
+    return "unknown status";
+}
+
+int32_t spgemm_version(void) { return kVersion; }
+
+static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const spgemm_csc *B,
+                                     spgemm_dtype dt, const spgemm_options *opt, void *stream,
+                                     spgemm_plan *plan_inout, int32_t *const *C_colptr,
+                                     int64_t *nnzC_host, bool batched) {
+    if (!plan_inout || !A || !B || !C_colptr || !nnzC_host) return SPGEMM_ERR_NULL;
+    if (dt != SPGEMM_F32 && dt != SPGEMM_F64) return SPGEMM_ERR_DTYPE;
+    if (count < 0) return SPGEMM_ERR_INVALID;
+    Tune tune;
+    uint32_t flags;
+    spgemm_status st = resolve_options(opt, tune, flags);
+    if (st) return st;
+    long long ncols = 0;
+    std::vector<Prob> probs(count);
+    std::vector<int4> tiles;
+    for (int i = 0; i < count; ++i) {
+        if ((st = check_desc(&A[i], false)) || (st = check_desc(&B[i], false))) return st;
+        if (!C_colptr[i]) return SPGEMM_ERR_NULL;
+        if (A[i].ncols != B[i].nrows) return SPGEMM_ERR_SHAPE;
+        if (flags & SPGEMM_VALIDATE) {
+            if ((st = validate_host(&A[i])) || (st = validate_host(&B[i]))) return st;
+        }
+        Prob &q = probs[i];
+        q = Prob{};
+        q.m = A[i].nrows; q.k = A[i].ncols; q.n = B[i].ncols;
+        q.col0 = (int32_t)ncols;
+        q.nnza = A[i].nnz; q.nnzb = B[i].nnz;
+        q.acp = A[i].colptr; q.ari = A[i].rowidx; q.av = A[i].val;
+        q.bcp = B[i].colptr; q.bri = B[i].rowidx; q.bv = B[i].val;
+        q.ccp = C_colptr[i];
+        for (int j0 = 0; j0 < q.n; j0 += kTile)
+            tiles.push_back(make_int4(i, j0, std::min(q.n, j0 + kTile), 0));
+        ncols += q.n;
+        if (ncols > 0x7fffffffll) return SPGEMM_ERR_INDEX_OVERFLOW;
+    }
+    spgemm_plan p = get_or_new_plan(plan_inout);
+    if (!p) return SPGEMM_ERR_NO_MEMORY;
+    const bool fresh = (*plan_inout == nullptr);
+    p->dt = dt;
+    p->batched = batched;
+    p->nprob = count;
+    p->tune = tune;
+    p->flags = flags;
+    p->probs = std::move(probs);
+    p->ncols = (int)ncols;
+    p->ntiles = (int)tiles.size();
+    p->item_cap = std::max(p->item_cap, 2 * p->ncols + 4096);
+    p->symbolic_ok = false;
+    p->bt_ready = false;
+    (void)hipGetDevice(&p->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (count == 0) {
+        *plan_inout = p;
+        p->symbolic_ok = true;
+        p->hdr_host = Hdr{};
+        return SPGEMM_OK;
+    }
+    st = run_symbolic(p, s, tiles);
+    p->last_stream = s;
+    if (st) {
+        if (fresh) spgemm_plan_destroy(p);
+        else p->symbolic_ok = false;
+        return st;
+    }
+    for (int i = 0; i < count; ++i) nnzC_host[i] = p->totals_host[i];
+    *plan_inout = p;
+    return SPGEMM_OK;
+}
+
+spgemm_status spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, spgemm_dtype dt,
+                              const spgemm_options *opt, void *stream, spgemm_plan *plan_inout,
+                              int32_t *C_colptr, int64_t *nnzC_host) {
+    if (!C_colptr) return SPGEMM_ERR_NULL;
+    int32_t *cps[1] = {C_colptr};
+    return symbolic_common(1, A, B, dt, opt, stream, plan_inout, cps, nnzC_host, false);
+}
+
+spgemm_status spgemm_numeric(spgemm_plan p, const void *A_val, const void *B_val,
+                             int32_t *C_rowidx, void *C_val, void *stream) {
+    if (!p) return SPGEMM_ERR_PLAN;
+    if (p->batched || p->nprob != 1 || !p->symbolic_ok) return SPGEMM_ERR_PLAN;
+    Prob &q = p->probs[0];
+    const long long nnzc = p->totals_host[0];
+    if ((q.nnza > 0 && !A_val) || (q.nnzb > 0 && !B_val)) return SPGEMM_ERR_NULL;
+    if (nnzc > 0 && (!C_rowidx || !C_val)) return SPGEMM_ERR_NULL;
+    q.av = A_val;
+    q.bv = B_val;
+    q.cri = C_rowidx;
+    q.cv = C_val;
+    if (nnzc == 0) return SPGEMM_OK;
+    return run_numeric(p, (hipStream_t)stream);
+}
+
+spgemm_status spgemm_batched(int32_t count, const spgemm_csc *A_host, const spgemm_csc *B_host,
+                             spgemm_dtype dt, const spgemm_options *opt, void *stream,
+                             spgemm_plan *plan_inout, int32_t *const *C_colptr_host,
+                             int64_t *nnzC_host, int32_t *const *C_rowidx_host,
+                             void *const *C_val_host) {
+    if (!plan_inout) return SPGEMM_ERR_NULL;
+    if (!C_rowidx_host) {
+        if (count == 1) {
+            // one problem still runs through the batched (table) path
+        }
+        return symbolic_common(count, A_host, B_host, dt, opt, stream, plan_inout, C_colptr_host,
+                               nnzC_host, true);
+    }
+    spgemm_plan p = *plan_inout;
+    if (!p || !p->batched || !p->symbolic_ok || p->nprob != count || p->dt != dt)
+        return SPGEMM_ERR_PLAN;
+    if (!A_host || !B_host || !C_val_host) return SPGEMM_ERR_NULL;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < count; ++i) {
+        Prob &q = p->probs[i];
+        if (A_host[i].nnz != q.nnza || B_host[i].nnz != q.nnzb) return SPGEMM_ERR_PLAN;
+        if ((q.nnza > 0 && !A_host[i].val) || (q.nnzb > 0 && !B_host[i].val)) return SPGEMM_ERR_NULL;
+        if (p->totals_host[i] > 0 && (!C_rowidx_host[i] || !C_val_host[i])) return SPGEMM_ERR_NULL;
+        q.av = A_host[i].val;
+        q.bv = B_host[i].val;
+        q.cri = C_rowidx_host[i];
+        q.cv = C_val_host[i];
+    }
+    if (count == 0) return SPGEMM_OK;
+    if (count > 1) {
+        bool same = p->table_dev_copy.size() == p->probs.size() &&
+                    std::memcmp(p->table_dev_copy.data(), p->probs.data(),
+                                sizeof(Prob) * p->probs.size()) == 0;
+        if (!same) {
+            SPG_TRY(hipMemcpyAsync(p->table, p->probs.data(), sizeof(Prob) * p->nprob,
+                                   hipMemcpyHostToDevice, s));
+            // the pageable source may be reused by the caller: wait for the copy
+            SPG_TRY(hipStreamSynchronize(s));
+            p->table_dev_copy = p->probs;
+        }
+    }
+    return run_numeric(p, s);
+}
+
+spgemm_status spgemm_backward(spgemm_plan p, const void *A_val, const void *B_val,
+                              const int32_t *C_rowidx, const void *G_val, void *dA_val,
+                              void *dB_val, void *stream) {
+    if (!p) return SPGEMM_ERR_PLAN;
+    if (p->nprob != 1 || !p->symbolic_ok) return SPGEMM_ERR_PLAN;
+    const Prob &q0 = p->probs[0];
+    if (!dA_val && !dB_val) return SPGEMM_OK;
+    if ((q0.nnza > 0 && !A_val && dB_val) || (q0.nnzb > 0 && !B_val && dA_val)) return SPGEMM_ERR_NULL;
+    if (p->totals_host[0] > 0 && (!C_rowidx || !G_val)) return SPGEMM_ERR_NULL;
+    hipStream_t s = (hipStream_t)stream;
+    Prob q = q0;
+    q.av = A_val;
+    q.bv = B_val;
+    const bool f64 = p->dt == SPGEMM_F64;
+    // row view of B (rowptr, fill, colj, pos), scan scratch and an error word
+    const size_t k = (size_t)q.k, nb = (size_t)std::max(q.nnzb, 1);
+    const int nbs = ceil_div((int)k + 1, kScanBlock) + 2;
+    const size_t o_fill = align_up(4 * (k + 1), 256);
+    const size_t o_colj = o_fill + align_up(4 * std::max<size_t>(k, 1), 256);
+    const size_t o_pos = o_colj + align_up(4 * nb, 256);
+    const size_t o_scr = o_pos + align_up(4 * nb, 256);
+    const size_t o_err = o_scr + align_up(8 * (size_t)nbs, 256);
+    const size_t need = o_err + 256;
+    if (need > p->bt_bytes) {
+        if (p->bt) {
+            (void)hipStreamSynchronize(p->last_stream);
+            (void)hipFree(p->bt);
+        }
+        p->bt = nullptr;
+        p->bt_bytes = 0;
+        p->bt_ready = false;
+        if (hipMalloc(&p->bt, need) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
+        p->bt_bytes = need;
+    }
+    char *b = (char *)p->bt;
+    int32_t *rowptr = (int32_t *)b;
+    int32_t *fill = (int32_t *)(b + o_fill);
+    int32_t *colj = (int32_t *)(b + o_colj);
+    int32_t *pos = (int32_t *)(b + o_pos);
+    long long *scr = (long long *)(b + o_scr);
+    p->bt_err = (int *)(b + o_err);
+    SPG_TRY(hipMemsetAsync(p->bt_err, 0, sizeof(int), s));
+    if (dA_val && !p->bt_ready) {
+        ProfScope ps("b_rowview", s);
+        SPG_TRY(launch_btranspose(q, rowptr, fill, colj, pos, scr, nbs, s));
+        p->bt_ready = true;
+    }
+    int *err = p->bt_err;
+    {
+        ProfScope ps("gradients", s);
+        SPG_TRY(launch_backward(q, f64, A_val, B_val, C_rowidx, G_val, dA_val, dB_val, rowptr,
+                                colj, pos, err, s));
+    }
+    p->last_stream = s;
+    return SPGEMM_OK;
+}
+
+spgemm_status spgemm_plan_get_stats(spgemm_plan p, spgemm_plan_stats *out) {
+    if (!p) return SPGEMM_ERR_PLAN;
+    if (!out) return SPGEMM_ERR_NULL;
+    if (!p->symbolic_ok) return SPGEMM_ERR_PLAN;
+    const Hdr &h = p->hdr_host;
+    spgemm_plan_stats s{};
+    s.total_products = (int64_t)h.total_op;
+    for (long long t : p->totals_host) s.nnz_c += t;
+    s.ncols = p->ncols;
+    s.cols_empty = h.bin_count[BIN_EMPTY];
+    for (int i = 0; i < kEscBins; ++i) s.cols_esc += h.bin_count[BIN_ESC0 + i];
+    s.cols_dense = h.bin_count[BIN_DENSE];
+    s.cols_hash = h.bin_count[BIN_HASH];
+    s.hash_items = h.item_count;
+    s.esc_groups = esc_groups(h);
+    s.nprob = p->nprob;
+    *out = s;
+    return SPGEMM_OK;
+}
+
+spgemm_status spgemm_profile_enable(int32_t on) {
+    g_prof.on = on != 0;
+    if (g_prof.on) g_prof.used = 0;
+    return SPGEMM_OK;
+}
+
+spgemm_status spgemm_profile_read(spgemm_kernel_time *out, int32_t max, int32_t *n_out) {
+    if (!out || !n_out) return SPGEMM_ERR_NULL;
+    std::vector<spgemm_kernel_time> acc;
+    for (size_t i = 0; i < g_prof.used; ++i) {
+        const ProfRec &r = g_prof.recs[i];
+        if (hipEventSynchronize(r.b) != hipSuccess) return SPGEMM_ERR_HIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return SPGEMM_ERR_HIP;
+        size_t k = 0;
+        for (; k < acc.size(); ++k)
+            if (std::strncmp(acc[k].name, r.name, sizeof(acc[k].name)) == 0) break;
+        if (k == acc.size()) {
+            spgemm_kernel_time t{};
+            std::strncpy(t.name, r.name, sizeof(t.name) - 1);
+            acc.push_back(t);
+        }
+        acc[k].launches += 1;
+        acc[k].total_ms += ms;
+    }
+    const int n = (int)std::min<size_t>(acc.size(), (size_t)std::max(max, 0));
+    for (int i = 0; i < n; ++i) out[i] = acc[i];
+    *n_out = n;
+    return SPGEMM_OK;
+}
+
+void spgemm_plan_destroy(spgemm_plan p) {
+    if (!p) return;
+    if (p->last_stream || p->ws) (void)hipStreamSynchronize(p->last_stream);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->bt) (void)hipFree(p->bt);
+    if (p->pinned) (void)hipHostFree(p->pinned);
+    delete p;
+}
+
+}  // extern "C"

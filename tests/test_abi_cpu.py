@@ -1,0 +1,92 @@
+"""CPU checks of the C ABI: the library loads and exports every declared symbol.
+
+No compute call is made here (there is no GPU in this environment); calls that
+only touch host state (status strings, version, argument checks that fail
+before any device work) are exercised.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2303_02471_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spgemm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(spgemm_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2303_02471_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ("spgemm_symbolic", "spgemm_numeric", "spgemm_batched", "spgemm_backward"):
+        assert must in names
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_every_declared_symbol_exported(L):
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_version(L):
+    assert L.spgemm_version() == 10000
+    for code in range(10):
+        s = L.spgemm_status_string(code)
+        assert isinstance(s, bytes) and len(s) > 0
+    assert L.spgemm_status_string(0) == b"ok"
+    assert L.spgemm_status_string(99) == b"unknown status"
+
+
+def test_null_and_invalid_arguments_rejected_on_host(L):
+    """Argument checks that return before any device work."""
+    plan = C.c_void_p()
+    nnz = C.c_int64()
+    a = _lib.Csc(4, 4, 0, None, None, None)
+    # NULL plan pointer / NULL descriptors
+    assert L.spgemm_symbolic(None, None, 1, None, None, None, None, None) == 1
+    assert L.spgemm_symbolic(C.byref(a), C.byref(a), 1, None, None, C.byref(plan), None,
+                             C.byref(nnz)) == 1
+    # numeric / backward / stats on a NULL plan
+    assert L.spgemm_numeric(None, None, None, None, None, None) == 8
+    assert L.spgemm_backward(None, None, None, None, None, None, None, None) == 8
+    st = _lib.PlanStats()
+    assert L.spgemm_plan_get_stats(None, C.byref(st)) == 8
+    L.spgemm_plan_destroy(None)  # no-op
+
+
+def test_options_validated_on_host(L):
+    """Out-of-range tuning values are refused before the device is touched."""
+    fake = C.c_int32(0)
+    a = _lib.Csc(4, 4, 0, C.addressof(fake), None, None)
+    plan = C.c_void_p()
+    nnz = C.c_int64()
+    for bad in (_lib.Options(2, 0, 0, 0, 0), _lib.Options(512, 0, 0, 0, 0),
+                _lib.Options(0, 0, 10, 0, 0), _lib.Options(0, 0, 0, 100000, 0),
+                _lib.Options(0, -1, 0, 0, 0)):
+        st = L.spgemm_symbolic(C.byref(a), C.byref(a), 1, C.byref(bad), None, C.byref(plan),
+                               C.addressof(fake), C.byref(nnz))
+        assert st == 9, (bad.t_esc, bad.t_dense, bad.dense_rows, bad.hash_cap)
+    # unknown dtype
+    st = L.spgemm_symbolic(C.byref(a), C.byref(a), 7, None, None, C.byref(plan),
+                           C.addressof(fake), C.byref(nnz))
+    assert st == 4
+    # shape mismatch
+    b = _lib.Csc(5, 4, 0, C.addressof(fake), None, None)
+    st = L.spgemm_symbolic(C.byref(a), C.byref(b), 1, None, None, C.byref(plan),
+                           C.addressof(fake), C.byref(nnz))
+    assert st == 2

@@ -1,0 +1,176 @@
+"""Parity of the HIP path with the CPU oracle (element by element).
+
+Structure (column pointers, ascending rows) must be identical; FP64 values
+must be bit-identical (and so inside the stated 1e-12 relative tolerance);
+FP32 values must equal the oracle's single-precision twin and stay inside the
+float32 rounding bound of the double oracle.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_02471_amd import inputs as gen
+from helpers import (HAVE_GPU, assert_same_structure, assert_values_exact, check_f32, check_f64,
+                     gpu_product)
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not HAVE_GPU, reason="needs an MI355X GPU")]
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _fig1():
+    here = os.path.join(os.path.dirname(__file__), "golden", "fig1_gustavson_4x4.txt")
+    mats, cur = {}, None
+    for line in open(here):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line in ("A", "B", "C"):
+            cur = line
+            mats[cur] = []
+        else:
+            mats[cur].append([float(x) for x in line.split()])
+    return {k: np.array(v) for k, v in mats.items()}
+
+
+def test_figure1_on_gpu():
+    _say("figure 1 4x4")
+    m = _fig1()
+    A, B = gen.from_dense(m["A"]), gen.from_dense(m["B"])
+    cp, ri, v = gpu_product(A, B)
+    d = np.zeros((4, 4))
+    d[ri, np.repeat(np.arange(4), np.diff(cp))] = v
+    assert np.array_equal(d, m["C"])
+    assert cp.tolist() == [0, 3, 6, 9, 13]
+
+
+def test_tiny_random_many():
+    rng = np.random.default_rng(123)
+    for trial in range(150):
+        m, k, n = (int(x) for x in rng.integers(1, 40, size=3))
+        dist = "int" if trial % 2 else "uniform"
+        A = gen.random_tiny(rng, m, k, float(rng.choice([0.05, 0.2, 0.5, 1.0])), dist)
+        B = gen.random_tiny(rng, k, n, float(rng.choice([0.05, 0.2, 0.5, 1.0])), dist)
+        _say(f"tiny trial {trial} m={m} k={k} n={n} nnzA={A.nnz} nnzB={B.nnz}")
+        check_f64(A, B, what=f"tiny {trial}")
+
+
+def test_config1_diag_plus_random():
+    _say("diag+4 random n=1000")
+    A = gen.diag_plus_random(1000, 4, seed=0)
+    check_f64(A, A, what="config 1")
+
+
+def test_laplacian_squared():
+    _say("laplacian 64x64 squared")
+    L = gen.laplacian_2d(64)
+    cp, ri, v = check_f64(L, L, what="laplacian")
+    assert int(cp[-1]) == 51972
+
+
+def test_dense_bin_n4096_z40():
+    _say("n=4096 z=40 (dense accumulator)")
+    A = gen.uniform_z(4096, 40, seed=0)
+    check_f64(A, A, what="n4096 z40")
+
+
+def test_powerlaw_reduced():
+    _say("power law n=50000")
+    A, B = gen.powerlaw(50_000, seed=1)
+    check_f64(A, B, what="powerlaw 50k")
+
+
+@pytest.mark.parametrize("opts", [
+    dict(t_esc=4), dict(t_esc=16, hash_cap=128), dict(t_esc=256, hash_cap=128),
+    dict(t_dense=1), dict(t_dense=100000), dict(dense_rows=64), dict(t_esc=4, t_dense=1)])
+def test_forced_bins_identical(opts):
+    """Any split of the work between accumulators gives the same bits (the
+    t = 0 / t = infinity limits of Section 3.3 and everything between)."""
+    from paper_2303_02471_amd import api
+    _say(f"forced bins {opts}")
+    rng = np.random.default_rng(5)
+    cases = [gen.uniform_z(3000, 12, seed=3), gen.powerlaw(20_000, seed=2)[0],
+             gen.random_tiny(rng, 300, 300, 0.2, "uniform")]
+    for A in cases:
+        ocp, ori, ov = oracle.spgemm(A, A)
+        cp, ri, v = gpu_product(A, A, api.options(**opts))
+        assert_same_structure(cp, ri, ocp, ori, str(opts))
+        assert_values_exact(v, ov, str(opts))
+
+
+def test_input_order_free():
+    _say("shuffled storage order")
+    A = gen.uniform_z(2000, 9, seed=4)
+    B = gen.uniform_z(2000, 7, seed=5)
+    ocp, ori, ov = oracle.spgemm(A, B)
+    As, Bs = gen.shuffle_within_columns(A, 1), gen.shuffle_within_columns(B, 2)
+    ocp2, ori2, ov2 = oracle.spgemm(As, Bs)
+    cp, ri, v = gpu_product(As, Bs)
+    assert_same_structure(cp, ri, ocp, ori, "shuffled")
+    assert_values_exact(v, ov2, "shuffled")
+
+
+def test_rectangular_and_empty():
+    rng = np.random.default_rng(9)
+    for (m, k, n) in [(1, 1, 1), (7, 300, 5), (500, 3, 800), (1000, 1000, 1), (3, 5, 0),
+                      (0, 5, 3), (4, 0, 6)]:
+        _say(f"rect m={m} k={k} n={n}")
+        A = gen.random_tiny(rng, m, k, 0.3, "uniform") if m and k else gen.CSC(
+            m, k, np.zeros(k + 1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+        B = gen.random_tiny(rng, k, n, 0.3, "uniform") if k and n else gen.CSC(
+            k, n, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+        check_f64(A, B, what=f"rect {m}x{k}x{n}")
+
+
+def test_empty_columns_and_empty_a_columns():
+    _say("empty columns in A and B")
+    rng = np.random.default_rng(3)
+    A = gen.random_tiny(rng, 200, 150, 0.02, "uniform")  # many empty A columns
+    B = gen.random_tiny(rng, 150, 180, 0.05, "uniform")
+    check_f64(A, B, what="empties")
+
+
+def test_deterministic_reruns():
+    _say("determinism")
+    A, B = gen.powerlaw(30_000, seed=7)
+    r1 = gpu_product(A, B)
+    r2 = gpu_product(A, B)
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
+
+
+def test_f32_config_small():
+    _say("f32 n=20000 z=8")
+    A = gen.uniform_z(20_000, 8, seed=11, dist="normal", dtype=np.float32)
+    B = gen.uniform_z(20_000, 8, seed=12, dist="normal", dtype=np.float32)
+    rel = check_f32(A, B, what="f32")
+    print("max rel err f32 vs f64 oracle", rel)
+
+
+def test_f32_dense_and_hash():
+    _say("f32 dense + hash")
+    A = gen.uniform_z(4096, 40, seed=1, dtype=np.float32)
+    check_f32(A, A, what="f32 dense")
+    P, Q = gen.powerlaw(20_000, seed=3, dtype=np.float32)
+    check_f32(P, Q, what="f32 powerlaw")
+
+
+def test_stats_reported():
+    from paper_2303_02471_amd import api
+    _say("plan stats")
+    A, B = gen.powerlaw(20_000, seed=5)
+    _, plan, _ = gpu_product(A, B, return_plan=True)
+    st = plan.stats()
+    op = oracle.opcount(A, B)
+    assert st["total_products"] == int(op.sum())
+    assert st["ncols"] == 20_000
+    assert st["cols_empty"] == int((op == 0).sum())
+    assert st["cols_empty"] + st["cols_esc"] + st["cols_dense"] + st["cols_hash"] == 20_000
+    assert st["nnz_c"] == int(oracle.symbolic(A, B)[-1])
