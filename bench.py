@@ -1,0 +1,292 @@
+#!/usr/bin/env python
+"""Benchmark of the column-wise sparse product C = A x B on one MI355X.
+
+A step is one pass of the whole hot path over one synthetic input: the
+symbolic phase (product counts, accumulator binning, distinct-row counts,
+column-pointer scan, one device-to-host copy of nnz(C)) and the numeric
+phase (rows and values of C) -- i.e. C = A x B from scratch, excluding
+allocation (the paper's protocol, Section 5.1).
+
+Default workload: A, B square n = 1,000,000 with power-law column degrees
+(truncated Zipf, exponent 2.0, degrees 1..2000, uniform rows, N(0,1) values,
+seed 0), FP64, C = A x B. Inputs are resident in HBM before timing starts.
+
+The single JSON line carries the metric (GFLOP/s = 2 x products / s), the
+roofline of the dominant kernel (event-timed inside the timed region), the
+oracle's CPU rate on the same workload, and two side measurements named by the
+metric: forward+backward against forward on the n = 100,000 / 8-per-column
+FP32 workload, and one batched launch set against a per-matrix loop.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "SpGEMM GFLOP/s + HBM GB/s vs peak; batched & fwd+bwd speedup vs plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1_000_000, help="columns of the power-law workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-runs", type=int, default=4)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=64)
+    return ap.parse_args()
+
+
+def csc_bytes(n, nnz, vb):
+    return 4 * (n + 1) + (4 + vb) * nnz
+
+
+def per_column_work(A, B, m_dense_limit=4096, t_esc=256, t_dense=512):
+    """Host accounting of the per-column work and of the accumulator each
+    column goes to (the library's default rule), for algorithmic byte counts."""
+    import numpy as np
+    za = np.diff(A.colptr.astype(np.int64))
+    nb = np.diff(B.colptr.astype(np.int64))
+    colB = np.repeat(np.arange(B.ncols), nb)
+    op = np.bincount(colB, weights=za[B.rowidx], minlength=B.ncols).astype(np.int64)
+    w = np.maximum(op, nb)
+    esc = (op > 0) & (w <= t_esc)
+    dense = (op > 0) & ~esc & (A.nrows <= m_dense_limit) & (op >= t_dense)
+    hsh = (op > 0) & ~esc & ~dense
+    return op, nb, {"esc": esc, "dense": dense, "hash": hsh}
+
+
+def kernel_bytes(op, nb, nnzc, sel, vb):
+    """Algorithmic bytes of the accumulator kernels over the columns `sel`.
+    numeric: B colptr pair 8, B entry (4+vb) + A colptr pair 8 per stored B
+    entry, (4+vb) per product (A row and value), C colptr pair 8, (4+vb) per
+    output entry. symbolic: 8 + 12 per B entry + 4 per product + 4."""
+    s_nb, s_op, s_nnz, ncol = int(nb[sel].sum()), int(op[sel].sum()), int(nnzc[sel].sum()), int(sel.sum())
+    num = 8 * ncol + (4 + vb + 8) * s_nb + (4 + vb) * s_op + 8 * ncol + (4 + vb) * s_nnz
+    sym = 8 * ncol + 12 * s_nb + 4 * s_op + 4 * ncol
+    return num, sym
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                          "described in DESIGN.md but not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2303_02471_amd import api
+    from paper_2303_02471_amd import inputs as gen
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # ------------------------------------------------------------ workload
+    t0 = time.time()
+    A, B = gen.powerlaw(args.n, seed=0)
+    log(f"generated n={args.n} nnzA={A.nnz} nnzB={B.nnz} in {time.time() - t0:.1f}s")
+    At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
+    vb = 8
+    plan, colptr, nnz = api.symbolic(At, Bt, torch.float64)
+    rowidx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    stats = plan.stats()
+    total_op = stats["total_products"]
+    log(f"plan: {stats}")
+
+    def step():
+        api.symbolic(At, Bt, torch.float64, plan=plan, out_colptr=colptr)
+        api.numeric(plan, At.val, Bt.val, rowidx, val)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    api.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.profile_enable(False)
+    prof = api.profile_read()
+    ms = (t1 - t0) * 1e3 / args.steps
+    gflops = 2.0 * total_op / (ms * 1e-3) / 1e9
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step, {gflops:.1f} GFLOP/s")
+
+    # ------------------------------------------------------------ roofline of the dominant kernel
+    nnzc = np.diff(colptr.cpu().numpy().astype(np.int64))
+    op, nb, bins = per_column_work(A, B)
+    kbytes = {}
+    for name in ("esc", "dense", "hash"):
+        num, sym = kernel_bytes(op, nb, nnzc, bins[name], vb)
+        kbytes[f"{name}_numeric"] = num
+        kbytes[f"{name}_symbolic"] = sym
+    kbytes["classify"] = 4 * (B.ncols + 1) + 12 * B.nnz + 12 * B.ncols
+    kbytes["place"] = 8 * B.ncols
+    kbytes["scan"] = 4 * B.ncols + 4 * (B.ncols + 1) + 8 * B.ncols
+    kernels = {}
+    for name, (launches, tot) in prof.items():
+        avg = tot / launches
+        kb = kbytes.get(name)
+        kernels[name] = {"avg_ms": round(avg, 4), "launches": launches,
+                         "GBps": None if kb is None or avg <= 0 else round(kb / (avg * 1e-3) / 1e9, 1)}
+    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    dom_avg_s = prof[dom][1] / prof[dom][0] * 1e-3
+    achieved = kbytes[dom] / dom_avg_s / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        if tj.get("kernel_key") == dom and tj.get("workload") == f"powerlaw_n{args.n}":
+            traffic = tj.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes": int(kbytes[dom])}
+    compulsory = csc_bytes(A.ncols, A.nnz, vb) + csc_bytes(B.ncols, B.nnz, vb) + \
+        csc_bytes(B.ncols, nnz, vb)
+    log(f"dominant kernel {dom}: {achieved:.0f} GB/s")
+
+    # ------------------------------------------------------------ CPU baseline (the oracle)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        times = []
+        for r in range(args.cpu_runs):
+            c0 = time.perf_counter()
+            oracle.spgemm(A, B)
+            times.append(time.perf_counter() - c0)
+            log(f"oracle run {r}: {times[-1]:.2f}s")
+        tmed = statistics.median(times)
+        cpu = {"value": round(2.0 * total_op / tmed / 1e9, 5), "unit": "GFLOP/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"full workload (symbolic + numeric), median of {args.cpu_runs} "
+                         f"single-thread runs, {tmed:.2f} s each"}
+
+    # ------------------------------------------------------------ side measurements
+    extras = {}
+    if not args.no_extras:
+        extras["fwd_bwd"] = fwd_bwd(api, gen, np, torch)
+        extras["batched"] = batched(api, gen, np, torch, args.batch_count)
+
+    out = {
+        "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"C=A*B, A and B n={args.n} square CSC, power-law column degrees "
+                               "(Zipf 2.0, max 2000), uniform rows, N(0,1), FP64, seed 0",
+                   "n": args.n, "nnz_a": A.nnz, "nnz_b": B.nnz, "products": int(total_op),
+                   "nnz_c": int(nnz), "parallelism": "single GPU"},
+        "hbm_compulsory_GBps": round(compulsory / (ms * 1e-3) / 1e9, 1),
+        "hbm_compulsory_frac": round(compulsory / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    out.update(extras)
+    print(json.dumps(out), flush=True)
+
+
+def fwd_bwd(api, gen, np, torch, n=100_000, z=8, reps=20):
+    """t(numeric forward + backward) / t(numeric forward) on a fixed pattern."""
+    A = gen.uniform_z(n, z, seed=1, dist="normal", dtype=np.float32)
+    B = gen.uniform_z(n, z, seed=2, dist="normal", dtype=np.float32)
+    At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
+    Cm, plan = api.matmul(At, Bt, return_plan=True)
+    G = torch.from_numpy(gen.gradient_values(Cm.nnz, seed=3, dtype=np.float32)).cuda()
+    dA, dB = torch.empty_like(At.val), torch.empty_like(Bt.val)
+
+    def fwd():
+        api.numeric(plan, At.val, Bt.val, Cm.rowidx, Cm.val)
+
+    def fb():
+        fwd()
+        api.backward(plan, At.val, Bt.val, Cm.rowidx, G)
+
+    def timeit(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    tf, tfb = timeit(fwd), timeit(fb)
+    log(f"fwd {tf:.3f} ms, fwd+bwd {tfb:.3f} ms")
+    return {"workload": f"n={n}, {z} per column, FP32", "fwd_ms": round(tf, 4),
+            "fwd_bwd_ms": round(tfb, 4), "fwd_bwd_over_fwd": round(tfb / tf, 3)}
+
+
+def batched(api, gen, np, torch, count, reps=5):
+    """One batched launch set against a loop of per-matrix calls, same kernels."""
+    probs = gen.batched_problems(count, seed=0)
+    pairs = [(api.CscTensor.from_host(a), api.CscTensor.from_host(b)) for a, b in probs]
+    outs, bplan = api.batched_matmul(pairs, return_plan=True)
+    nnzs = bplan.nnzs
+    rowidxs = [o.rowidx for o in outs]
+    vals = [o.val for o in outs]
+    plans = []
+    for (a, b), o in zip(pairs, outs):
+        _, p = api.matmul(a, b, return_plan=True)
+        plans.append(p)
+
+    def t_batched():
+        bplan2, cps, _ = api.batched_symbolic(pairs, torch.float64, plan=bplan)
+        api.batched_numeric(bplan, pairs, rowidxs, vals)
+
+    def t_loop():
+        for (a, b), p, ri, v in zip(pairs, plans, rowidxs, vals):
+            api.symbolic(a, b, torch.float64, plan=p, out_colptr=p.colptr)
+            api.numeric(p, a.val, b.val, ri, v)
+
+    def t_batched_num():
+        api.batched_numeric(bplan, pairs, rowidxs, vals)
+
+    def t_loop_num():
+        for (a, b), p, ri, v in zip(pairs, plans, rowidxs, vals):
+            api.numeric(p, a.val, b.val, ri, v)
+
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    tb, tl = timeit(t_batched), timeit(t_loop)
+    tbn, tln = timeit(t_batched_num), timeit(t_loop_num)
+    log(f"batched {tb:.2f} ms vs loop {tl:.2f} ms; numeric {tbn:.2f} vs {tln:.2f}")
+    return {"workload": f"{count} problems, n log-uniform [500, 20000], 2..40 per column, FP64",
+            "products": int(sum(p.stats()["total_products"] for p in plans)),
+            "nnz_c": int(sum(nnzs)),
+            "batched_ms": round(tb, 3), "per_matrix_loop_ms": round(tl, 3),
+            "speedup": round(tl / tb, 3),
+            "numeric_batched_ms": round(tbn, 3), "numeric_loop_ms": round(tln, 3),
+            "numeric_speedup": round(tln / tbn, 3)}
+
+
+if __name__ == "__main__":
+    main()

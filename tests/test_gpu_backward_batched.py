@@ -1,0 +1,265 @@
+"""GPU parity of the gradient kernels, the batched path, plan reuse, HIP-graph
+replay of the batched numeric phase, and the device-side input checks."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_02471_amd import inputs as gen
+from helpers import (HAVE_GPU, assert_same_structure, assert_values_exact, f32_bound,
+                     gpu_product)
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not HAVE_GPU, reason="needs an MI355X GPU")]
+
+if HAVE_GPU:
+    import torch
+    from paper_2303_02471_amd import api
+    from paper_2303_02471_amd._lib import SpgemmError
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _grads_gpu(A, B, G, dtype):
+    At = api.CscTensor.from_host(A, dtype=dtype)
+    Bt = api.CscTensor.from_host(B, dtype=dtype)
+    Cm, plan = api.matmul(At, Bt, return_plan=True)
+    Gt = torch.from_numpy(np.ascontiguousarray(G.astype(dtype))).cuda()
+    dA, dB = api.backward(plan, At.val, Bt.val, Cm.rowidx, Gt)
+    torch.cuda.synchronize()
+    return Cm, dA.cpu().numpy(), dB.cpu().numpy()
+
+
+def test_backward_f64_matches_oracle():
+    _say("backward f64 n=2000 z=8")
+    A = gen.uniform_z(2000, 8, seed=1, dist="normal")
+    B = gen.uniform_z(2000, 8, seed=2, dist="normal")
+    cp, ri, _ = oracle.spgemm(A, B)
+    G = gen.gradient_values(int(cp[-1]), seed=3, dtype=np.float64)
+    odA, odB = oracle.backward(A, B, cp, ri, G)
+    _, dA, dB = _grads_gpu(A, B, G, np.float64)
+    assert_values_exact(dA, odA, "dA")
+    assert_values_exact(dB, odB, "dB")
+
+
+def test_backward_powerlaw_f64():
+    _say("backward f64 power law n=20000")
+    A, B = gen.powerlaw(20_000, seed=4)
+    cp, ri, _ = oracle.spgemm(A, B)
+    G = gen.gradient_values(int(cp[-1]), seed=5, dtype=np.float64)
+    odA, odB = oracle.backward(A, B, cp, ri, G)
+    _, dA, dB = _grads_gpu(A, B, G, np.float64)
+    assert_values_exact(dA, odA, "dA")
+    assert_values_exact(dB, odB, "dB")
+
+
+def test_backward_f32_config5():
+    """n = 100,000, 8 per column, FP32: equal to the oracle's float twin and
+    inside the float32 rounding bound of the double oracle."""
+    _say("backward f32 n=100000 z=8")
+    A = gen.uniform_z(100_000, 8, seed=1, dist="normal", dtype=np.float32)
+    B = gen.uniform_z(100_000, 8, seed=2, dist="normal", dtype=np.float32)
+    cp, ri, _ = oracle.spgemm(A, B, "f32")
+    G = gen.gradient_values(int(cp[-1]), seed=3, dtype=np.float32)
+    o32A, o32B = oracle.backward(A, B, cp, ri, G, "f32")
+    o64A, o64B = oracle.backward(A, B, cp, ri, G.astype(np.float64), "f64")
+    _, dA, dB = _grads_gpu(A, B, G, np.float32)
+    assert_values_exact(dA, o32A, "dA f32")
+    assert_values_exact(dB, o32B, "dB f32")
+    # |sum of t terms in float - exact| <= (t + 1) u sum|terms|, u = 2^-24
+    abs_dA, _ = oracle.backward(gen.CSC(A.nrows, A.ncols, A.colptr, A.rowidx, np.abs(A.val)),
+                              gen.CSC(B.nrows, B.ncols, B.colptr, B.rowidx, np.abs(B.val)),
+                              cp, ri, np.abs(G).astype(np.float64), "f64")
+    za = np.diff(A.colptr)
+    nbrow = np.bincount(B.rowidx, minlength=B.nrows)
+    termsA = nbrow[np.repeat(np.arange(A.ncols), za)]
+    assert np.all(np.abs(dA.astype(np.float64) - o64A) <= 1.01 * (termsA + 1) * 2.0 ** -24 * abs_dA
+                  + 1e-38)
+
+
+def test_autograd_function_and_finite_differences():
+    _say("autograd + central differences n=200")
+    n, z = 200, 8
+    A = gen.uniform_z(n, z, seed=1, dist="normal")
+    B = gen.uniform_z(n, z, seed=2, dist="normal")
+    At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
+    a = At.val.clone().requires_grad_(True)
+    b = Bt.val.clone().requires_grad_(True)
+    cval, rowidx, colptr = api.SpGEMMFunction.apply(a, b, At, Bt)
+    G = torch.from_numpy(gen.gradient_values(cval.numel(), seed=3, dtype=np.float64)).cuda()
+    loss = (cval * G).sum()
+    loss.backward()
+    ga, gb = a.grad.cpu().numpy(), b.grad.cpu().numpy()
+    cp, ri, _ = oracle.spgemm(A, B)
+    odA, odB = oracle.backward(A, B, cp, ri, G.cpu().numpy())
+    assert_values_exact(ga, odA, "autograd dA")
+    assert_values_exact(gb, odB, "autograd dB")
+    # central differences through the GPU forward (bilinear: exact up to rounding)
+    h = 2.0 ** -10
+    _, plan = api.matmul(At, Bt, return_plan=True)
+    cbuf = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+    rbuf = torch.empty(plan.nnz, dtype=torch.int32, device="cuda")
+
+    def L(av, bv):
+        api.numeric(plan, av, bv, rbuf, cbuf)
+        return float((cbuf * G).sum())
+
+    rng = np.random.default_rng(0)
+    for q in rng.choice(A.nnz, 20, replace=False):
+        vp, vm = At.val.clone(), At.val.clone()
+        vp[q] += h
+        vm[q] -= h
+        fd = (L(vp, Bt.val) - L(vm, Bt.val)) / (2 * h)
+        assert abs(fd - ga[q]) <= 1e-9 * max(1.0, abs(ga[q]))
+    for q in rng.choice(B.nnz, 20, replace=False):
+        vp, vm = Bt.val.clone(), Bt.val.clone()
+        vp[q] += h
+        vm[q] -= h
+        fd = (L(At.val, vp) - L(At.val, vm)) / (2 * h)
+        assert abs(fd - gb[q]) <= 1e-9 * max(1.0, abs(gb[q]))
+
+
+def _batch(count, seed, nmax=3000):
+    rng = np.random.default_rng(seed)
+    probs = gen.batched_problems(count, seed=seed, nmin=50, nmax=nmax)
+    # add an empty problem and a rectangular one
+    probs.append((gen.CSC(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0)),
+                  gen.CSC(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))))
+    probs.append((gen.random_tiny(rng, 40, 70, 0.1, "uniform"),
+                  gen.random_tiny(rng, 70, 33, 0.1, "uniform")))
+    return probs
+
+
+def test_batched_matches_oracle_and_single_path():
+    _say("batched 40 problems")
+    probs = _batch(38, seed=3)
+    pairs = [(api.CscTensor.from_host(a), api.CscTensor.from_host(b)) for a, b in probs]
+    outs = api.batched_matmul(pairs)
+    torch.cuda.synchronize()
+    for i, ((a, b), o) in enumerate(zip(probs, outs)):
+        cp, ri, v = o.to_host()
+        ocp, ori, ov = oracle.spgemm(a, b)
+        assert_same_structure(cp, ri, ocp, ori, f"problem {i}")
+        assert_values_exact(v, ov, f"problem {i}")
+        if a.ncols and b.ncols:
+            scp, sri, sv = gpu_product(a, b)
+            assert np.array_equal(scp, cp) and np.array_equal(sri, ri) and np.array_equal(sv, v)
+
+
+def test_batched_f32():
+    _say("batched f32")
+    probs = [(a.astype(np.float32), b.astype(np.float32)) for a, b in _batch(12, seed=8)]
+    pairs = [(api.CscTensor.from_host(a), api.CscTensor.from_host(b)) for a, b in probs]
+    outs = api.batched_matmul(pairs)
+    for i, ((a, b), o) in enumerate(zip(probs, outs)):
+        cp, ri, v = o.to_host()
+        ocp, ori, ov = oracle.spgemm(a, b, "f32")
+        assert_same_structure(cp, ri, ocp, ori, f"problem {i}")
+        assert_values_exact(v, ov, f"f32 problem {i}")
+
+
+def test_plan_reuse_new_values():
+    _say("plan reuse with new values")
+    A = gen.uniform_z(5000, 10, seed=1)
+    B = gen.uniform_z(5000, 10, seed=2)
+    At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
+    Cm, plan = api.matmul(At, Bt, return_plan=True)
+    rng = np.random.default_rng(1)
+    for r in range(3):
+        av = rng.standard_normal(A.nnz)
+        bv = rng.standard_normal(B.nnz)
+        api.numeric(plan, torch.from_numpy(av).cuda(), torch.from_numpy(bv).cuda(), Cm.rowidx,
+                    Cm.val)
+        _, _, ov = oracle.spgemm(gen.CSC(A.nrows, A.ncols, A.colptr, A.rowidx, av),
+                                 gen.CSC(B.nrows, B.ncols, B.colptr, B.rowidx, bv))
+        assert_values_exact(Cm.val.cpu().numpy(), ov, f"reuse {r}")
+    # symbolic again into the same plan (workspace reused) gives the same structure
+    p2, cp2, nnz2 = api.symbolic(At, Bt, torch.float64, plan=plan, out_colptr=plan.colptr)
+    assert nnz2 == Cm.nnz
+
+
+def test_batched_numeric_graph_replay():
+    """Capture the batched numeric phase in a HIP graph; replay it several times
+    with eager work in between; every replay equals the eager result."""
+    _say("graph replay of batched numeric")
+    probs = _batch(10, seed=5, nmax=2000)
+    pairs = [(api.CscTensor.from_host(a), api.CscTensor.from_host(b)) for a, b in probs]
+    outs, plan = api.batched_matmul(pairs, return_plan=True)
+    torch.cuda.synchronize()
+    ref = [o.val.clone() for o in outs]
+    ris = [o.rowidx for o in outs]
+    vals = [torch.zeros_like(o.val) for o in outs]
+    api.batched_numeric(plan, pairs, ris, vals)  # uploads the pointer table once
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            api.batched_numeric(plan, pairs, ris, vals)
+    torch.cuda.current_stream().wait_stream(s)
+    for r in range(4):
+        for v in vals:
+            v.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, (v, rv) in enumerate(zip(vals, ref)):
+            assert torch.equal(v, rv), f"replay {r} problem {i}"
+        # eager work between replays
+        _ = gpu_product(*probs[0])
+
+
+def _bad_case(kind):
+    A = gen.uniform_z(300, 4, seed=1)
+    B = gen.uniform_z(300, 4, seed=2)
+    if kind == "b_row_out_of_range":
+        ri = B.rowidx.copy()
+        ri[17] = 300
+        B = gen.CSC(B.nrows, B.ncols, B.colptr, ri, B.val)
+    elif kind == "a_row_out_of_range":
+        ri = A.rowidx.copy()
+        ri[5] = -3
+        A = gen.CSC(A.nrows, A.ncols, A.colptr, ri, A.val)
+    elif kind == "b_colptr_decreasing":
+        cp = B.colptr.copy()
+        cp[10], cp[11] = cp[11], cp[10]
+        B = gen.CSC(B.nrows, B.ncols, cp, B.rowidx, B.val)
+    elif kind == "b_colptr_last":
+        cp = B.colptr.copy()
+        cp[-1] -= 1
+        B = gen.CSC(B.nrows, B.ncols, cp, B.rowidx, B.val)
+    return A, B
+
+
+@pytest.mark.parametrize("kind", ["b_row_out_of_range", "a_row_out_of_range",
+                                  "b_colptr_decreasing", "b_colptr_last"])
+def test_device_input_checks(kind):
+    """Malformed inputs are reported (SPGEMM_ERR_CSC) by the kernels' own
+    range checks, which run before any index is used as an address."""
+    _say(f"device check {kind}")
+    A, B = _bad_case(kind)
+    At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
+    with pytest.raises(SpgemmError) as ei:
+        api.symbolic(At, Bt, torch.float64)
+    assert ei.value.status == 3
+
+
+def test_validate_flag_detects_repeated_rows():
+    _say("validate flag")
+    A = gen.uniform_z(100, 3, seed=1)
+    ri = A.rowidx.copy()
+    ri[1] = ri[0]  # repeated row in column 0
+    Ad = gen.CSC(A.nrows, A.ncols, A.colptr, ri, A.val)
+    At = api.CscTensor.from_host(Ad)
+    with pytest.raises(SpgemmError) as ei:
+        api.symbolic(At, At, torch.float64, api.options(validate=True))
+    assert ei.value.status == 3
+    # without the flag the library still runs (memory-safe) and keeps rows ascending
+    cp, ri2, v = gpu_product(Ad, Ad)
+    for j in range(len(cp) - 1):
+        assert np.all(np.diff(ri2[cp[j]:cp[j + 1]]) > 0)
