@@ -47,14 +47,32 @@ def parse():
     ap.add_argument("--cpu-runs", type=int, default=4)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--t-esc", type=int, default=0, help="library option (0 = default)")
+    ap.add_argument("--hash-cap", type=int, default=0, help="library option (0 = default)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of exactly 1 GiB, three times: the
+    FETCH_SIZE / WRITE_SIZE counters of this kernel against its 1 GiB read and
+    1 GiB write give the scale factor of the HBM byte counters."""
+    import torch
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
 
 
 def csc_bytes(n, nnz, vb):
     return 4 * (n + 1) + (4 + vb) * nnz
 
 
-def per_column_work(A, B, m_dense_limit=4096, t_esc=256, t_dense=512):
+def per_column_work(A, B, m_dense_limit=4096, t_esc=256, t_dense=512, hash_cap=4096):
     """Host accounting of the per-column work and of the accumulator each
     column goes to (the library's default rule), for algorithmic byte counts."""
     import numpy as np
@@ -66,7 +84,14 @@ def per_column_work(A, B, m_dense_limit=4096, t_esc=256, t_dense=512):
     esc = (op > 0) & (w <= t_esc)
     dense = (op > 0) & ~esc & (A.nrows <= m_dense_limit) & (op >= t_dense)
     hsh = (op > 0) & ~esc & ~dense
-    return op, nb, {"esc": esc, "dense": dense, "hash": hsh}
+    # hash table class: windows W = ceil(op / cap); table = power of two
+    # >= 2 ceil(op / W), in [64, 8192]; classes <= 1024, <= 4096, larger
+    W = np.maximum(1, -(-op // hash_cap))
+    per = -(-op // W)
+    H = np.clip(2 ** np.ceil(np.log2(np.maximum(2 * per, 1))), 64, 8192)
+    return op, nb, {"esc": esc, "dense": dense,
+                    "hash_s": hsh & (H <= 1024), "hash_l": hsh & (H > 1024) & (H <= 4096),
+                    "hash_xl": hsh & (H > 4096)}
 
 
 def kernel_bytes(op, nb, nnzc, sel, vb):
@@ -82,6 +107,9 @@ def kernel_bytes(op, nb, nnzc, sel, vb):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
                           "described in DESIGN.md but not implemented", "n_gpus": args.gpus}))
@@ -103,7 +131,8 @@ def main():
     log(f"generated n={args.n} nnzA={A.nnz} nnzB={B.nnz} in {time.time() - t0:.1f}s")
     At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
     vb = 8
-    plan, colptr, nnz = api.symbolic(At, Bt, torch.float64)
+    opts = api.options(t_esc=args.t_esc, hash_cap=args.hash_cap)
+    plan, colptr, nnz = api.symbolic(At, Bt, torch.float64, opts)
     rowidx = torch.empty(nnz, dtype=torch.int32, device=dev)
     val = torch.empty(nnz, dtype=torch.float64, device=dev)
     stats = plan.stats()
@@ -111,7 +140,7 @@ def main():
     log(f"plan: {stats}")
 
     def step():
-        api.symbolic(At, Bt, torch.float64, plan=plan, out_colptr=colptr)
+        api.symbolic(At, Bt, torch.float64, opts, plan=plan, out_colptr=colptr)
         api.numeric(plan, At.val, Bt.val, rowidx, val)
 
     for _ in range(args.warmup):
@@ -134,9 +163,9 @@ def main():
 
     # ------------------------------------------------------------ roofline of the dominant kernel
     nnzc = np.diff(colptr.cpu().numpy().astype(np.int64))
-    op, nb, bins = per_column_work(A, B)
+    op, nb, bins = per_column_work(A, B, t_esc=args.t_esc or 256, hash_cap=args.hash_cap or 4096)
     kbytes = {}
-    for name in ("esc", "dense", "hash"):
+    for name in bins:
         num, sym = kernel_bytes(op, nb, nnzc, bins[name], vb)
         kbytes[f"{name}_numeric"] = num
         kbytes[f"{name}_symbolic"] = sym

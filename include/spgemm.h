@@ -93,8 +93,8 @@ typedef struct spgemm_plan_s *spgemm_plan;
  *               the dense LDS accumulator (SPA, Section 2.2) when A has at
  *               most dense_rows rows; default 512.
  *   dense_rows  row limit of the dense LDS accumulator, 64..4096; default 4096.
- *   hash_cap    planned distinct rows per LDS hash-table window, 128..2048;
- *               default 2048. Columns with more products are split into
+ *   hash_cap    planned distinct rows per LDS hash-table window, 128..4096;
+ *               default 4096. Columns with more products are split into
  *               row windows.
  */
 typedef struct {

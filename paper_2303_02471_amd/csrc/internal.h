@@ -16,24 +16,33 @@ constexpr int kWave = 64;
 //   ESC_i      max(Op_j, nB_j) <= 4 << i: wavefront sort-merge (Section 4),
 //              64 >> i columns per wavefront group (at most 256 products)
 //   DENSE      dense LDS accumulator over all rows (SPA, Section 2.2)
-//   HASH       LDS hash table per row window (HASH, Section 3.2)
+//   HASH_S/L   LDS hash table per row window (HASH, Section 3.2); the two
+//              bins differ only in the largest table they hold, so the small
+//              one runs with a small LDS footprint (more workgroups per CU)
 enum Bin : int {
     BIN_EMPTY = 0,
     BIN_ESC0 = 1,  // w <= 4
     BIN_ESC6 = 7,  // w <= 256
     BIN_DENSE = 8,
-    BIN_HASH = 9,
-    NBINS = 10
+    BIN_HASH_S = 9,
+    BIN_HASH_L = 10,
+    BIN_HASH_XL = 11,
+    NBINS = 12
 };
+constexpr int kHashBins = 3;
 constexpr int kEscBins = 7;
 constexpr int kEscMaxProducts = 256;  // products and B entries per wavefront group
 
 // dense accumulator: rows per LDS slice
 constexpr int kDenseRows = 4096;
-// hash accumulator: largest table, probe overrun area, threads per block
-constexpr int kHashMax = 4096;
-constexpr int kHashPad = 256;
+// hash accumulator: largest table of the small, large and extra-large class,
+// smallest table, and the probe overrun area behind a table of h slots
+constexpr int kHashMaxS = 1024;
+constexpr int kHashMaxL = 4096;
+constexpr int kHashMax = 8192;
 constexpr int kHashMin = 64;
+__host__ __device__ constexpr int hash_class(int h) { return h <= kHashMaxS ? 0 : (h <= kHashMaxL ? 1 : 2); }
+__host__ __device__ constexpr int hash_pad(int h) { return h >= 1024 ? 256 : h / 4; }
 constexpr int kBlock = 256;
 // columns per classification tile
 constexpr int kTile = 512;
@@ -51,7 +60,8 @@ enum ErrBits : int {
 // pointers. Column j of this problem is global column col0 + j.
 struct Prob {
     int32_t m, k, n, col0;
-    int32_t nnza, nnzb, pad0, pad1;
+    int32_t nnza, nnzb;
+    long long ebase;  // offset of this problem's stored B entries in KArgs::E
     const int32_t *acp, *ari;
     const void *av;
     const int32_t *bcp, *bri;
@@ -64,9 +74,9 @@ struct Prob {
 struct Hdr {
     int32_t bin_count[NBINS];
     int32_t bin_cursor[NBINS];
-    int32_t hash_cols;        // == bin_count[BIN_HASH]
-    int32_t item_count;       // row windows of hash columns
-    unsigned long long hash_cursor;  // (items << 32) | columns placed
+    int32_t item_count[kHashBins];    // row windows (work items) per hash bin
+    int32_t pad0;
+    unsigned long long hash_cursor[kHashBins];  // (items << 32) | columns placed, per hash bin
     int32_t err;
     int32_t pad;
     unsigned long long total_op;
@@ -94,10 +104,14 @@ struct KArgs {
     Hdr *hdr;
     int32_t *op;            // [ncols]
     int32_t *binw;          // [ncols] bin | (windows << 8)
-    int32_t *binlist;       // [ncols]
+    int4 *binlist;          // [ncols] (global column, first stored B entry, B entries, 0),
+                            // grouped by bin
     int32_t *gnnz;          // [ncols]
-    int32_t *firstitem;     // [ncols]: first window index of each hash column
+    int4 *items;            // [item_cap] (global column, window, first B entry, B entries)
+                            // of every hash row window, hash bins in order
     int32_t *itemcnt;       // [item_cap]
+    int2 *E;                // [sum of nnz(B)] (A column start, A column length) of every
+                            // stored B entry, written by the classification
 };
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -136,7 +150,9 @@ __host__ __device__ inline int hash_table_size(int op, int windows) {
 hipError_t launch_classify(const KArgs &a, hipStream_t s);
 hipError_t launch_place(const KArgs &a, hipStream_t s);
 hipError_t launch_esc(const KArgs &a, bool numeric, bool f64, int grid, hipStream_t s);
-hipError_t launch_window(const KArgs &a, bool numeric, bool f64, bool dense, int grid,
+// mode: dense, or one of the three hash table classes
+enum WinMode : int { WIN_DENSE = 0, WIN_HASH_S = 1, WIN_HASH_L = 2, WIN_HASH_XL = 3 };
+hipError_t launch_window(const KArgs &a, bool numeric, bool f64, int mode, int grid,
                          hipStream_t s);
 hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk,
                        long long *totals, hipStream_t s);

@@ -128,7 +128,6 @@ __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
     }
     const int ngroups = gstart[kEscBins];
     const int wstride = gridDim.x * (kBlock / 64);
-
     for (int gi = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); gi < ngroups; gi += wstride) {
         int sb = 0;
 #pragma unroll
@@ -144,13 +143,13 @@ __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
         // ---- level 1: the group's columns, one per lane
         int g = 0, nb = 0;
         if (lane < ncols) {
-            g = a.binlist[first + lane];
+            const int4 ent = a.binlist[first + lane];
+            g = ent.x;
+            nb = ent.z;
             const int pid = find_prob(a, g);
             const Prob d = get_prob(a, pid);
             const int j = g - d.col0;
-            const int bs = d.bcp[j];
-            nb = d.bcp[j + 1] - bs;
-            S.cbs[lane] = bs;
+            S.cbs[lane] = ent.y;
             S.cpid[lane] = pid;
             if (NUM) {
                 const int c0 = d.ccp[j];
@@ -170,39 +169,19 @@ __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
 
         // ---- level 2: stored B entries of the group, in storage order
         int zr[4];
-        {
-            int kk[4], pidr[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int t = lane + 64 * r;
-                kk[r] = -1;
-                pidr[r] = 0;
-                if (t < TB) {
-                    const int cc = last_le(S.boff, ncols, t);
-                    const int p = S.cbs[cc] + t - S.boff[cc];
-                    pidr[r] = S.cpid[cc];
-                    const Prob d = get_prob(a, pidr[r]);
-                    kk[r] = d.bri[p];
-                    S.u.ex.tc[t] = (unsigned char)cc;
-                    if (NUM) S.u.ex.tb[t] = ((const V *)d.bv)[p];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int t = lane + 64 * r;
-                zr[r] = 0;
-                if (t < TB) {
-                    const Prob d = get_prob(a, pidr[r]);
-                    const int k = kk[r];
-                    int x0 = 0, x1 = 0;
-                    if (k >= 0 && k < d.k) {
-                        x0 = d.acp[k];
-                        x1 = d.acp[k + 1];
-                    }
-                    if (x0 < 0 || x1 < x0 || x1 > d.nnza) x1 = x0 = 0;
-                    S.u.ex.tacp[t] = x0;
-                    zr[r] = x1 - x0;
-                }
+        for (int r = 0; r < 4; ++r) {
+            const int t = lane + 64 * r;
+            zr[r] = 0;
+            if (t < TB) {
+                const int cc = last_le(S.boff, ncols, t);
+                const int p = S.cbs[cc] + t - S.boff[cc];
+                const Prob d = get_prob(a, S.cpid[cc]);
+                const int2 ez = a.E[d.ebase + p];  // (A column start, length), checked
+                S.u.ex.tc[t] = (unsigned char)cc;
+                S.u.ex.tacp[t] = ez.x;
+                zr[r] = ez.y;
+                if (NUM) S.u.ex.tb[t] = ((const V *)d.bv)[p];
             }
         }
         int E = 0;

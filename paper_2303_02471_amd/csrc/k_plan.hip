@@ -14,7 +14,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     __shared__ int s_bcp[kTile + 1];
     __shared__ unsigned long long s_op[kTile];
     __shared__ int s_hist[NBINS];
-    __shared__ int s_items;
+    __shared__ int s_items[kHashBins];
     __shared__ int s_err;
     __shared__ unsigned long long s_tot;
 
@@ -34,7 +34,8 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     for (int c = tid; c <= nt; c += kBlock) s_bcp[c] = d.bcp[j0 + c];
     for (int c = tid; c < nt; c += kBlock) s_op[c] = 0;
     if (tid < NBINS) s_hist[tid] = 0;
-    if (tid == 0) { s_items = 0; s_err = 0; s_tot = 0; }
+    if (tid < kHashBins) s_items[tid] = 0;
+    if (tid == 0) { s_err = 0; s_tot = 0; }
     __syncthreads();
 
     // column pointers of B: monotone, inside [0, nnz], 0 first, nnz last
@@ -69,14 +70,19 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
         for (int u = 0; u < 4; ++u) {
             z[u] = 0;
             int k = kk[u];
-            if (p0 + u * kBlock + tid < pe) {
+            const int p = p0 + u * kBlock + tid;
+            if (p < pe) {
+                int x0 = 0;
                 if (k < 0 || k >= d.k) {
                     err = ERR_CSC;
                 } else {
-                    int x0 = d.acp[k], x1 = d.acp[k + 1];
-                    if (x0 < 0 || x1 < x0 || x1 > d.nnza) err = ERR_CSC;
+                    x0 = d.acp[k];
+                    const int x1 = d.acp[k + 1];
+                    if (x0 < 0 || x1 < x0 || x1 > d.nnza) { err = ERR_CSC; x0 = 0; }
                     else z[u] = x1 - x0;
                 }
+                // the A column each stored B entry selects, for the accumulators
+                a.E[d.ebase + p] = make_int2(x0, z[u]);
             }
         }
 #pragma unroll
@@ -111,20 +117,23 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
         if (op == 0) bin = BIN_EMPTY;
         else if (w <= esc_max) bin = BIN_ESC0 + max(ceil_log2(w), 2) - 2;
         else if (d.m <= a.tune.dense_rows && op >= a.tune.t_dense) bin = BIN_DENSE;
-        else { bin = BIN_HASH; W = hash_windows(op, a.tune.hash_cap); }
+        else {
+            W = hash_windows(op, a.tune.hash_cap);
+            bin = BIN_HASH_S + hash_class(hash_table_size(op, W));
+        }
         a.op[g] = op;
         a.binw[g] = bin | (W << 8);
         a.gnnz[g] = 0;
         atomicAdd(&s_hist[bin], 1);
-        if (W) atomicAdd(&s_items, W);
+        if (W) atomicAdd(&s_items[bin - BIN_HASH_S], W);
     }
     if (err) atomicOr(&s_err, err);
     // tile total of products
     atomicAdd(&s_tot, tot);
     __syncthreads();
     if (tid < NBINS && s_hist[tid]) atomicAdd(&a.hdr->bin_count[tid], s_hist[tid]);
+    if (tid < kHashBins && s_items[tid]) atomicAdd(&a.hdr->item_count[tid], s_items[tid]);
     if (tid == 0) {
-        if (s_items) atomicAdd(&a.hdr->item_count, s_items);
         atomicAdd(&a.hdr->total_op, s_tot);
         if (s_err) atomicOr(&a.hdr->err, s_err);
     }
@@ -133,14 +142,15 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
 // ---------------------------------------------------------------- place
 // Same tiling. Each tile reserves a contiguous range in every bin list with
 // one global atomic per bin, then writes its columns there. Hash columns also
-// reserve their row windows; column and window cursors advance in one 64-bit
-// atomic so that window numbering follows the column order of the list.
+// reserve their row windows (work items); column and window cursors advance
+// in one 64-bit atomic per hash bin, so the windows of one column are
+// consecutive items.
 __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
     __shared__ int s_start[NBINS];
     __shared__ int s_cnt[NBINS];
     __shared__ int s_base[NBINS];
-    __shared__ unsigned long long s_hpack;
-    __shared__ unsigned long long s_hbase;
+    __shared__ unsigned long long s_hpack[kHashBins];
+    __shared__ unsigned long long s_hbase[kHashBins];
 
     if (a.hdr->err & (ERR_CSC | ERR_OPOVF)) return;
     int pid, j0, j1;
@@ -161,13 +171,20 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
             s_start[b] = run;
             run += a.hdr->bin_count[b];
         }
-        s_hpack = 0;
+        for (int h = 0; h < kHashBins; ++h) s_hpack[h] = 0;
     }
     if (tid < NBINS) s_cnt[tid] = 0;
     __syncthreads();
+    int item0[kHashBins];
+    int nitems = 0;
+#pragma unroll
+    for (int h = 0; h < kHashBins; ++h) {
+        item0[h] = nitems;
+        nitems += a.hdr->item_count[h];
+    }
 
     constexpr int PER = kTile / kBlock;
-    int rank[PER], binv[PER];
+    int rank[PER], binv[PER], wv[PER];
     unsigned long long hold[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -177,37 +194,43 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
             int bw = a.binw[col0 + j0 + c];
             int bin = bw & 255, W = bw >> 8;
             binv[u] = bin;
-            if (bin == BIN_HASH)
-                hold[u] = atomicAdd(&s_hpack, ((unsigned long long)W << 32) | 1ull);
+            wv[u] = W;
+            if (bin >= BIN_HASH_S)
+                hold[u] = atomicAdd(&s_hpack[bin - BIN_HASH_S], ((unsigned long long)W << 32) | 1ull);
             else
                 rank[u] = atomicAdd(&s_cnt[bin], 1);
         }
     }
     __syncthreads();
-    if (tid < NBINS && tid != BIN_HASH && s_cnt[tid])
+    if (tid < BIN_HASH_S && s_cnt[tid])
         s_base[tid] = s_start[tid] + atomicAdd(&a.hdr->bin_cursor[tid], s_cnt[tid]);
-    if (tid == BIN_HASH && s_hpack) s_hbase = atomicAdd(&a.hdr->hash_cursor, s_hpack);
+    if (tid >= BIN_HASH_S && tid < NBINS && s_hpack[tid - BIN_HASH_S])
+        s_hbase[tid - BIN_HASH_S] =
+            atomicAdd(&a.hdr->hash_cursor[tid - BIN_HASH_S], s_hpack[tid - BIN_HASH_S]);
     __syncthreads();
-    const int hstart = s_start[BIN_HASH];
+    const bool room = nitems <= a.item_cap;
+    const int32_t *bcp = a.nprob == 1 ? a.single.bcp : a.table[pid].bcp;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         int c = tid + u * kBlock;
         if (c >= nt) continue;
         const int g = col0 + j0 + c;
-        if (binv[u] == BIN_HASH) {
-            unsigned long long pos = s_hbase + hold[u];
+        const int bin = binv[u];
+        const int bs = bcp[j0 + c], nb = bcp[j0 + c + 1] - bs;
+        const int4 ent = make_int4(g, bs, nb, 0);
+        if (bin >= BIN_HASH_S) {
+            const int h = bin - BIN_HASH_S;
+            unsigned long long pos = s_hbase[h] + hold[u];
             int hcol = (int)(pos & 0xffffffffull);
-            int item = (int)(pos >> 32);
-            a.binlist[hstart + hcol] = g;
-            a.firstitem[hcol] = item;
+            int item = item0[h] + (int)(pos >> 32);
+            a.binlist[s_start[bin] + hcol] = ent;
+            if (room)
+                for (int w = 0; w < wv[u]; ++w) a.items[item + w] = make_int4(g, w, bs, nb);
         } else {
-            a.binlist[s_base[binv[u]] + rank[u]] = g;
+            a.binlist[s_base[bin] + rank[u]] = ent;
         }
     }
-    if (tid == 0 && s_hpack) {
-        unsigned long long end = s_hbase + s_hpack;
-        if ((long long)(end >> 32) > (long long)a.item_cap) atomicOr(&a.hdr->err, ERR_ITEMCAP);
-    }
+    if (tid == 0 && !room && blockIdx.x == 0) atomicOr(&a.hdr->err, ERR_ITEMCAP);
 }
 
 // ---------------------------------------------------------------- scan of nnz

@@ -9,13 +9,16 @@
 //          h(i) = floor((i - lo) * H / (hi - lo)), and probes never wrap, so
 //          every run of occupied slots only holds rows whose home slots lie in
 //          it; sorting each run in place leaves the whole table ascending.
+//          Two instantiations differ only in the largest table (LDS footprint).
 //
 // Products are taken in the order Algorithm 1 meets them (B entries in
-// storage order, then A's rows in storage order), kBlock at a time. Products
-// of one chunk that land on the same row are added in that order: every
-// pending thread offers (round, thread) to the slot with an LDS atomic max,
-// the lowest thread wins, adds and retires; the others retry next round. The
-// values therefore match Algorithm 1 bit for bit.
+// storage order, then A's rows in storage order), PER * T at a time, each
+// thread holding PER products; the global loads of the next chunk are issued
+// before the current chunk is accumulated. Products of one chunk that land on
+// the same row are added in that order: every pending product offers
+// (round, position in chunk) to its slot with an LDS atomic max, the earliest
+// product wins, adds and retires; the others retry next round. The values
+// therefore match Algorithm 1 bit for bit.
 //
 // A window whose distinct rows overflow the table (linear probing never
 // wraps; a probe running past the table's overrun area fails) is split in
@@ -26,48 +29,101 @@
 
 namespace spg {
 
-template <typename V, bool NUM, bool DENSE>
-struct WinSmem {
-    static constexpr int TBL = DENSE ? kDenseRows : kHashMax + kHashPad;
-    int keys[DENSE ? 1 : TBL];
-    unsigned bitmap[DENSE ? kDenseRows / 32 : 1];
-    unsigned stamps[NUM ? TBL : 1];
-    V vals[NUM ? TBL : 1];
-    int s_acp[kBlock];
-    int s_eoff[kBlock];
-    V s_b[NUM ? kBlock : 1];
-    int scan_tmp[kBlock / 64 + 1];
-    int stk_lo[40], stk_hi[40];
-    int s_fail, s_count, s_err;
+template <int MODE>
+struct WinCfg {
+    static constexpr bool DENSE = MODE == WIN_DENSE;
+    static constexpr int HMAX =
+        MODE == WIN_HASH_S ? kHashMaxS : (MODE == WIN_HASH_L ? kHashMaxL : kHashMax);
+    static constexpr int TBL = DENSE ? kDenseRows : HMAX + hash_pad(HMAX);
+    // threads per workgroup: the extra-large class fills a CU with one
+    // workgroup, the large class with two
+    static constexpr int T = MODE == WIN_HASH_XL ? 1024 : (MODE == WIN_HASH_L ? 512 : 256);
+    static constexpr int PER = 2;  // products per thread per chunk
 };
 
-template <typename V, bool NUM, bool DENSE>
-__global__ __launch_bounds__(kBlock) void k_window(KArgs a) {
-    using SM = WinSmem<V, NUM, DENSE>;
+template <typename V, bool NUM, int MODE>
+struct WinSmem {
+    using C = WinCfg<MODE>;
+    int keys[C::DENSE ? 1 : C::TBL];
+    unsigned bitmap[C::DENSE ? kDenseRows / 32 : 1];
+    unsigned stamps[NUM ? C::TBL : 1];
+    V vals[NUM ? C::TBL : 1];
+    int s_acp[C::T];
+    int s_eoff[C::T];
+    V s_b[NUM ? C::T : 1];
+    int scan_tmp[C::T / 64 + 1];
+    int stk_lo[40], stk_hi[40];
+    int s_count, s_err, s_next;
+};
+
+// exclusive prefix over the workgroup (T threads); contains barriers
+template <int T>
+__device__ __forceinline__ int wg_excl_scan(int v, int *tmp, int &total) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    int inc = wave_incl_scan(v);
+    if (l == 63) tmp[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int i = 0; i < T / 64; ++i) {
+            int x = tmp[i];
+            tmp[i] = run;
+            run += x;
+        }
+        tmp[T / 64] = run;
+    }
+    __syncthreads();
+    int ex = tmp[w] + inc - v;
+    total = tmp[T / 64];
+    __syncthreads();
+    return ex;
+}
+
+template <typename V, bool NUM, int MODE>
+__global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
+    using CF = WinCfg<MODE>;
+    using SM = WinSmem<V, NUM, MODE>;
+    constexpr bool DENSE = CF::DENSE;
+    constexpr int T = CF::T, PER = CF::PER, CH = T * PER;
+    // a stamp is (round << PB) | (CH - 1 - position in chunk)
+    constexpr int PB = CH <= 512 ? 9 : (CH <= 1024 ? 10 : 11);
+    static_assert(CH <= (1 << PB), "chunk positions must fit the stamp");
+    constexpr unsigned kRoundLimit = 1u << (31 - PB);
     __shared__ SM S;
     if (a.hdr->err) return;
     const int tid = threadIdx.x;
-    const int bin = DENSE ? BIN_DENSE : BIN_HASH;
-    int bstart = 0;
-    for (int b = 0; b < bin; ++b) bstart += a.hdr->bin_count[b];
-    const int ncolsbin = a.hdr->bin_count[bin];
-    const int nitems = DENSE ? ncolsbin : a.hdr->item_count;
-    if (!DENSE && nitems > a.item_cap) return;
+
+    int istart = 0, nitems = 0, dstart = 0;
+    if (DENSE) {
+        for (int b = 0; b < BIN_DENSE; ++b) dstart += a.hdr->bin_count[b];
+        nitems = a.hdr->bin_count[BIN_DENSE];
+    } else {
+        int tot = 0;
+        for (int h = 0; h < kHashBins; ++h) {
+            if (h == MODE - WIN_HASH_S) {
+                istart = tot;
+                nitems = a.hdr->item_count[h];
+            }
+            tot += a.hdr->item_count[h];
+        }
+        if (tot > a.item_cap) return;
+    }
 
     unsigned round = 0;
     if (NUM) {
-        for (int s = tid; s < SM::TBL; s += kBlock) S.stamps[s] = 0;
+        for (int s = tid; s < CF::TBL; s += T) S.stamps[s] = 0;
         __syncthreads();
     }
 
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        int g, w = 0, W = 1;
+    for (int li = blockIdx.x; li < nitems; li += gridDim.x) {
+        const int it = istart + li;
+        int g, w = 0, W = 1, bs, nbe;
         if (DENSE) {
-            g = a.binlist[bstart + it];
+            const int4 ent = a.binlist[dstart + li];
+            g = ent.x; bs = ent.y; nbe = ent.z;
         } else {
-            const int h = last_le(a.firstitem, ncolsbin, it);
-            g = a.binlist[bstart + h];
-            w = it - a.firstitem[h];
+            const int4 iw = a.items[it];
+            g = iw.x; w = iw.y; bs = iw.z; nbe = iw.w;
             W = a.binw[g] >> 8;
         }
         const int pid = find_prob(a, g);
@@ -77,7 +133,8 @@ __global__ __launch_bounds__(kBlock) void k_window(KArgs a) {
         const int lo0 = (int)(((long long)w * d.m) / W);
         const int hi0 = (int)(((long long)(w + 1) * d.m) / W);
         const int H = DENSE ? 0 : hash_table_size(op, W);
-        const int bs = d.bcp[j], be = d.bcp[j + 1];
+        const int be = bs + nbe;
+        const int2 *E = a.E + d.ebase;
 
         long long outpos = 0;
         int outlen = 0;
@@ -103,104 +160,137 @@ __global__ __launch_bounds__(kBlock) void k_window(KArgs a) {
             --sp;
             const int x = S.stk_lo[sp], y = S.stk_hi[sp];
             const int span = y - x;
-            const int nslot = DENSE ? span : H + kHashPad;
+            const int nslot = DENSE ? span : H + hash_pad(H);
             __syncthreads();
             // ---- clear the accumulator
             if (DENSE) {
-                for (int s = tid; s < ceil_div(span, 32); s += kBlock) S.bitmap[s] = 0u;
+                for (int s = tid; s < ceil_div(span, 32); s += T) S.bitmap[s] = 0u;
             } else {
-                for (int s = tid; s < nslot; s += kBlock) S.keys[s] = -1;
+                for (int s = tid; s < nslot; s += T) S.keys[s] = -1;
             }
             if (NUM)
-                for (int s = tid; s < nslot; s += kBlock) S.vals[s] = V(0);
-            if (tid == 0) { S.s_fail = 0; S.s_count = 0; }
-            if (NUM && round > (1u << 23)) {  // keep stamps within 24 round bits
-                for (int s = tid; s < SM::TBL; s += kBlock) S.stamps[s] = 0;
+                for (int s = tid; s < nslot; s += T) S.vals[s] = V(0);
+            if (tid == 0) S.s_count = 0;
+            if (NUM && round > kRoundLimit) {  // keep the round inside its stamp bits
+                for (int s = tid; s < CF::TBL; s += T) S.stamps[s] = 0;
                 round = 0;
             }
             __syncthreads();
             const float scale = DENSE ? 0.f : (float)H / (float)span;
 
             bool failed = false;
-            for (int bw = bs; bw < be && !failed; bw += kBlock) {
+            int myfail = 0;
+            for (int bw = bs; bw < be && !failed; bw += T) {
                 const int t = bw + tid;
                 int z = 0, acp = 0;
                 V b = V(0);
                 if (t < be) {
-                    const int k = d.bri[t];
-                    if (k >= 0 && k < d.k) {
-                        acp = d.acp[k];
-                        z = d.acp[k + 1] - acp;
-                    }
+                    const int2 ez = E[t];  // (A column start, length), checked
+                    acp = ez.x;
+                    z = ez.y;
                     if (NUM) b = ((const V *)d.bv)[t];
                 }
                 int Ew;
-                const int ex = block_excl_scan(z, S.scan_tmp, Ew);
+                const int ex = wg_excl_scan<T>(z, S.scan_tmp, Ew);
                 S.s_acp[tid] = acp;
                 S.s_eoff[tid] = ex;
                 if (NUM) S.s_b[tid] = b;
                 __syncthreads();
-                const int nbw = min(kBlock, be - bw);
-                for (int e0 = 0; e0 < Ew; e0 += kBlock) {
-                    const int e = e0 + tid;
-                    bool valid = e < Ew;
-                    int row = -1;
-                    V val = V(0);
-                    if (valid) {
-                        const int tt = last_le(S.s_eoff, nbw, e);
-                        const int q = S.s_acp[tt] + e - S.s_eoff[tt];
-                        row = d.ari[q];
-                        if (NUM) val = ((const V *)d.av)[q] * S.s_b[tt];
-                        if (row < 0 || row >= d.m) { S.s_err = ERR_CSC; valid = false; }
+                const int nbw = min(T, be - bw);
+
+                // fetch the products of the chunk starting at c0 (loads in flight)
+                int nrow[PER];
+                V naval[PER], nbval[PER];
+                auto fetch = [&](int c0) {
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) {
+                        const int e = c0 + u * T + tid;
+                        nrow[u] = -1;
+                        if (e < Ew) {
+                            const int tt = last_le(S.s_eoff, nbw, e);
+                            const int q = S.s_acp[tt] + e - S.s_eoff[tt];
+                            nrow[u] = d.ari[q];
+                            if (NUM) {
+                                naval[u] = ((const V *)d.av)[q];
+                                nbval[u] = S.s_b[tt];
+                            }
+                        }
                     }
-                    valid = valid && row >= x && row < y;
-                    int slot = -1;
-                    bool isnew = false;
-                    if (valid) {
+                };
+                fetch(0);
+                for (int e0 = 0; e0 < Ew; e0 += CH) {
+                    int row[PER];
+                    V val[PER];
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) {
+                        row[u] = nrow[u];
+                        if (NUM) val[u] = naval[u] * nbval[u];
+                    }
+                    if (e0 + CH < Ew) fetch(e0 + CH);
+                    int slot[PER];
+                    int nnew = 0;
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) {
+                        slot[u] = -1;
+                        const int e = e0 + u * T + tid;
+                        if (e >= Ew) continue;
+                        const int r = row[u];
+                        if (r < 0 || r >= d.m) { S.s_err = ERR_CSC; continue; }
+                        if (r < x || r >= y) continue;
                         if (DENSE) {
-                            slot = row - x;
-                            const unsigned bit = 1u << (slot & 31);
-                            const unsigned old = atomicOr(&S.bitmap[slot >> 5], bit);
-                            isnew = !(old & bit);
+                            const int sl = r - x;
+                            const unsigned bit = 1u << (sl & 31);
+                            const unsigned old = atomicOr(&S.bitmap[sl >> 5], bit);
+                            nnew += !(old & bit);
+                            slot[u] = sl;
                         } else {
-                            int s = min((int)((float)(row - x) * scale), H - 1);
+                            int s = min((int)((float)(r - x) * scale), H - 1);
                             while (true) {
-                                if (s >= nslot) { S.s_fail = 1; break; }
+                                if (s >= nslot) { myfail = 1; break; }
                                 int cur = S.keys[s];
                                 if (cur == -1) {
-                                    cur = atomicCAS(&S.keys[s], -1, row);
-                                    if (cur == -1) { isnew = true; slot = s; break; }
+                                    cur = atomicCAS(&S.keys[s], -1, r);
+                                    if (cur == -1) { ++nnew; slot[u] = s; break; }
                                 }
-                                if (cur == row) { slot = s; break; }
+                                if (cur == r) { slot[u] = s; break; }
                                 ++s;
                             }
                         }
                     }
                     if (!NUM) {
-                        const int c = popc64(ballot(isnew));
+                        const int c = wave_sum(nnew);
                         if (lane_id() == 0 && c) atomicAdd(&S.s_count, c);
                     } else {
-                        // ordered accumulation: lowest thread (earliest product) first
-                        bool pending = slot >= 0;
+                        // ordered accumulation: earliest product of each slot first
+                        bool pend[PER];
+#pragma unroll
+                        for (int u = 0; u < PER; ++u) pend[u] = slot[u] >= 0;
                         int more;
                         do {
                             ++round;
-                            const unsigned mine = (round << 8) | (unsigned)(kBlock - 1 - tid);
-                            if (pending) atomicMax(&S.stamps[slot], mine);
-                            __syncthreads();
-                            if (pending && S.stamps[slot] == mine) {
-                                S.vals[slot] = S.vals[slot] + val;
-                                pending = false;
+                            unsigned mine[PER];
+#pragma unroll
+                            for (int u = 0; u < PER; ++u) {
+                                mine[u] = (round << PB) | (unsigned)(CH - 1 - (u * T + tid));
+                                if (pend[u]) atomicMax(&S.stamps[slot[u]], mine[u]);
                             }
-                            more = __syncthreads_or(pending);
+                            __syncthreads();
+                            bool any = false;
+#pragma unroll
+                            for (int u = 0; u < PER; ++u) {
+                                if (pend[u] && S.stamps[slot[u]] == mine[u]) {
+                                    S.vals[slot[u]] = S.vals[slot[u]] + val[u];
+                                    pend[u] = false;
+                                }
+                                any = any || pend[u];
+                            }
+                            more = __syncthreads_or(any);
                         } while (more);
                     }
-                    __syncthreads();
-                    if (S.s_fail) { failed = true; break; }
                 }
-                __syncthreads();
+                failed = __syncthreads_or(myfail);
             }
-            if (failed || S.s_fail) {
+            if (failed) {
                 if (span <= 1 || sp + 2 > 40) {  // cannot happen: one row always fits
                     if (tid == 0) S.s_err = ERR_GROUP;
                     __syncthreads();
@@ -222,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_window(KArgs a) {
             }
             // ---- sort every run of occupied slots (hash only)
             if (!DENSE) {
-                for (int s0 = tid; s0 < nslot; s0 += kBlock) {
+                for (int s0 = tid; s0 < nslot; s0 += T) {
                     if (S.keys[s0] == -1 || (s0 > 0 && S.keys[s0 - 1] != -1)) continue;
                     int e = s0 + 1;
                     while (e < nslot && S.keys[e] != -1) ++e;
@@ -242,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_window(KArgs a) {
                 __syncthreads();
             }
             // ---- emit occupied slots in slot order
-            const int per = ceil_div(nslot, kBlock);
+            const int per = ceil_div(nslot, T);
             const int s0 = tid * per, s1 = min(nslot, s0 + per);
             int mycnt = 0;
             for (int s = s0; s < s1; ++s) {
@@ -250,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_window(KArgs a) {
                 mycnt += occ;
             }
             int tot;
-            int pos = block_excl_scan(mycnt, S.scan_tmp, tot);
+            int pos = wg_excl_scan<T>(mycnt, S.scan_tmp, tot);
             if (total + tot > outlen) {
                 if (tid == 0) S.s_err = ERR_GROUP;
             } else {
@@ -278,18 +368,24 @@ __global__ __launch_bounds__(kBlock) void k_window(KArgs a) {
     }
 }
 
-hipError_t launch_window(const KArgs &a, bool numeric, bool f64, bool dense, int grid,
+hipError_t launch_window(const KArgs &a, bool numeric, bool f64, int mode, int grid,
                          hipStream_t s) {
     if (grid <= 0) return hipSuccess;
-#define SPG_LAUNCH(V, N, D) \
-    hipLaunchKernelGGL((k_window<V, N, D>), dim3(grid), dim3(kBlock), 0, s, a)
+#define SPG_LAUNCH(V, N, M) \
+    hipLaunchKernelGGL((k_window<V, N, M>), dim3(grid), dim3(WinCfg<M>::T), 0, s, a)
+#define SPG_MODES(V, N)                                                \
+    do {                                                               \
+        if (mode == WIN_DENSE) SPG_LAUNCH(V, N, WIN_DENSE);            \
+        else if (mode == WIN_HASH_S) SPG_LAUNCH(V, N, WIN_HASH_S);     \
+        else if (mode == WIN_HASH_L) SPG_LAUNCH(V, N, WIN_HASH_L);     \
+        else SPG_LAUNCH(V, N, WIN_HASH_XL);                            \
+    } while (0)
     if (f64) {
-        if (numeric) { if (dense) SPG_LAUNCH(double, true, true); else SPG_LAUNCH(double, true, false); }
-        else { if (dense) SPG_LAUNCH(double, false, true); else SPG_LAUNCH(double, false, false); }
+        if (numeric) SPG_MODES(double, true); else SPG_MODES(double, false);
     } else {
-        if (numeric) { if (dense) SPG_LAUNCH(float, true, true); else SPG_LAUNCH(float, true, false); }
-        else { if (dense) SPG_LAUNCH(float, false, true); else SPG_LAUNCH(float, false, false); }
+        if (numeric) SPG_MODES(float, true); else SPG_MODES(float, false);
     }
+#undef SPG_MODES
 #undef SPG_LAUNCH
     return hipGetLastError();
 }

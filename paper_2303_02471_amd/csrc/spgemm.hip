@@ -35,8 +35,11 @@ struct spgemm_plan_s {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     Hdr *hdr = nullptr;
-    int32_t *op = nullptr, *binw = nullptr, *binlist = nullptr, *gnnz = nullptr,
-            *firstitem = nullptr, *itemcnt = nullptr, *col0s = nullptr;
+    int32_t *op = nullptr, *binw = nullptr, *gnnz = nullptr,
+            *itemcnt = nullptr, *col0s = nullptr;
+    int4 *binlist = nullptr, *items = nullptr;
+    int2 *E = nullptr;
+    long long total_nnzb = 0;
     long long *gcp = nullptr, *bsum = nullptr, *totals = nullptr;
     Prob *table = nullptr;
     int4 *tiles = nullptr;
@@ -51,6 +54,12 @@ struct spgemm_plan_s {
     // table currently on the device (batched numeric uploads when it changes)
     std::vector<Prob> table_dev_copy;
     hipEvent_t upload_done = nullptr;
+
+    // side streams (default priority) on which the accumulator kinds run
+    // concurrently with the caller's stream; fork/join through events
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[kSide] = {nullptr, nullptr, nullptr};
 
     // backward: row view of B
     void *bt = nullptr;
@@ -111,6 +120,7 @@ spgemm_status hip_status(hipError_t e) {
 
 spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flags) {
     int t_esc = 256, t_dense = 512, dense_rows = kDenseRows, cap = kHashMax / 2;
+    // (cap: the extra-large table class holds kHashMax / 2 distinct rows at load 1/2)
     flags = 0;
     if (opt) {
         if (opt->t_esc) t_esc = opt->t_esc;
@@ -173,8 +183,10 @@ spgemm_status ensure_workspace(spgemm_plan p) {
         return o;
     };
     const size_t o_hdr = take(sizeof(Hdr));
-    const size_t o_op = take(4 * n), o_binw = take(4 * n), o_binlist = take(4 * n),
-                 o_gnnz = take(4 * n), o_first = take(4 * n);
+    const size_t o_op = take(4 * n), o_binw = take(4 * n), o_binlist = take(16 * n),
+                 o_gnnz = take(4 * n);
+    const size_t o_items = take(16 * (size_t)p->item_cap);
+    const size_t o_E = take(8 * (size_t)std::max(p->total_nnzb, 1ll));
     const size_t o_item = take(4 * (size_t)p->item_cap);
     const size_t o_gcp = take(8 * (n + 1));
     const size_t o_bsum = take(8 * (size_t)p->nbsum);
@@ -198,9 +210,10 @@ spgemm_status ensure_workspace(spgemm_plan p) {
     p->hdr = (Hdr *)(b + o_hdr);
     p->op = (int32_t *)(b + o_op);
     p->binw = (int32_t *)(b + o_binw);
-    p->binlist = (int32_t *)(b + o_binlist);
+    p->binlist = (int4 *)(b + o_binlist);
     p->gnnz = (int32_t *)(b + o_gnnz);
-    p->firstitem = (int32_t *)(b + o_first);
+    p->items = (int4 *)(b + o_items);
+    p->E = (int2 *)(b + o_E);
     p->itemcnt = (int32_t *)(b + o_item);
     p->gcp = (long long *)(b + o_gcp);
     p->bsum = (long long *)(b + o_bsum);
@@ -236,7 +249,8 @@ KArgs make_args(spgemm_plan p) {
     a.binw = p->binw;
     a.binlist = p->binlist;
     a.gnnz = p->gnnz;
-    a.firstitem = p->firstitem;
+    a.items = p->items;
+    a.E = p->E;
     a.itemcnt = p->itemcnt;
     return a;
 }
@@ -259,6 +273,55 @@ int device_cus() {
     return cus;
 }
 
+// One launch per accumulator kind, each with one wavefront (sort-merge) or
+// one workgroup (dense, hash) per work item; the grids come from the bin sizes
+// on the host.
+hipError_t ensure_side_streams(spgemm_plan p) {
+    if (p->fork_ev) return hipSuccess;
+    hipError_t e;
+    for (int i = 0; i < spgemm_plan_s::kSide; ++i) {
+        if ((e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking))) return e;
+        if ((e = hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming))) return e;
+    }
+    return hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+}
+
+hipError_t launch_accumulators(spgemm_plan p, const KArgs &a, bool numeric, hipStream_t s) {
+    const bool f64 = p->dt == SPGEMM_F64;
+    const Hdr &h = p->hdr_host;
+    static const char *names[2][5] = {
+        {"esc_symbolic", "dense_symbolic", "hash_s_symbolic", "hash_l_symbolic", "hash_xl_symbolic"},
+        {"esc_numeric", "dense_numeric", "hash_s_numeric", "hash_l_numeric", "hash_xl_numeric"}};
+    const char *const *nm = names[numeric ? 1 : 0];
+    // The accumulator kinds work on disjoint columns: the sort-merge groups
+    // run on the caller's stream, dense + small hash, large hash and
+    // extra-large hash on three side streams, so their memory latencies overlap.
+    hipError_t e;
+    if ((e = hipEventRecord(p->fork_ev, s))) return e;
+    for (int i = 0; i < spgemm_plan_s::kSide; ++i)
+        if ((e = hipStreamWaitEvent(p->side[i], p->fork_ev, 0))) return e;
+    {
+        ProfScope ps(nm[0], s);
+        if ((e = launch_esc(a, numeric, f64, ceil_div(esc_groups(h), kBlock / 64), s))) return e;
+    }
+    {
+        ProfScope ps(nm[1], p->side[0]);
+        if ((e = launch_window(a, numeric, f64, WIN_DENSE, h.bin_count[BIN_DENSE], p->side[0])))
+            return e;
+    }
+    for (int c = 0; c < kHashBins; ++c) {
+        if (!h.item_count[c]) continue;
+        hipStream_t sc = p->side[c];
+        ProfScope ps(nm[2 + c], sc);
+        if ((e = launch_window(a, numeric, f64, WIN_HASH_S + c, h.item_count[c], sc))) return e;
+    }
+    for (int i = 0; i < spgemm_plan_s::kSide; ++i) {
+        if ((e = hipEventRecord(p->join_ev[i], p->side[i]))) return e;
+        if ((e = hipStreamWaitEvent(s, p->join_ev[i], 0))) return e;
+    }
+    return hipSuccess;
+}
+
 // Symbolic launch sequence; returns after the totals are on the host.
 spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4> &tiles_host) {
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -277,19 +340,24 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         }
         SPG_TRY(hipMemsetAsync(p->hdr, 0, sizeof(Hdr), s));
         const KArgs a = make_args(p);
-        const bool f64 = p->dt == SPGEMM_F64;
-        const int cus = device_cus();
         { ProfScope ps("classify", s); SPG_TRY(launch_classify(a, s)); }
         { ProfScope ps("place", s); SPG_TRY(launch_place(a, s)); }
-        if (p->ncols > 0) {
-            { ProfScope ps("esc_symbolic", s);
-              SPG_TRY(launch_esc(a, false, f64, std::min(ceil_div(p->ncols, 4), cus * 16), s)); }
-            { ProfScope ps("dense_symbolic", s);
-              SPG_TRY(launch_window(a, false, f64, true, std::min(p->ncols, cus * 8), s)); }
-            { ProfScope ps("hash_symbolic", s);
-              SPG_TRY(launch_window(a, false, f64, false, std::min(p->item_cap, cus * 8), s)); }
+        // the bin sizes fix the grid of every accumulator launch: read them once
+        SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+        SPG_TRY(hipStreamSynchronize(s));
+        std::memcpy(&p->hdr_host, p->pinned, sizeof(Hdr));
+        int err = p->hdr_host.err;
+        if (err & ERR_ITEMCAP) {
+            // more hash row windows than planned: grow and redo once
+            int items = 0;
+            for (int h = 0; h < kHashBins; ++h) items += p->hdr_host.item_count[h];
+            p->item_cap = items + 1024;
+            continue;
         }
+        if (err & ERR_CSC) return SPGEMM_ERR_CSC;
+        if (err & ERR_OPOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
         if (p->ncols > 0) {
+            SPG_TRY(launch_accumulators(p, a, false, s));
             ProfScope ps("scan", s);
             SPG_TRY(launch_scan(a, p->gcp, p->bsum, p->nblk, p->totals, s));
         }
@@ -302,12 +370,7 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         p->totals_host.assign(p->nprob, 0);
         if (p->ncols > 0)
             std::memcpy(p->totals_host.data(), (char *)p->pinned + sizeof(Hdr), 8 * (size_t)p->nprob);
-        const int err = p->hdr_host.err;
-        if (err & ERR_ITEMCAP) {
-            // more hash row windows than planned: grow and redo once
-            p->item_cap = p->hdr_host.item_count + 1024;
-            continue;
-        }
+        err = p->hdr_host.err;
         if (err & (ERR_CSC | ERR_GROUP)) return SPGEMM_ERR_CSC;
         if (err & (ERR_OPOVF | ERR_NNZOVF)) return SPGEMM_ERR_INDEX_OVERFLOW;
         if (p->ncols == 0) {
@@ -324,16 +387,7 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
 
 spgemm_status run_numeric(spgemm_plan p, hipStream_t s) {
     const KArgs a = make_args(p);
-    const bool f64 = p->dt == SPGEMM_F64;
-    const Hdr &h = p->hdr_host;
-    const int cus = device_cus();
-    const int ng = esc_groups(h);
-    { ProfScope ps("esc_numeric", s);
-      SPG_TRY(launch_esc(a, true, f64, std::min(ceil_div(ng, 4), cus * 16), s)); }
-    { ProfScope ps("dense_numeric", s);
-      SPG_TRY(launch_window(a, true, f64, true, std::min(h.bin_count[BIN_DENSE], cus * 8), s)); }
-    { ProfScope ps("hash_numeric", s);
-      SPG_TRY(launch_window(a, true, f64, false, std::min(h.item_count, cus * 8), s)); }
+    SPG_TRY(launch_accumulators(p, a, true, s));
     p->last_stream = s;
     return SPGEMM_OK;
 }
@@ -376,7 +430,7 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
     uint32_t flags;
     spgemm_status st = resolve_options(opt, tune, flags);
     if (st) return st;
-    long long ncols = 0;
+    long long ncols = 0, nnzb_total = 0;
     std::vector<Prob> probs(count);
     std::vector<int4> tiles;
     for (int i = 0; i < count; ++i) {
@@ -391,6 +445,8 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
         q.m = A[i].nrows; q.k = A[i].ncols; q.n = B[i].ncols;
         q.col0 = (int32_t)ncols;
         q.nnza = A[i].nnz; q.nnzb = B[i].nnz;
+        q.ebase = nnzb_total;
+        nnzb_total += q.nnzb;
         q.acp = A[i].colptr; q.ari = A[i].rowidx; q.av = A[i].val;
         q.bcp = B[i].colptr; q.bri = B[i].rowidx; q.bv = B[i].val;
         q.ccp = C_colptr[i];
@@ -409,6 +465,7 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
     p->flags = flags;
     p->probs = std::move(probs);
     p->ncols = (int)ncols;
+    p->total_nnzb = nnzb_total;
     p->ntiles = (int)tiles.size();
     p->item_cap = std::max(p->item_cap, 2 * p->ncols + 4096);
     p->symbolic_ok = false;
@@ -420,6 +477,10 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
         p->symbolic_ok = true;
         p->hdr_host = Hdr{};
         return SPGEMM_OK;
+    }
+    if (hipError_t e = ensure_side_streams(p)) {
+        if (fresh) spgemm_plan_destroy(p);
+        return hip_status(e);
     }
     st = run_symbolic(p, s, tiles);
     p->last_stream = s;
@@ -570,8 +631,8 @@ spgemm_status spgemm_plan_get_stats(spgemm_plan p, spgemm_plan_stats *out) {
     s.cols_empty = h.bin_count[BIN_EMPTY];
     for (int i = 0; i < kEscBins; ++i) s.cols_esc += h.bin_count[BIN_ESC0 + i];
     s.cols_dense = h.bin_count[BIN_DENSE];
-    s.cols_hash = h.bin_count[BIN_HASH];
-    s.hash_items = h.item_count;
+    s.cols_hash = h.bin_count[BIN_HASH_S] + h.bin_count[BIN_HASH_L] + h.bin_count[BIN_HASH_XL];
+    s.hash_items = h.item_count[0] + h.item_count[1] + h.item_count[2];
     s.esc_groups = esc_groups(h);
     s.nprob = p->nprob;
     *out = s;
@@ -612,6 +673,14 @@ spgemm_status spgemm_profile_read(spgemm_kernel_time *out, int32_t max, int32_t 
 void spgemm_plan_destroy(spgemm_plan p) {
     if (!p) return;
     if (p->last_stream || p->ws) (void)hipStreamSynchronize(p->last_stream);
+    for (int i = 0; i < spgemm_plan_s::kSide; ++i) {
+        if (p->side[i]) {
+            (void)hipStreamSynchronize(p->side[i]);
+            (void)hipStreamDestroy(p->side[i]);
+        }
+        if (p->join_ev[i]) (void)hipEventDestroy(p->join_ev[i]);
+    }
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
     if (p->ws) (void)hipFree(p->ws);
     if (p->bt) (void)hipFree(p->bt);
     if (p->pinned) (void)hipHostFree(p->pinned);
