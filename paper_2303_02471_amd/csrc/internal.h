@@ -46,6 +46,9 @@ __host__ __device__ constexpr int hash_pad(int h) { return h >= 1024 ? 256 : h /
 constexpr int kBlock = 256;
 // columns per classification tile
 constexpr int kTile = 512;
+// row windows per hash column (a window holding more distinct rows than its
+// table splits itself)
+constexpr int kMaxWindows = 4096;
 
 // error bits gathered on the device
 enum ErrBits : int {
@@ -80,6 +83,7 @@ struct Hdr {
     int32_t err;
     int32_t pad;
     unsigned long long total_op;
+    unsigned long long list_products;  // products of the dense and hash columns (list length)
 };
 
 // Resolved tuning values.
@@ -112,6 +116,16 @@ struct KArgs {
     int32_t *itemcnt;       // [item_cap]
     int2 *E;                // [sum of nnz(B)] (A column start, A column length) of every
                             // stored B entry, written by the classification
+    // product lists of the dense and hash columns (built once by the symbolic
+    // phase, reused by every numeric call on the same patterns): for each such
+    // column a segment of Op_j entries, grouped by row window, each window's
+    // products in Algorithm 1 order
+    long long *colprod;     // [ncols] segment start of the column at bin-list position
+    int32_t *colitem;       // [ncols] first work item of the hash column at bin-list position
+    long long *itemstart;   // [item_cap] list start of every hash row window
+    int32_t *itemlen;       // [item_cap] products of every hash row window
+    int32_t *lrow;          // [list products] row of each product
+    int2 *lqp;              // [list products] (A entry q, B entry p) of each product
 };
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -131,9 +145,23 @@ __device__ __forceinline__ Prob get_prob(const KArgs &a, int pid) {
     return a.nprob == 1 ? a.single : a.table[pid];
 }
 
-// Number of hash row windows of a column with `op` products.
+// Number of hash row windows of a column with `op` products (at most
+// kMaxWindows; a window holding too many distinct rows splits itself).
 __host__ __device__ inline int hash_windows(int op, int cap) {
-    return op <= cap ? 1 : ceil_div(op, cap);
+    const int w = op <= cap ? 1 : ceil_div(op, cap);
+    return w < kMaxWindows ? w : kMaxWindows;
+}
+
+// Row window [lo(w), lo(w+1)) of w in [0, W) over m rows, and the window of a row.
+__host__ __device__ inline int window_lo(int w, int W, int m) {
+    return (int)(((long long)w * m) / W);
+}
+__host__ __device__ inline int window_of(int row, int W, int m) {
+    int w = (int)(((long long)row * W) / (m > 0 ? m : 1));
+    if (w >= W) w = W - 1;
+    while (w + 1 < W && window_lo(w + 1, W, m) <= row) ++w;
+    while (w > 0 && window_lo(w, W, m) > row) --w;
+    return w;
 }
 
 // Table size of one hash row window: a power of two at least twice the
@@ -156,6 +184,14 @@ hipError_t launch_window(const KArgs &a, bool numeric, bool f64, int mode, int g
                          hipStream_t s);
 hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk,
                        long long *totals, hipStream_t s);
+// product lists of the dense and hash columns (`ncols_list` bin-list entries
+// from bin-list position `first`, the start of the dense bin); tmp holds
+// ncols_list ints of scratch, bsum nbsum scan partials
+hipError_t launch_lists(const KArgs &a, int first, int ncols_list, int32_t *tmp, long long *bsum,
+                        int nbsum, hipStream_t s);
+// exclusive scan of int32 values into int64
+hipError_t launch_scan_i64(const int32_t *in, int n, long long *bsum, int nbsum, long long *out,
+                           hipStream_t s);
 hipError_t launch_btranspose(const Prob &p, int32_t *rowptr, int32_t *fill, int32_t *colj,
                              int32_t *pos, long long *scratch, int nscratch, hipStream_t s);
 hipError_t launch_backward(const Prob &p, bool f64, const void *av, const void *bv,

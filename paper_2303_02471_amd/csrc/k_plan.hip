@@ -16,7 +16,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     __shared__ int s_hist[NBINS];
     __shared__ int s_items[kHashBins];
     __shared__ int s_err;
-    __shared__ unsigned long long s_tot;
+    __shared__ unsigned long long s_tot, s_ltot;
 
     int pid, j0, j1;
     if (a.nprob == 1) {
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     for (int c = tid; c < nt; c += kBlock) s_op[c] = 0;
     if (tid < NBINS) s_hist[tid] = 0;
     if (tid < kHashBins) s_items[tid] = 0;
-    if (tid == 0) { s_err = 0; s_tot = 0; }
+    if (tid == 0) { s_err = 0; s_tot = 0; s_ltot = 0; }
     __syncthreads();
 
     // column pointers of B: monotone, inside [0, nnz], 0 first, nnz last
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     }
 
     const int esc_max = 4 << (a.tune.esc_bins - 1);
-    unsigned long long tot = 0;
+    unsigned long long tot = 0, ltot = 0;
     err = 0;
     for (int c = tid; c < nt; c += kBlock) {
         const int g = d.col0 + j0 + c;
@@ -124,17 +124,20 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
         a.op[g] = op;
         a.binw[g] = bin | (W << 8);
         a.gnnz[g] = 0;
+        if (bin >= BIN_DENSE) ltot += op64;
         atomicAdd(&s_hist[bin], 1);
         if (W) atomicAdd(&s_items[bin - BIN_HASH_S], W);
     }
     if (err) atomicOr(&s_err, err);
-    // tile total of products
+    // tile totals of products (all, and those of list columns)
     atomicAdd(&s_tot, tot);
+    if (ltot) atomicAdd(&s_ltot, ltot);
     __syncthreads();
     if (tid < NBINS && s_hist[tid]) atomicAdd(&a.hdr->bin_count[tid], s_hist[tid]);
     if (tid < kHashBins && s_items[tid]) atomicAdd(&a.hdr->item_count[tid], s_items[tid]);
     if (tid == 0) {
         atomicAdd(&a.hdr->total_op, s_tot);
+        if (s_ltot) atomicAdd(&a.hdr->list_products, s_ltot);
         if (s_err) atomicOr(&a.hdr->err, s_err);
     }
 }
@@ -224,6 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
             int hcol = (int)(pos & 0xffffffffull);
             int item = item0[h] + (int)(pos >> 32);
             a.binlist[s_start[bin] + hcol] = ent;
+            a.colitem[s_start[bin] + hcol] = item;
             if (room)
                 for (int w = 0; w < wv[u]; ++w) a.items[item + w] = make_int4(g, w, bs, nb);
         } else {
@@ -398,7 +402,54 @@ __global__ __launch_bounds__(kBlock) void k_scan_down_i32(const int32_t *in, int
     }
 }
 
+// exclusive scan of int32 values into int64 (block sums already scanned)
+__global__ __launch_bounds__(kBlock) void k_scan_down_i64(const int32_t *__restrict__ in, int n,
+                                                          const long long *__restrict__ bsum,
+                                                          long long *__restrict__ out) {
+    __shared__ long long s[kScanBlock];
+    const int base = blockIdx.x * kScanBlock;
+    for (int u = 0; u < kScanBlock / kBlock; ++u) {
+        int i = base + u * kBlock + threadIdx.x;
+        s[u * kBlock + threadIdx.x] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    constexpr int PER = kScanBlock / kBlock;
+    long long loc[PER], run = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        loc[u] = run;
+        run += s[threadIdx.x * PER + u];
+    }
+    __syncthreads();
+    s[threadIdx.x] = run;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {
+        long long t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const long long off = bsum[blockIdx.x] + s[threadIdx.x] - run;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        int i = base + threadIdx.x * PER + u;
+        if (i < n) out[i] = off + loc[u];
+    }
+}
+
 // ---------------------------------------------------------------- launchers
+hipError_t launch_scan_i64(const int32_t *in, int n, long long *bsum, int nbsum, long long *out,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nblk = ceil_div(n, kScanBlock);
+    if (nblk + 1 > nbsum) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kBlock), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nblk);
+    hipLaunchKernelGGL(k_scan_down_i64, dim3(nblk), dim3(kBlock), 0, s, in, n,
+                       (const long long *)bsum, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan_i32(const int32_t *in, int n, long long *bsum, int nbsum, int32_t *out,
                            hipStream_t s) {
     if (n <= 0) return hipSuccess;

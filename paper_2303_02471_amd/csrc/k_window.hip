@@ -9,22 +9,23 @@
 //          h(i) = floor((i - lo) * H / (hi - lo)), and probes never wrap, so
 //          every run of occupied slots only holds rows whose home slots lie in
 //          it; sorting each run in place leaves the whole table ascending.
-//          Two instantiations differ only in the largest table (LDS footprint).
+//          Three instantiations differ only in the largest table (LDS
+//          footprint) and in the workgroup size.
 //
-// Products are taken in the order Algorithm 1 meets them (B entries in
-// storage order, then A's rows in storage order), PER * T at a time, each
-// thread holding PER products; the global loads of the next chunk are issued
-// before the current chunk is accumulated. Products of one chunk that land on
-// the same row are added in that order: every pending product offers
-// (round, position in chunk) to its slot with an LDS atomic max, the earliest
-// product wins, adds and retires; the others retry next round. The values
-// therefore match Algorithm 1 bit for bit.
+// The products of the window come from its slice of the column's product list
+// (k_list.hip), already in the order Algorithm 1 meets them. They are taken
+// PER * T at a time, each thread holding PER products; the loads of the next
+// chunk are issued before the current chunk is accumulated. Products of one
+// chunk that land on the same row are added in list order: every pending
+// product offers (round, position in chunk) to its slot with an LDS atomic
+// max, the earliest product wins, adds and retires; the others retry next
+// round. The values therefore match Algorithm 1 bit for bit.
 //
 // A window whose distinct rows overflow the table (linear probing never
 // wraps; a probe running past the table's overrun area fails) is split in
-// halves and each half is redone. The set of occupied slots of linear
-// probing does not depend on the insertion order, so the symbolic and the
-// numeric pass split identically.
+// halves and each half is redone from the same slice. The set of occupied
+// slots of linear probing does not depend on the insertion order, so the
+// symbolic and the numeric pass split identically.
 #include "devutil.h"
 
 namespace spg {
@@ -48,12 +49,9 @@ struct WinSmem {
     unsigned bitmap[C::DENSE ? kDenseRows / 32 : 1];
     unsigned stamps[NUM ? C::TBL : 1];
     V vals[NUM ? C::TBL : 1];
-    int s_acp[C::T];
-    int s_eoff[C::T];
-    V s_b[NUM ? C::T : 1];
     int scan_tmp[C::T / 64 + 1];
     int stk_lo[40], stk_hi[40];
-    int s_count, s_err, s_next;
+    int s_count, s_err;
 };
 
 // exclusive prefix over the workgroup (T threads); contains barriers
@@ -117,24 +115,31 @@ __global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
 
     for (int li = blockIdx.x; li < nitems; li += gridDim.x) {
         const int it = istart + li;
-        int g, w = 0, W = 1, bs, nbe;
+        int g, w = 0, W = 1, len;
+        long long lst;
         if (DENSE) {
-            const int4 ent = a.binlist[dstart + li];
-            g = ent.x; bs = ent.y; nbe = ent.z;
+            g = a.binlist[dstart + li].x;
+            lst = a.colprod[li];  // dense columns open the list range
+            len = a.op[g];
         } else {
             const int4 iw = a.items[it];
-            g = iw.x; w = iw.y; bs = iw.z; nbe = iw.w;
+            g = iw.x;
+            w = iw.y;
             W = a.binw[g] >> 8;
+            lst = a.itemstart[it];
+            len = a.itemlen[it];
         }
         const int pid = find_prob(a, g);
         const Prob d = get_prob(a, pid);
         const int j = g - d.col0;
         const int op = a.op[g];
-        const int lo0 = (int)(((long long)w * d.m) / W);
-        const int hi0 = (int)(((long long)(w + 1) * d.m) / W);
+        const int lo0 = window_lo(w, W, d.m);
+        const int hi0 = window_lo(w + 1, W, d.m);
         const int H = DENSE ? 0 : hash_table_size(op, W);
-        const int be = bs + nbe;
-        const int2 *E = a.E + d.ebase;
+        const int *__restrict__ lrow = a.lrow + lst;
+        const int2 *__restrict__ lqp = a.lqp + lst;
+        const V *__restrict__ av = (const V *)d.av;
+        const V *__restrict__ bv = (const V *)d.bv;
 
         long long outpos = 0;
         int outlen = 0;
@@ -178,118 +183,90 @@ __global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
             __syncthreads();
             const float scale = DENSE ? 0.f : (float)H / (float)span;
 
-            bool failed = false;
             int myfail = 0;
-            for (int bw = bs; bw < be && !failed; bw += T) {
-                const int t = bw + tid;
-                int z = 0, acp = 0;
-                V b = V(0);
-                if (t < be) {
-                    const int2 ez = E[t];  // (A column start, length), checked
-                    acp = ez.x;
-                    z = ez.y;
-                    if (NUM) b = ((const V *)d.bv)[t];
+            // products of the chunk starting at c0 (loads in flight)
+            int nrow[PER];
+            int2 nqp[PER];
+            auto fetch = [&](int c0) {
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int e = c0 + u * T + tid;
+                    nrow[u] = -1;
+                    if (e < len) {
+                        nrow[u] = lrow[e];
+                        if (NUM) nqp[u] = lqp[e];
+                    }
                 }
-                int Ew;
-                const int ex = wg_excl_scan<T>(z, S.scan_tmp, Ew);
-                S.s_acp[tid] = acp;
-                S.s_eoff[tid] = ex;
-                if (NUM) S.s_b[tid] = b;
-                __syncthreads();
-                const int nbw = min(T, be - bw);
-
-                // fetch the products of the chunk starting at c0 (loads in flight)
-                int nrow[PER];
-                V naval[PER], nbval[PER];
-                auto fetch = [&](int c0) {
+            };
+            fetch(0);
+            for (int e0 = 0; e0 < len; e0 += CH) {
+                int row[PER];
+                V val[PER];
 #pragma unroll
-                    for (int u = 0; u < PER; ++u) {
-                        const int e = c0 + u * T + tid;
-                        nrow[u] = -1;
-                        if (e < Ew) {
-                            const int tt = last_le(S.s_eoff, nbw, e);
-                            const int q = S.s_acp[tt] + e - S.s_eoff[tt];
-                            nrow[u] = d.ari[q];
-                            if (NUM) {
-                                naval[u] = ((const V *)d.av)[q];
-                                nbval[u] = S.s_b[tt];
-                            }
-                        }
-                    }
-                };
-                fetch(0);
-                for (int e0 = 0; e0 < Ew; e0 += CH) {
-                    int row[PER];
-                    V val[PER];
+                for (int u = 0; u < PER; ++u) {
+                    row[u] = nrow[u];
+                    if (NUM && row[u] >= 0) val[u] = av[nqp[u].x] * bv[nqp[u].y];
+                }
+                if (e0 + CH < len) fetch(e0 + CH);
+                int slot[PER];
+                int nnew = 0;
 #pragma unroll
-                    for (int u = 0; u < PER; ++u) {
-                        row[u] = nrow[u];
-                        if (NUM) val[u] = naval[u] * nbval[u];
-                    }
-                    if (e0 + CH < Ew) fetch(e0 + CH);
-                    int slot[PER];
-                    int nnew = 0;
-#pragma unroll
-                    for (int u = 0; u < PER; ++u) {
-                        slot[u] = -1;
-                        const int e = e0 + u * T + tid;
-                        if (e >= Ew) continue;
-                        const int r = row[u];
-                        if (r < 0 || r >= d.m) { S.s_err = ERR_CSC; continue; }
-                        if (r < x || r >= y) continue;
-                        if (DENSE) {
-                            const int sl = r - x;
-                            const unsigned bit = 1u << (sl & 31);
-                            const unsigned old = atomicOr(&S.bitmap[sl >> 5], bit);
-                            nnew += !(old & bit);
-                            slot[u] = sl;
-                        } else {
-                            int s = min((int)((float)(r - x) * scale), H - 1);
-                            while (true) {
-                                if (s >= nslot) { myfail = 1; break; }
-                                int cur = S.keys[s];
-                                if (cur == -1) {
-                                    cur = atomicCAS(&S.keys[s], -1, r);
-                                    if (cur == -1) { ++nnew; slot[u] = s; break; }
-                                }
-                                if (cur == r) { slot[u] = s; break; }
-                                ++s;
-                            }
-                        }
-                    }
-                    if (!NUM) {
-                        const int c = wave_sum(nnew);
-                        if (lane_id() == 0 && c) atomicAdd(&S.s_count, c);
+                for (int u = 0; u < PER; ++u) {
+                    slot[u] = -1;
+                    const int r = row[u];
+                    if (r < x || r >= y) continue;  // also skips the padding (-1)
+                    if (DENSE) {
+                        const int sl = r - x;
+                        const unsigned bit = 1u << (sl & 31);
+                        const unsigned old = atomicOr(&S.bitmap[sl >> 5], bit);
+                        nnew += !(old & bit);
+                        slot[u] = sl;
                     } else {
-                        // ordered accumulation: earliest product of each slot first
-                        bool pend[PER];
-#pragma unroll
-                        for (int u = 0; u < PER; ++u) pend[u] = slot[u] >= 0;
-                        int more;
-                        do {
-                            ++round;
-                            unsigned mine[PER];
-#pragma unroll
-                            for (int u = 0; u < PER; ++u) {
-                                mine[u] = (round << PB) | (unsigned)(CH - 1 - (u * T + tid));
-                                if (pend[u]) atomicMax(&S.stamps[slot[u]], mine[u]);
+                        int s = min((int)((float)(r - x) * scale), H - 1);
+                        while (true) {
+                            if (s >= nslot) { myfail = 1; break; }
+                            int cur = S.keys[s];
+                            if (cur == -1) {
+                                cur = atomicCAS(&S.keys[s], -1, r);
+                                if (cur == -1) { ++nnew; slot[u] = s; break; }
                             }
-                            __syncthreads();
-                            bool any = false;
-#pragma unroll
-                            for (int u = 0; u < PER; ++u) {
-                                if (pend[u] && S.stamps[slot[u]] == mine[u]) {
-                                    S.vals[slot[u]] = S.vals[slot[u]] + val[u];
-                                    pend[u] = false;
-                                }
-                                any = any || pend[u];
-                            }
-                            more = __syncthreads_or(any);
-                        } while (more);
+                            if (cur == r) { slot[u] = s; break; }
+                            ++s;
+                        }
                     }
                 }
-                failed = __syncthreads_or(myfail);
+                if (!NUM) {
+                    const int c = wave_sum(nnew);
+                    if (lane_id() == 0 && c) atomicAdd(&S.s_count, c);
+                } else {
+                    // ordered accumulation: earliest product of each slot first
+                    bool pend[PER];
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) pend[u] = slot[u] >= 0;
+                    int more;
+                    do {
+                        ++round;
+                        unsigned mine[PER];
+#pragma unroll
+                        for (int u = 0; u < PER; ++u) {
+                            mine[u] = (round << PB) | (unsigned)(CH - 1 - (u * T + tid));
+                            if (pend[u]) atomicMax(&S.stamps[slot[u]], mine[u]);
+                        }
+                        __syncthreads();
+                        bool any = false;
+#pragma unroll
+                        for (int u = 0; u < PER; ++u) {
+                            if (pend[u] && S.stamps[slot[u]] == mine[u]) {
+                                S.vals[slot[u]] = S.vals[slot[u]] + val[u];
+                                pend[u] = false;
+                            }
+                            any = any || pend[u];
+                        }
+                        more = __syncthreads_or(any);
+                    } while (more);
+                }
             }
+            const bool failed = __syncthreads_or(myfail);
             if (failed) {
                 if (span <= 1 || sp + 2 > 40) {  // cannot happen: one row always fits
                     if (tid == 0) S.s_err = ERR_GROUP;

@@ -40,6 +40,14 @@ struct spgemm_plan_s {
     int4 *binlist = nullptr, *items = nullptr;
     int2 *E = nullptr;
     long long total_nnzb = 0;
+    long long *colprod = nullptr, *itemstart = nullptr;
+    int32_t *colitem = nullptr, *itemlen = nullptr;
+    // product lists of the dense and hash columns (own allocation: its size is
+    // known only after the classification)
+    void *lists = nullptr;
+    size_t lists_bytes = 0;
+    int32_t *lrow = nullptr;
+    int2 *lqp = nullptr;
     long long *gcp = nullptr, *bsum = nullptr, *totals = nullptr;
     Prob *table = nullptr;
     int4 *tiles = nullptr;
@@ -60,6 +68,7 @@ struct spgemm_plan_s {
     static constexpr int kSide = 3;
     hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[kSide] = {nullptr, nullptr, nullptr};
+    hipEvent_t list_ev = nullptr;
 
     // backward: row view of B
     void *bt = nullptr;
@@ -187,6 +196,8 @@ spgemm_status ensure_workspace(spgemm_plan p) {
                  o_gnnz = take(4 * n);
     const size_t o_items = take(16 * (size_t)p->item_cap);
     const size_t o_E = take(8 * (size_t)std::max(p->total_nnzb, 1ll));
+    const size_t o_colprod = take(8 * n), o_colitem = take(4 * n);
+    const size_t o_istart = take(8 * (size_t)p->item_cap), o_ilen = take(4 * (size_t)p->item_cap);
     const size_t o_item = take(4 * (size_t)p->item_cap);
     const size_t o_gcp = take(8 * (n + 1));
     const size_t o_bsum = take(8 * (size_t)p->nbsum);
@@ -214,6 +225,10 @@ spgemm_status ensure_workspace(spgemm_plan p) {
     p->gnnz = (int32_t *)(b + o_gnnz);
     p->items = (int4 *)(b + o_items);
     p->E = (int2 *)(b + o_E);
+    p->colprod = (long long *)(b + o_colprod);
+    p->colitem = (int32_t *)(b + o_colitem);
+    p->itemstart = (long long *)(b + o_istart);
+    p->itemlen = (int32_t *)(b + o_ilen);
     p->itemcnt = (int32_t *)(b + o_item);
     p->gcp = (long long *)(b + o_gcp);
     p->bsum = (long long *)(b + o_bsum);
@@ -251,6 +266,12 @@ KArgs make_args(spgemm_plan p) {
     a.gnnz = p->gnnz;
     a.items = p->items;
     a.E = p->E;
+    a.colprod = p->colprod;
+    a.colitem = p->colitem;
+    a.itemstart = p->itemstart;
+    a.itemlen = p->itemlen;
+    a.lrow = p->lrow;
+    a.lqp = p->lqp;
     a.itemcnt = p->itemcnt;
     return a;
 }
@@ -283,6 +304,7 @@ hipError_t ensure_side_streams(spgemm_plan p) {
         if ((e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking))) return e;
         if ((e = hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming))) return e;
     }
+    if ((e = hipEventCreateWithFlags(&p->list_ev, hipEventDisableTiming))) return e;
     return hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
 }
 
@@ -300,6 +322,20 @@ hipError_t launch_accumulators(spgemm_plan p, const KArgs &a, bool numeric, hipS
     if ((e = hipEventRecord(p->fork_ev, s))) return e;
     for (int i = 0; i < spgemm_plan_s::kSide; ++i)
         if ((e = hipStreamWaitEvent(p->side[i], p->fork_ev, 0))) return e;
+    if (!numeric) {
+        // product lists first (side stream 0); the other side streams wait
+        int first = 0, nlist = 0;
+        for (int b = 0; b < BIN_DENSE; ++b) first += h.bin_count[b];
+        for (int b = BIN_DENSE; b < NBINS; ++b) nlist += h.bin_count[b];
+        {
+            ProfScope ps("lists", p->side[0]);
+            if ((e = launch_lists(a, first, nlist, p->itemcnt, p->bsum, p->nbsum, p->side[0])))
+                return e;
+        }
+        if ((e = hipEventRecord(p->list_ev, p->side[0]))) return e;
+        for (int i = 1; i < spgemm_plan_s::kSide; ++i)
+            if ((e = hipStreamWaitEvent(p->side[i], p->list_ev, 0))) return e;
+    }
     {
         ProfScope ps(nm[0], s);
         if ((e = launch_esc(a, numeric, f64, ceil_div(esc_groups(h), kBlock / 64), s))) return e;
@@ -356,8 +392,21 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         }
         if (err & ERR_CSC) return SPGEMM_ERR_CSC;
         if (err & ERR_OPOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
+        // product lists of the dense and hash columns
+        const size_t L = (size_t)p->hdr_host.list_products;
+        const size_t lneed = align_up(4 * std::max<size_t>(L, 1), 256) + 8 * std::max<size_t>(L, 1);
+        if (lneed > p->lists_bytes) {
+            if (p->lists) (void)hipFree(p->lists);
+            p->lists = nullptr;
+            p->lists_bytes = 0;
+            if (hipMalloc(&p->lists, lneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
+            p->lists_bytes = lneed;
+        }
+        p->lrow = (int32_t *)p->lists;
+        p->lqp = (int2 *)((char *)p->lists + align_up(4 * std::max<size_t>(L, 1), 256));
         if (p->ncols > 0) {
-            SPG_TRY(launch_accumulators(p, a, false, s));
+            const KArgs al = make_args(p);
+            SPG_TRY(launch_accumulators(p, al, false, s));
             ProfScope ps("scan", s);
             SPG_TRY(launch_scan(a, p->gcp, p->bsum, p->nblk, p->totals, s));
         }
@@ -681,6 +730,8 @@ void spgemm_plan_destroy(spgemm_plan p) {
         if (p->join_ev[i]) (void)hipEventDestroy(p->join_ev[i]);
     }
     if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+    if (p->list_ev) (void)hipEventDestroy(p->list_ev);
+    if (p->lists) (void)hipFree(p->lists);
     if (p->ws) (void)hipFree(p->ws);
     if (p->bt) (void)hipFree(p->bt);
     if (p->pinned) (void)hipHostFree(p->pinned);
