@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--t-esc", type=int, default=0, help="library option (0 = default)")
     ap.add_argument("--hash-cap", type=int, default=0, help="library option (0 = default)")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="library option: no overlap of accumulator kinds (per-kernel timings)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -96,12 +98,13 @@ def per_column_work(A, B, m_dense_limit=4096, t_esc=256, t_dense=512, hash_cap=4
 
 def kernel_bytes(op, nb, nnzc, sel, vb):
     """Algorithmic bytes of the accumulator kernels over the columns `sel`.
-    numeric: B colptr pair 8, B entry (4+vb) + A colptr pair 8 per stored B
-    entry, (4+vb) per product (A row and value), C colptr pair 8, (4+vb) per
-    output entry. symbolic: 8 + 12 per B entry + 4 per product + 4."""
+    numeric: B column pointer 4 per column, B entry (4+vb) + A column pointer
+    pair 8 per stored B entry, (4+vb) per product (A row and value), C column
+    pointer 4 per column, (4+vb) per output entry. symbolic: 4 per column, 12
+    per stored B entry, 4 per product, 4 per column (the count)."""
     s_nb, s_op, s_nnz, ncol = int(nb[sel].sum()), int(op[sel].sum()), int(nnzc[sel].sum()), int(sel.sum())
-    num = 8 * ncol + (4 + vb + 8) * s_nb + (4 + vb) * s_op + 8 * ncol + (4 + vb) * s_nnz
-    sym = 8 * ncol + 12 * s_nb + 4 * s_op + 4 * ncol
+    num = 4 * ncol + (4 + vb + 8) * s_nb + (4 + vb) * s_op + 4 * ncol + (4 + vb) * s_nnz
+    sym = 4 * ncol + 12 * s_nb + 4 * s_op + 4 * ncol
     return num, sym
 
 
@@ -131,7 +134,7 @@ def main():
     log(f"generated n={args.n} nnzA={A.nnz} nnzB={B.nnz} in {time.time() - t0:.1f}s")
     At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
     vb = 8
-    opts = api.options(t_esc=args.t_esc, hash_cap=args.hash_cap)
+    opts = api.options(t_esc=args.t_esc, hash_cap=args.hash_cap, one_stream=args.one_stream)
     plan, colptr, nnz = api.symbolic(At, Bt, torch.float64, opts)
     rowidx = torch.empty(nnz, dtype=torch.int32, device=dev)
     val = torch.empty(nnz, dtype=torch.float64, device=dev)
@@ -169,8 +172,13 @@ def main():
         num, sym = kernel_bytes(op, nb, nnzc, bins[name], vb)
         kbytes[f"{name}_numeric"] = num
         kbytes[f"{name}_symbolic"] = sym
+    kbytes["numeric"] = sum(kbytes[f"{k}_numeric"] for k in bins)
+    # expansion: (A column start, length) per stored B entry, A row read and
+    # product row written per product
+    kbytes["expand"] = 8 * B.nnz + 8 * int(op.sum())
     kbytes["classify"] = 4 * (B.ncols + 1) + 12 * B.nnz + 12 * B.ncols
     kbytes["place"] = 8 * B.ncols
+    kbytes["product_offsets"] = 4 * B.ncols + 8 * B.ncols
     kbytes["scan"] = 4 * B.ncols + 4 * (B.ncols + 1) + 8 * B.ncols
     kernels = {}
     for name, (launches, tot) in prof.items():

@@ -80,6 +80,9 @@ typedef struct spgemm_plan_s *spgemm_plan;
 
 /* flags */
 #define SPGEMM_VALIDATE 1u /* host-side check of both inputs, including repeated rows per column */
+#define SPGEMM_ONE_STREAM 2u /* run every accumulator kind on the caller's stream instead of
+                                 overlapping them on internal side streams (same results;
+                                 per-kernel timings without overlap) */
 
 /*
  * Tuning options. Results never depend on them: they only choose which

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libspgemm.so")
 SPGEMM_F32 = 0
 SPGEMM_F64 = 1
 SPGEMM_VALIDATE = 1
+SPGEMM_ONE_STREAM = 2
 
 STATUS = {
     0: "SPGEMM_OK", 1: "SPGEMM_ERR_NULL", 2: "SPGEMM_ERR_SHAPE", 3: "SPGEMM_ERR_CSC",

@@ -83,7 +83,10 @@ struct Hdr {
     int32_t err;
     int32_t pad;
     unsigned long long total_op;
-    unsigned long long list_products;  // products of the dense and hash columns (list length)
+    unsigned long long list_products;  // products of the dense and hash columns
+    unsigned long long later_count;    // products that are not the first of their output entry
+    int32_t later_maxk;                // largest occurrence index k of any product
+    int32_t pad2;
 };
 
 // Resolved tuning values.
@@ -111,22 +114,37 @@ struct KArgs {
     int4 *binlist;          // [ncols] (global column, first stored B entry, B entries, 0),
                             // grouped by bin
     int32_t *gnnz;          // [ncols]
-    int4 *items;            // [item_cap] (global column, window, first B entry, B entries)
-                            // of every hash row window, hash bins in order
-    int32_t *itemcnt;       // [item_cap]
+    int4 *items;            // [item_cap] (global column, bin-list position, first B entry,
+                            // B entries) of every hash row window, hash bins in order; the
+                            // windows of one column are consecutive from colitem[column]
+    int32_t *itemcnt;       // [item_cap] distinct rows of every hash row window
+    int32_t *itemoff;       // [item_cap] distinct rows of the column's earlier windows
+    int32_t *colitem;       // [ncols] first work item of every hash column (by global column)
     int2 *E;                // [sum of nnz(B)] (A column start, A column length) of every
                             // stored B entry, written by the classification
-    // product lists of the dense and hash columns (built once by the symbolic
-    // phase, reused by every numeric call on the same patterns): for each such
-    // column a segment of Op_j entries, grouped by row window, each window's
-    // products in Algorithm 1 order
-    long long *colprod;     // [ncols] segment start of the column at bin-list position
-    int32_t *colitem;       // [ncols] first work item of the hash column at bin-list position
-    long long *itemstart;   // [item_cap] list start of every hash row window
-    int32_t *itemlen;       // [item_cap] products of every hash row window
-    int32_t *lrow;          // [list products] row of each product
-    int2 *lqp;              // [list products] (A entry q, B entry p) of each product
+    // Product space: the products of all columns in column order (problems in
+    // order), each column's products in the order Algorithm 1 meets them:
+    // stored B entries in storage order, then the rows of the selected A
+    // column in storage order.
+    long long *colprod;     // [ncols + 1] first product of every global column
+    int32_t *prow;          // [products] row of every product (written once by the expansion)
+    uint32_t *dst;          // [products] destination of every product (see below)
+    // Products that are not the first of their output entry ("later"
+    // products), in a compact list: occurrence index k >= 1 and output rank
+    // (symbolic), and the output position, problem and value staged by the
+    // numeric phase.
+    long long later_cap;
+    int32_t *lk;            // [later_cap]
+    int32_t *lr;            // [later_cap] rank of the output row (as in dst)
+    int32_t *lo;            // [later count]
+    int32_t *lpid;          // [later count]
+    void *lv;               // [later count] values (V)
 };
+
+// Destination code of a product: the rank of its output row inside its
+// column (for a hash column split into row windows: inside its window), or,
+// for a later product, kDstLater | its index in the later list.
+constexpr uint32_t kDstLater = 0x80000000u;
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
@@ -177,18 +195,21 @@ __host__ __device__ inline int hash_table_size(int op, int windows) {
 // Each returns hipSuccess or the launch error.
 hipError_t launch_classify(const KArgs &a, hipStream_t s);
 hipError_t launch_place(const KArgs &a, hipStream_t s);
-hipError_t launch_esc(const KArgs &a, bool numeric, bool f64, int grid, hipStream_t s);
+hipError_t launch_esc(const KArgs &a, int grid, hipStream_t s);
 // mode: dense, or one of the three hash table classes
 enum WinMode : int { WIN_DENSE = 0, WIN_HASH_S = 1, WIN_HASH_L = 2, WIN_HASH_XL = 3 };
-hipError_t launch_window(const KArgs &a, bool numeric, bool f64, int mode, int grid,
-                         hipStream_t s);
+hipError_t launch_window(const KArgs &a, int mode, int grid, hipStream_t s);
 hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk,
                        long long *totals, hipStream_t s);
-// product lists of the dense and hash columns (`ncols_list` bin-list entries
-// from bin-list position `first`, the start of the dense bin); tmp holds
-// ncols_list ints of scratch, bsum nbsum scan partials
-hipError_t launch_lists(const KArgs &a, int first, int ncols_list, int32_t *tmp, long long *bsum,
-                        int nbsum, hipStream_t s);
+// row of every product (prow), one workgroup per column tile
+hipError_t launch_expand(const KArgs &a, hipStream_t s);
+// numeric phase: every first product written to its output entry, later
+// products staged; one workgroup per column tile
+hipError_t launch_numeric(const KArgs &a, bool f64, hipStream_t s);
+// adds the staged later products of occurrence index k (n of them listed)
+hipError_t launch_layer(const KArgs &a, bool f64, int k, long long n, hipStream_t s);
+// itemoff of the `n` hash columns from bin-list position `first`
+hipError_t launch_item_offsets(const KArgs &a, int first, int n, hipStream_t s);
 // exclusive scan of int32 values into int64
 hipError_t launch_scan_i64(const int32_t *in, int n, long long *bsum, int nbsum, long long *out,
                            hipStream_t s);

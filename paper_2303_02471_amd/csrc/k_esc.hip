@@ -3,38 +3,29 @@
 //
 // A group holds up to 64 columns whose products and stored B entries each add
 // up to at most 256. The wavefront
-//   1. expands every product of the group in the order the sequential SPA of
-//      Algorithm 1 meets them (B entries in storage order, then the rows of
-//      the A column in storage order); e is the position in that order;
+//   1. reads the rows of the group's products from the product space (each
+//      column's products in the order the sequential SPA of Algorithm 1 meets
+//      them); e is the position in the group;
 //   2. sorts the keys (column, row, e) with a register bitonic network whose
 //      lane exchanges use DPP, ds_swizzle and ds_bpermute;
-//   3. compresses: the first key of every (column, row) run sums the run's
-//      products in e order, which is the order Algorithm 1 adds them, so the
-//      values are bit-identical to it; its rank inside the column is its
-//      output position (rows come out ascending).
-// The symbolic mode runs steps 1-3 without values and counts the runs.
+//   3. compresses: every (column, row) run is one output entry; its rank
+//      inside the column is its output position (rows come out ascending),
+//      and the position of a key inside its run is the occurrence index k of
+//      that product among the products Algorithm 1 adds into the entry.
+// It counts the runs per column and records the destination of every
+// product: the rank of its row for the first product of a run, a place in the
+// list of later products (with k and the rank) for the others.
 #include "devutil.h"
 
 namespace spg {
 
-template <typename V, bool NUM>
 struct EscSmem {
-    int boff[65];   // first B-entry index of each column in the group
-    int cbs[64];    // first stored B entry of each column
-    int cpid[64];   // problem of each column
-    int cbase[64];  // output position of each column (numeric)
-    int clen[64];   // nnz of each output column (numeric)
-    int cnt[64];    // symbolic: runs per column; numeric: first run index
-    union {
-        struct {
-            int tacp[kEscMaxProducts];       // A column start per B entry
-            int teoff[kEscMaxProducts + 1];  // first product index per B entry
-            unsigned char tc[kEscMaxProducts];
-            V tb[NUM ? kEscMaxProducts : 1];  // B value per entry
-        } ex;
-        unsigned long long sk[kEscMaxProducts];  // sorted keys
-    } u;
-    V pv[NUM ? kEscMaxProducts : 1];  // product value by expansion position
+    int goff[65];    // first product of each column inside the group
+    long long cbase[64];  // first product of each column in the product space
+    int cnt[65];     // first run index of each column
+    long long lbase; // first place of the group's later products in the later list
+    unsigned long long sk[kEscMaxProducts];  // sorted keys
+    int rh[kEscMaxProducts];                 // sorted position of every run head
 };
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -103,12 +94,11 @@ __device__ __forceinline__ void wave_bitonic_sort(unsigned long long (&key)[4]) 
 
 constexpr unsigned long long kNoKey = ~0ull;
 
-template <typename V, bool NUM>
 __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
-    __shared__ EscSmem<V, NUM> smem[kBlock / 64];
+    __shared__ EscSmem smem[kBlock / 64];
     if (a.hdr->err) return;
     const int lane = lane_id();
-    EscSmem<V, NUM> &S = smem[threadIdx.x >> 6];
+    EscSmem &S = smem[threadIdx.x >> 6];
 
     // group numbering over the sort-merge sub-bins
     int bstart[kEscBins], bcnt[kEscBins], gstart[kEscBins + 1];
@@ -140,114 +130,59 @@ __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
         const int ncols = min(G, cntb - lg * G);
         first += lg * G;
 
-        // ---- level 1: the group's columns, one per lane
-        int g = 0, nb = 0;
+        // ---- the group's columns, one per lane
+        int g = 0, op = 0;
         if (lane < ncols) {
-            const int4 ent = a.binlist[first + lane];
-            g = ent.x;
-            nb = ent.z;
-            const int pid = find_prob(a, g);
-            const Prob d = get_prob(a, pid);
-            const int j = g - d.col0;
-            S.cbs[lane] = ent.y;
-            S.cpid[lane] = pid;
-            if (NUM) {
-                const int c0 = d.ccp[j];
-                S.cbase[lane] = c0;
-                S.clen[lane] = d.ccp[j + 1] - c0;
-            }
+            g = a.binlist[first + lane].x;
+            op = a.op[g];
+            S.cbase[lane] = a.colprod[g];
         }
-        const int incl = wave_incl_scan(nb);
-        const int TB = wave_bcast(incl, 63);
-        S.boff[lane] = incl - nb;
+        const int incl = wave_incl_scan(op);
+        const int E = wave_bcast(incl, 63);
+        S.goff[lane] = incl - op;
         S.cnt[lane] = 0;
-        if (TB > kEscMaxProducts) {  // cannot happen for unchanged inputs
+        if (E > kEscMaxProducts) {  // cannot happen for unchanged inputs
             if (lane == 0) atomicOr(&a.hdr->err, ERR_GROUP);
             continue;
         }
         wave_sync_lds();
 
-        // ---- level 2: stored B entries of the group, in storage order
-        int zr[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int t = lane + 64 * r;
-            zr[r] = 0;
-            if (t < TB) {
-                const int cc = last_le(S.boff, ncols, t);
-                const int p = S.cbs[cc] + t - S.boff[cc];
-                const Prob d = get_prob(a, S.cpid[cc]);
-                const int2 ez = a.E[d.ebase + p];  // (A column start, length), checked
-                S.u.ex.tc[t] = (unsigned char)cc;
-                S.u.ex.tacp[t] = ez.x;
-                zr[r] = ez.y;
-                if (NUM) S.u.ex.tb[t] = ((const V *)d.bv)[p];
-            }
-        }
-        int E = 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int t = lane + 64 * r;
-            const int inc = wave_incl_scan(zr[r]);
-            if (t < TB) S.u.ex.teoff[t] = E + inc - zr[r];
-            E += wave_bcast(inc, 63);
-        }
-        if (E > kEscMaxProducts) {
-            if (lane == 0) atomicOr(&a.hdr->err, ERR_GROUP);
-            continue;
-        }
-        wave_sync_lds();
-
-        // ---- level 3: products, key = (column, row, e)
+        // ---- keys (column, row, e) of the group's products
         unsigned long long key[4];
-        int bad = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int e = lane + 64 * r;
             key[r] = kNoKey;
             if (e < E) {
-                const int tt = last_le(S.u.ex.teoff, TB, e);
-                const int q = S.u.ex.tacp[tt] + e - S.u.ex.teoff[tt];
-                const int cc = S.u.ex.tc[tt];
-                const Prob d = get_prob(a, S.cpid[cc]);
-                const int row = d.ari[q];
-                if (row < 0 || row >= d.m) {
-                    bad = 1;
-                } else {
-                    key[r] = ((unsigned long long)cc << 40) | ((unsigned long long)row << 8) |
-                             (unsigned long long)e;
-                    if (NUM) S.pv[e] = ((const V *)d.av)[q] * S.u.ex.tb[tt];
-                }
+                const int cc = last_le(S.goff, ncols, e);
+                const int row = a.prow[S.cbase[cc] + (e - S.goff[cc])];
+                key[r] = ((unsigned long long)cc << 40) | ((unsigned long long)row << 8) |
+                         (unsigned long long)e;
             }
-        }
-        if (ballot(bad)) {
-            if (lane == 0) atomicOr(&a.hdr->err, ERR_CSC);
-            continue;
         }
         const int R = E <= 64 ? 1 : (E <= 128 ? 2 : 4);
         if (R == 1) wave_bitonic_sort<1>(key);
         else if (R == 2) wave_bitonic_sort<2>(key);
         else wave_bitonic_sort<4>(key);
-        wave_sync_lds();
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            if (r < R) S.u.sk[r * 64 + lane] = key[r];
+            if (r < R) S.sk[r * 64 + lane] = key[r];
         wave_sync_lds();
 
-        // ---- compress
+        // ---- compress: run heads, run index of every sorted key
         bool head[4];
-        int hidx[4];
+        int run[4];
         int before = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int s = r * 64 + lane;
             head[r] = false;
             if (r < R && key[r] != kNoKey) {
-                const unsigned long long prev = s > 0 ? S.u.sk[s - 1] : kNoKey;
+                const unsigned long long prev = s > 0 ? S.sk[s - 1] : kNoKey;
                 head[r] = (prev >> 8) != (key[r] >> 8);
             }
             const unsigned long long m = ballot(head[r]);
-            hidx[r] = before + popc64(m & mask_lt());
+            run[r] = before + popc64(m & mask_lt()) + (head[r] ? 0 : -1);
             before += popc64(m);
         }
 #pragma unroll
@@ -255,51 +190,59 @@ __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
             if (!head[r]) continue;
             const int s = r * 64 + lane;
             const int cc = (int)(key[r] >> 40);
-            if (NUM) {
-                const unsigned long long prev = s > 0 ? S.u.sk[s - 1] : kNoKey;
-                if ((prev >> 40) != (unsigned long long)cc) S.cnt[cc] = hidx[r];
-            } else {
-                atomicAdd(&S.cnt[cc], 1);
-            }
+            S.rh[run[r]] = s;
+            const unsigned long long prev = s > 0 ? S.sk[s - 1] : kNoKey;
+            if ((prev >> 40) != (unsigned long long)cc) S.cnt[cc] = run[r];
         }
+        if (lane == 0) S.cnt[ncols] = before;
         wave_sync_lds();
-        if (!NUM) {
-            if (lane < ncols) a.gnnz[g] = S.cnt[lane];
-            continue;
+        if (lane < ncols) a.gnnz[g] = S.cnt[lane + 1] - S.cnt[lane];
+        // later products of the group: one reservation in the later list
+        const int nlater = E - before;
+        long long lbase = 0;
+        if (nlater > 0) {
+            int kmax = 0;
+            if (lane == 0)
+                S.lbase = (long long)atomicAdd(&a.hdr->later_count, (unsigned long long)nlater);
+            wave_sync_lds();
+            lbase = S.lbase;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < R && key[r] != kNoKey) kmax = max(kmax, r * 64 + lane - S.rh[run[r]]);
+#pragma unroll
+            for (int dd = 32; dd >= 1; dd >>= 1)
+                kmax = max(kmax, __builtin_amdgcn_ds_bpermute((lane ^ dd) << 2, kmax));
+            if (lane == 0) atomicMax(&a.hdr->later_maxk, kmax);
         }
-        int oob = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (!head[r]) continue;
+            if (r >= R || key[r] == kNoKey) continue;
             const int s = r * 64 + lane;
-            const unsigned long long kr = key[r] >> 8;
             const int cc = (int)(key[r] >> 40);
-            V acc = V(0);
-            for (int t = s; t < E; ++t) {
-                const unsigned long long k2 = S.u.sk[t];
-                if ((k2 >> 8) != kr) break;
-                acc = acc + S.pv[(int)(k2 & 255u)];
+            const int e = (int)(key[r] & 255u);
+            const int rank = run[r] - S.cnt[cc];
+            const int k = s - S.rh[run[r]];
+            const long long pe = S.cbase[cc] + (e - S.goff[cc]);
+            if (k == 0) {
+                a.dst[pe] = (uint32_t)rank;
+            } else {
+                // later products of the group take places in sorted order
+                const long long li = lbase + (s - run[r] - 1);
+                if (li < a.later_cap) {
+                    a.dst[pe] = kDstLater | (uint32_t)li;
+                    a.lk[li] = k;
+                    a.lr[li] = rank;
+                } else {
+                    atomicOr(&a.hdr->err, ERR_GROUP);
+                }
             }
-            const int rank = hidx[r] - S.cnt[cc];
-            if (rank >= S.clen[cc]) { oob = 1; continue; }
-            const int out = S.cbase[cc] + rank;
-            const Prob d = get_prob(a, S.cpid[cc]);
-            d.cri[out] = (int)((key[r] >> 8) & 0x7fffffffull);
-            ((V *)d.cv)[out] = acc;
         }
-        if (ballot(oob) && lane == 0) atomicOr(&a.hdr->err, ERR_GROUP);
     }
 }
 
-hipError_t launch_esc(const KArgs &a, bool numeric, bool f64, int grid, hipStream_t s) {
+hipError_t launch_esc(const KArgs &a, int grid, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
-    if (f64) {
-        if (numeric) hipLaunchKernelGGL((k_esc<double, true>), dim3(grid), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((k_esc<double, false>), dim3(grid), dim3(kBlock), 0, s, a);
-    } else {
-        if (numeric) hipLaunchKernelGGL((k_esc<float, true>), dim3(grid), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((k_esc<float, false>), dim3(grid), dim3(kBlock), 0, s, a);
-    }
+    hipLaunchKernelGGL(k_esc, dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

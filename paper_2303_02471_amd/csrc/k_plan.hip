@@ -226,10 +226,11 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
             unsigned long long pos = s_hbase[h] + hold[u];
             int hcol = (int)(pos & 0xffffffffull);
             int item = item0[h] + (int)(pos >> 32);
-            a.binlist[s_start[bin] + hcol] = ent;
-            a.colitem[s_start[bin] + hcol] = item;
+            const int lpos = s_start[bin] + hcol;
+            a.binlist[lpos] = ent;
+            a.colitem[g] = item;
             if (room)
-                for (int w = 0; w < wv[u]; ++w) a.items[item + w] = make_int4(g, w, bs, nb);
+                for (int w = 0; w < wv[u]; ++w) a.items[item + w] = make_int4(g, lpos, bs, nb);
         } else {
             a.binlist[s_base[bin] + rank[u]] = ent;
         }

@@ -1,31 +1,36 @@
-// LDS accumulators for heavier columns, one workgroup per (column, row window):
+// Symbolic accumulators of the heavier columns, one workgroup per (column,
+// row window):
 //
-//   DENSE: the SPA of Section 2.2 restricted to LDS -- a value slot per row of
-//          the window plus an occupancy bitmap; rows come out ascending by
-//          scanning the bitmap.
+//   DENSE: the SPA of Section 2.2 restricted to LDS -- one slot per row of the
+//          window plus an occupancy bitmap; the rank of a row is the number
+//          of occupied rows below it.
 //   HASH:  the hash accumulator of Section 3.2 -- an open-addressing table with
 //          linear probing, sized per column from its product count (its
 //          size adaptation). The hash is order-preserving,
 //          h(i) = floor((i - lo) * H / (hi - lo)), and probes never wrap, so
 //          every run of occupied slots only holds rows whose home slots lie in
-//          it; sorting each run in place leaves the whole table ascending.
+//          it, and all of them lie between the rows of the runs before and
+//          after it: the rank of a row is the number of occupied slots before
+//          its run plus the number of smaller rows inside its run.
 //          Three instantiations differ only in the largest table (LDS
 //          footprint) and in the workgroup size.
 //
-// The products of the window come from its slice of the column's product list
-// (k_list.hip), already in the order Algorithm 1 meets them. They are taken
-// PER * T at a time, each thread holding PER products; the loads of the next
-// chunk are issued before the current chunk is accumulated. Products of one
-// chunk that land on the same row are added in list order: every pending
-// product offers (round, position in chunk) to its slot with an LDS atomic
-// max, the earliest product wins, adds and retires; the others retry next
-// round. The values therefore match Algorithm 1 bit for bit.
+// Pass 1 expands the window's products in the order Algorithm 1 meets them
+// (stored B entries in storage order, then the rows of the selected A column
+// in storage order) and inserts their rows, counting products per slot. When
+// the window is the whole column it also writes each product's slot to the
+// product's destination entry. After the ranks are known, pass 2 streams
+// those slots (or expands the products again for a windowed or split column)
+// and records the destination of every product: the rank of its row in the
+// window, and for an output reached by several products the occurrence index
+// k of the product among them (list order). Products of one chunk that land on the
+// same slot take their k in list order: every pending product offers
+// (round, position in chunk) to the slot with an LDS atomic max, the earliest
+// one wins and retires; the others retry next round.
 //
 // A window whose distinct rows overflow the table (linear probing never
 // wraps; a probe running past the table's overrun area fails) is split in
-// halves and each half is redone from the same slice. The set of occupied
-// slots of linear probing does not depend on the insertion order, so the
-// symbolic and the numeric pass split identically.
+// halves and each half is redone; ranks continue across the halves.
 #include "devutil.h"
 
 namespace spg {
@@ -42,16 +47,19 @@ struct WinCfg {
     static constexpr int PER = 2;  // products per thread per chunk
 };
 
-template <typename V, bool NUM, int MODE>
+template <int MODE>
 struct WinSmem {
     using C = WinCfg<MODE>;
-    int keys[C::DENSE ? 1 : C::TBL];
+    int keys[C::DENSE ? 1 : C::TBL];  // row held by each slot, -1 when empty
     unsigned bitmap[C::DENSE ? kDenseRows / 32 : 1];
-    unsigned stamps[NUM ? C::TBL : 1];
-    V vals[NUM ? C::TBL : 1];
+    int wpre[C::DENSE ? kDenseRows / 32 : 1];  // occupied rows before each bitmap word
+    int cnt[C::TBL];    // pass 1: products per slot; pass 2: occurrences handed out
+    int rank[C::TBL];   // rank of the slot's row; bit 31 when several products reach it
+    unsigned stamps[C::TBL];
     int scan_tmp[C::T / 64 + 1];
     int stk_lo[40], stk_hi[40];
-    int s_count, s_err;
+    int s_count, s_prod, s_err, s_lcur, s_kmax;
+    long long s_lbase;  // first place of the window's later products in the later list
 };
 
 // exclusive prefix over the workgroup (T threads); contains barriers
@@ -77,10 +85,12 @@ __device__ __forceinline__ int wg_excl_scan(int v, int *tmp, int &total) {
     return ex;
 }
 
-template <typename V, bool NUM, int MODE>
+constexpr int kMulti = (int)0x80000000u;
+
+template <int MODE>
 __global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
     using CF = WinCfg<MODE>;
-    using SM = WinSmem<V, NUM, MODE>;
+    using SM = WinSmem<MODE>;
     constexpr bool DENSE = CF::DENSE;
     constexpr int T = CF::T, PER = CF::PER, CH = T * PER;
     // a stamp is (round << PB) | (CH - 1 - position in chunk)
@@ -108,56 +118,34 @@ __global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
     }
 
     unsigned round = 0;
-    if (NUM) {
-        for (int s = tid; s < CF::TBL; s += T) S.stamps[s] = 0;
-        __syncthreads();
-    }
+    for (int s = tid; s < CF::TBL; s += T) S.stamps[s] = 0;
+    __syncthreads();
 
     for (int li = blockIdx.x; li < nitems; li += gridDim.x) {
         const int it = istart + li;
-        int g, w = 0, W = 1, len;
-        long long lst;
+        int g, w = 0, W = 1;
         if (DENSE) {
             g = a.binlist[dstart + li].x;
-            lst = a.colprod[li];  // dense columns open the list range
-            len = a.op[g];
         } else {
-            const int4 iw = a.items[it];
-            g = iw.x;
-            w = iw.y;
+            g = a.items[it].x;
+            w = it - a.colitem[g];
             W = a.binw[g] >> 8;
-            lst = a.itemstart[it];
-            len = a.itemlen[it];
         }
         const int pid = find_prob(a, g);
         const Prob d = get_prob(a, pid);
-        const int j = g - d.col0;
         const int op = a.op[g];
+        const long long pbase = a.colprod[g];
         const int lo0 = window_lo(w, W, d.m);
         const int hi0 = window_lo(w + 1, W, d.m);
         const int H = DENSE ? 0 : hash_table_size(op, W);
-        const int *__restrict__ lrow = a.lrow + lst;
-        const int2 *__restrict__ lqp = a.lqp + lst;
-        const V *__restrict__ av = (const V *)d.av;
-        const V *__restrict__ bv = (const V *)d.bv;
+        const int *__restrict__ prow = a.prow + pbase;
 
-        long long outpos = 0;
-        int outlen = 0;
-        if (NUM) {
-            outpos = d.ccp[j];
-            outlen = d.ccp[j + 1] - d.ccp[j];
-            if (!DENSE)
-                for (int x = 0; x < w; ++x) {
-                    const int c = a.itemcnt[it - w + x];
-                    outpos += c;
-                    outlen -= c;
-                }
-        }
         int total = 0;
         if (tid == 0) {
             S.stk_lo[0] = lo0;
             S.stk_hi[0] = hi0;
             S.s_err = 0;
+            S.s_kmax = 0;
         }
         int sp = 1;
         __syncthreads();
@@ -173,98 +161,79 @@ __global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
             } else {
                 for (int s = tid; s < nslot; s += T) S.keys[s] = -1;
             }
-            if (NUM)
-                for (int s = tid; s < nslot; s += T) S.vals[s] = V(0);
-            if (tid == 0) S.s_count = 0;
-            if (NUM && round > kRoundLimit) {  // keep the round inside its stamp bits
-                for (int s = tid; s < CF::TBL; s += T) S.stamps[s] = 0;
-                round = 0;
+            for (int s = tid; s < nslot; s += T) S.cnt[s] = 0;
+            if (tid == 0) {
+                S.s_count = 0;
+                S.s_prod = 0;
+                S.s_lcur = 0;
             }
             __syncthreads();
             const float scale = DENSE ? 0.f : (float)H / (float)span;
 
-            int myfail = 0;
-            // products of the chunk starting at c0 (loads in flight)
-            int nrow[PER];
-            int2 nqp[PER];
-            auto fetch = [&](int c0) {
+            // Streams the rows of the column's products (Algorithm 1 order), PER
+            // per thread per chunk, the next chunk's loads in flight; f(u, e, row)
+            // gets every product of the chunk (row -1 past the end), then
+            // done() is called by all threads.
+            auto expand = [&](auto &&f, auto &&done) {
+                int nrow[PER];
 #pragma unroll
-                for (int u = 0; u < PER; ++u) {
-                    const int e = c0 + u * T + tid;
-                    nrow[u] = -1;
-                    if (e < len) {
-                        nrow[u] = lrow[e];
-                        if (NUM) nqp[u] = lqp[e];
+                for (int u = 0; u < PER; ++u) nrow[u] = u * T + tid < op ? prow[u * T + tid] : -1;
+                for (int e0 = 0; e0 < op; e0 += CH) {
+                    int row[PER];
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) {
+                        row[u] = nrow[u];
+                        const int e = e0 + CH + u * T + tid;
+                        nrow[u] = e < op ? prow[e] : -1;
                     }
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) f(u, e0 + u * T + tid, row[u]);
+                    done();
                 }
             };
-            fetch(0);
-            for (int e0 = 0; e0 < len; e0 += CH) {
-                int row[PER];
-                V val[PER];
-#pragma unroll
-                for (int u = 0; u < PER; ++u) {
-                    row[u] = nrow[u];
-                    if (NUM && row[u] >= 0) val[u] = av[nqp[u].x] * bv[nqp[u].y];
-                }
-                if (e0 + CH < len) fetch(e0 + CH);
-                int slot[PER];
-                int nnew = 0;
-#pragma unroll
-                for (int u = 0; u < PER; ++u) {
-                    slot[u] = -1;
-                    const int r = row[u];
-                    if (r < x || r >= y) continue;  // also skips the padding (-1)
+
+            // A window that is the whole column and has not been split records
+            // every product's slot in its destination entry during pass 1;
+            // pass 2 then streams those entries instead of expanding again.
+            const bool flat = W == 1 && x == lo0 && y == hi0;
+
+            // ---- pass 1: insert rows, count products per slot
+            int myfail = 0, nnew = 0, nin = 0;
+            expand(
+                [&](int, int e, int r) {
+                    if (r < x || r >= y) return;  // also skips the padding (-1)
+                    ++nin;
+                    int s;
                     if (DENSE) {
-                        const int sl = r - x;
-                        const unsigned bit = 1u << (sl & 31);
-                        const unsigned old = atomicOr(&S.bitmap[sl >> 5], bit);
+                        s = r - x;
+                        const unsigned bit = 1u << (s & 31);
+                        const unsigned old = atomicOr(&S.bitmap[s >> 5], bit);
                         nnew += !(old & bit);
-                        slot[u] = sl;
+                        atomicAdd(&S.cnt[s], 1);
                     } else {
-                        int s = min((int)((float)(r - x) * scale), H - 1);
+                        s = min((int)((float)(r - x) * scale), H - 1);
                         while (true) {
                             if (s >= nslot) { myfail = 1; break; }
                             int cur = S.keys[s];
                             if (cur == -1) {
                                 cur = atomicCAS(&S.keys[s], -1, r);
-                                if (cur == -1) { ++nnew; slot[u] = s; break; }
+                                if (cur == -1) {
+                                    ++nnew;
+                                    atomicAdd(&S.cnt[s], 1);
+                                    break;
+                                }
                             }
-                            if (cur == r) { slot[u] = s; break; }
+                            if (cur == r) { atomicAdd(&S.cnt[s], 1); break; }
                             ++s;
                         }
                     }
-                }
-                if (!NUM) {
-                    const int c = wave_sum(nnew);
-                    if (lane_id() == 0 && c) atomicAdd(&S.s_count, c);
-                } else {
-                    // ordered accumulation: earliest product of each slot first
-                    bool pend[PER];
-#pragma unroll
-                    for (int u = 0; u < PER; ++u) pend[u] = slot[u] >= 0;
-                    int more;
-                    do {
-                        ++round;
-                        unsigned mine[PER];
-#pragma unroll
-                        for (int u = 0; u < PER; ++u) {
-                            mine[u] = (round << PB) | (unsigned)(CH - 1 - (u * T + tid));
-                            if (pend[u]) atomicMax(&S.stamps[slot[u]], mine[u]);
-                        }
-                        __syncthreads();
-                        bool any = false;
-#pragma unroll
-                        for (int u = 0; u < PER; ++u) {
-                            if (pend[u] && S.stamps[slot[u]] == mine[u]) {
-                                S.vals[slot[u]] = S.vals[slot[u]] + val[u];
-                                pend[u] = false;
-                            }
-                            any = any || pend[u];
-                        }
-                        more = __syncthreads_or(any);
-                    } while (more);
-                }
+                    if (flat) a.dst[pbase + e] = (uint32_t)s;
+                },
+                [&]() {});
+            {
+                const int c = wave_sum(nnew), c2 = wave_sum(nin);
+                if (lane_id() == 0 && c) atomicAdd(&S.s_count, c);
+                if (lane_id() == 0 && c2) atomicAdd(&S.s_prod, c2);
             }
             const bool failed = __syncthreads_or(myfail);
             if (failed) {
@@ -283,86 +252,176 @@ __global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
                 __syncthreads();
                 continue;
             }
-            if (!NUM) {
-                total += S.s_count;
-                continue;
-            }
-            // ---- sort every run of occupied slots (hash only)
-            if (!DENSE) {
-                for (int s0 = tid; s0 < nslot; s0 += T) {
-                    if (S.keys[s0] == -1 || (s0 > 0 && S.keys[s0 - 1] != -1)) continue;
-                    int e = s0 + 1;
-                    while (e < nslot && S.keys[e] != -1) ++e;
-                    for (int u = s0 + 1; u < e; ++u) {
-                        const int ku = S.keys[u];
-                        const V vu = S.vals[u];
-                        int v = u - 1;
-                        while (v >= s0 && S.keys[v] > ku) {
-                            S.keys[v + 1] = S.keys[v];
-                            S.vals[v + 1] = S.vals[v];
-                            --v;
-                        }
-                        S.keys[v + 1] = ku;
-                        S.vals[v + 1] = vu;
+
+            // ---- ranks (bit 31: the slot's row is reached by several products)
+            if (DENSE) {
+                const int nw = ceil_div(span, 32);
+                int tot;
+                const int pc = tid < nw ? __builtin_popcount(S.bitmap[tid]) : 0;
+                const int pre = wg_excl_scan<T>(pc, S.scan_tmp, tot);  // nw <= 128 <= T
+                if (tid < nw) S.wpre[tid] = pre;
+                __syncthreads();
+                for (int sl = tid; sl < span; sl += T) {
+                    const unsigned wd = S.bitmap[sl >> 5];
+                    if ((wd >> (sl & 31)) & 1u) {
+                        const int rk =
+                            S.wpre[sl >> 5] + __builtin_popcount(wd & ((1u << (sl & 31)) - 1u));
+                        S.rank[sl] = rk | (S.cnt[sl] > 1 ? kMulti : 0);
                     }
                 }
-                __syncthreads();
-            }
-            // ---- emit occupied slots in slot order
-            const int per = ceil_div(nslot, T);
-            const int s0 = tid * per, s1 = min(nslot, s0 + per);
-            int mycnt = 0;
-            for (int s = s0; s < s1; ++s) {
-                const bool occ = DENSE ? ((S.bitmap[s >> 5] >> (s & 31)) & 1u) : (S.keys[s] != -1);
-                mycnt += occ;
-            }
-            int tot;
-            int pos = wg_excl_scan<T>(mycnt, S.scan_tmp, tot);
-            if (total + tot > outlen) {
-                if (tid == 0) S.s_err = ERR_GROUP;
             } else {
-                for (int s = s0; s < s1; ++s) {
-                    const bool occ =
-                        DENSE ? ((S.bitmap[s >> 5] >> (s & 31)) & 1u) : (S.keys[s] != -1);
-                    if (!occ) continue;
-                    const long long o = outpos + total + pos;
-                    d.cri[o] = DENSE ? x + s : S.keys[s];
-                    ((V *)d.cv)[o] = S.vals[s];
-                    ++pos;
+                // The table is ascending run by run: a row's rank is the number
+                // of occupied slots before its run plus the rows of its run
+                // that are smaller. Keys stay in place (pass 1 slots remain valid).
+                const int per = ceil_div(nslot, T);
+                const int s0 = tid * per, s1 = min(nslot, s0 + per);
+                int mycnt = 0;
+                for (int sl = s0; sl < s1; ++sl) mycnt += S.keys[sl] != -1;
+                int tot;
+                int run = wg_excl_scan<T>(mycnt, S.scan_tmp, tot);
+                int cs = -1, ce = -1;  // bounds of the current run of occupied slots
+                for (int sl = s0; sl < s1; ++sl) {
+                    const int ks = S.keys[sl];
+                    if (ks == -1) { cs = -1; continue; }
+                    if (cs < 0) {
+                        cs = sl;
+                        while (cs > 0 && S.keys[cs - 1] != -1) --cs;
+                        ce = sl + 1;
+                        while (ce < nslot && S.keys[ce] != -1) ++ce;
+                    }
+                    int less = 0;
+                    for (int t = cs; t < ce; ++t) less += S.keys[t] < ks;
+                    S.rank[sl] = (run - (sl - cs) + less) | (S.cnt[sl] > 1 ? kMulti : 0);
+                    ++run;
                 }
             }
-            total += tot;
+            // later products of this window: one reservation in the later list
+            if (tid == 0 && S.s_prod > S.s_count)
+                S.s_lbase = (long long)atomicAdd(&a.hdr->later_count,
+                                                 (unsigned long long)(S.s_prod - S.s_count));
             __syncthreads();
+            for (int sl = tid; sl < nslot; sl += T) S.cnt[sl] = 0;
+            __syncthreads();
+
+            // ---- pass 2: destinations
+            int slot[PER], rk[PER];
+            bool pend[PER];
+            long long eg[PER];
+            int myerr = 0;
+            // resolves one product given its slot (or -1)
+            auto settle = [&](int u, long long e, int sl) {
+                slot[u] = -1;
+                pend[u] = false;
+                if (sl < 0) return;
+                const int v = S.rank[sl];
+                eg[u] = e;
+                rk[u] = total + (v & 0x7fffffff);
+                if (v & kMulti) {
+                    slot[u] = sl;
+                    pend[u] = true;
+                } else {
+                    a.dst[e] = (uint32_t)rk[u];
+                }
+            };
+            // occurrence indices of products sharing a slot, in list order
+            auto order = [&]() {
+                bool any = false;
+#pragma unroll
+                for (int u = 0; u < PER; ++u) any = any || pend[u];
+                if (!__syncthreads_or(any)) return;
+                if (round + CH + 1 > kRoundLimit) {  // keep rounds inside their stamp bits
+                    for (int sl = tid; sl < CF::TBL; sl += T) S.stamps[sl] = 0;
+                    round = 0;
+                    __syncthreads();
+                }
+                int more;
+                do {
+                    ++round;
+                    unsigned mine[PER];
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) {
+                        mine[u] = (round << PB) | (unsigned)(CH - 1 - (u * T + tid));
+                        if (pend[u]) atomicMax(&S.stamps[slot[u]], mine[u]);
+                    }
+                    __syncthreads();
+                    bool left = false;
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) {
+                        if (pend[u] && S.stamps[slot[u]] == mine[u]) {
+                            const int k = S.cnt[slot[u]];
+                            S.cnt[slot[u]] = k + 1;
+                            if (k == 0) {
+                                a.dst[eg[u]] = (uint32_t)rk[u];
+                            } else {
+                                const long long lix = S.s_lbase + atomicAdd(&S.s_lcur, 1);
+                                if (lix < a.later_cap) {
+                                    a.dst[eg[u]] = kDstLater | (uint32_t)lix;
+                                    a.lk[lix] = k;
+                                    a.lr[lix] = rk[u];
+                                    atomicMax(&S.s_kmax, k);
+                                } else {
+                                    myerr = ERR_GROUP;
+                                }
+                            }
+                            pend[u] = false;
+                        }
+                        left = left || pend[u];
+                    }
+                    more = __syncthreads_or(left);
+                } while (more);
+            };
+            if (flat) {
+                // every product of the column is in this window: stream the slots
+                for (int e0 = 0; e0 < op; e0 += CH) {
+                    int sl[PER];
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) {
+                        const int e = e0 + u * T + tid;
+                        sl[u] = e < op ? (int)a.dst[pbase + e] : -1;
+                        if (sl[u] >= nslot) { myerr = ERR_GROUP; sl[u] = -1; }  // cannot happen
+                    }
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) settle(u, pbase + e0 + u * T + tid, sl[u]);
+                    order();
+                }
+            } else {
+                expand(
+                    [&](int u, int e, int r) {
+                        int sl = -1;
+                        if (r >= x && r < y) {
+                            if (DENSE) {
+                                sl = r - x;
+                            } else {
+                                sl = min((int)((float)(r - x) * scale), H - 1);
+                                while (sl < nslot && S.keys[sl] != r) ++sl;
+                                if (sl >= nslot) { myerr = ERR_GROUP; sl = -1; }  // cannot happen
+                            }
+                        }
+                        settle(u, pbase + e, sl);
+                    },
+                    order);
+            }
+            if (myerr) S.s_err = myerr;
+            __syncthreads();
+            total += S.s_count;
         }
         if (tid == 0) {
             if (S.s_err) atomicOr(&a.hdr->err, S.s_err);
-            if (!NUM) {
-                if (!DENSE) a.itemcnt[it] = total;
-                atomicAdd(&a.gnnz[g], total);
-            }
+            if (S.s_kmax) atomicMax(&a.hdr->later_maxk, S.s_kmax);
+            if (!DENSE) a.itemcnt[it] = total;
+            atomicAdd(&a.gnnz[g], total);
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_window(const KArgs &a, bool numeric, bool f64, int mode, int grid,
-                         hipStream_t s) {
+hipError_t launch_window(const KArgs &a, int mode, int grid, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
-#define SPG_LAUNCH(V, N, M) \
-    hipLaunchKernelGGL((k_window<V, N, M>), dim3(grid), dim3(WinCfg<M>::T), 0, s, a)
-#define SPG_MODES(V, N)                                                \
-    do {                                                               \
-        if (mode == WIN_DENSE) SPG_LAUNCH(V, N, WIN_DENSE);            \
-        else if (mode == WIN_HASH_S) SPG_LAUNCH(V, N, WIN_HASH_S);     \
-        else if (mode == WIN_HASH_L) SPG_LAUNCH(V, N, WIN_HASH_L);     \
-        else SPG_LAUNCH(V, N, WIN_HASH_XL);                            \
-    } while (0)
-    if (f64) {
-        if (numeric) SPG_MODES(double, true); else SPG_MODES(double, false);
-    } else {
-        if (numeric) SPG_MODES(float, true); else SPG_MODES(float, false);
-    }
-#undef SPG_MODES
+#define SPG_LAUNCH(M) hipLaunchKernelGGL((k_window<M>), dim3(grid), dim3(WinCfg<M>::T), 0, s, a)
+    if (mode == WIN_DENSE) SPG_LAUNCH(WIN_DENSE);
+    else if (mode == WIN_HASH_S) SPG_LAUNCH(WIN_HASH_S);
+    else if (mode == WIN_HASH_L) SPG_LAUNCH(WIN_HASH_L);
+    else SPG_LAUNCH(WIN_HASH_XL);
 #undef SPG_LAUNCH
     return hipGetLastError();
 }

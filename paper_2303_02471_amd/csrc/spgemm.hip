@@ -2,9 +2,12 @@
 // workspace, and the launch sequence of every phase.
 //
 // Symbolic:  classify (Op_j, accumulator bin) -> place (bin lists) ->
-//            ESC / dense / hash counts of distinct rows -> prefix scan into
-//            the column pointers -> one device-to-host copy of the totals.
-// Numeric:   ESC, dense and hash accumulators write rows and values.
+//            product-space offsets -> expansion (row of every product) ->
+//            ESC / dense / hash: distinct rows per column and the destination
+//            of every product -> window offsets -> prefix scan into the column
+//            pointers -> one device-to-host copy of the totals.
+// Numeric:   every product formed and written or staged through its
+//            destination, then the staged later products added in order.
 // Backward:  row view of B (once per plan) -> sampled products for dB, dA.
 #include <hip/hip_runtime.h>
 
@@ -40,14 +43,22 @@ struct spgemm_plan_s {
     int4 *binlist = nullptr, *items = nullptr;
     int2 *E = nullptr;
     long long total_nnzb = 0;
-    long long *colprod = nullptr, *itemstart = nullptr;
-    int32_t *colitem = nullptr, *itemlen = nullptr;
-    // product lists of the dense and hash columns (own allocation: its size is
-    // known only after the classification)
-    void *lists = nullptr;
-    size_t lists_bytes = 0;
-    int32_t *lrow = nullptr;
-    int2 *lqp = nullptr;
+    long long *colprod = nullptr;
+    int32_t *colitem = nullptr, *itemoff = nullptr;
+    // per-product arrays (own allocation: the product count is known only
+    // after the classification): row and destination of every product, and
+    // the later list's occurrence indices and ranks
+    void *prod = nullptr;
+    size_t prod_bytes = 0;
+    int32_t *prow = nullptr;
+    uint32_t *dst = nullptr;
+    int32_t *lk = nullptr, *lr = nullptr;
+    long long later_cap = 0;
+    // staging of the later products for the numeric phase (sized by their count)
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+    int32_t *lo = nullptr, *lpid = nullptr;
+    void *lv = nullptr;
     long long *gcp = nullptr, *bsum = nullptr, *totals = nullptr;
     Prob *table = nullptr;
     int4 *tiles = nullptr;
@@ -68,7 +79,6 @@ struct spgemm_plan_s {
     static constexpr int kSide = 3;
     hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[kSide] = {nullptr, nullptr, nullptr};
-    hipEvent_t list_ev = nullptr;
 
     // backward: row view of B
     void *bt = nullptr;
@@ -196,8 +206,8 @@ spgemm_status ensure_workspace(spgemm_plan p) {
                  o_gnnz = take(4 * n);
     const size_t o_items = take(16 * (size_t)p->item_cap);
     const size_t o_E = take(8 * (size_t)std::max(p->total_nnzb, 1ll));
-    const size_t o_colprod = take(8 * n), o_colitem = take(4 * n);
-    const size_t o_istart = take(8 * (size_t)p->item_cap), o_ilen = take(4 * (size_t)p->item_cap);
+    const size_t o_colprod = take(8 * (n + 1)), o_colitem = take(4 * n);
+    const size_t o_ioff = take(4 * (size_t)p->item_cap);
     const size_t o_item = take(4 * (size_t)p->item_cap);
     const size_t o_gcp = take(8 * (n + 1));
     const size_t o_bsum = take(8 * (size_t)p->nbsum);
@@ -227,8 +237,7 @@ spgemm_status ensure_workspace(spgemm_plan p) {
     p->E = (int2 *)(b + o_E);
     p->colprod = (long long *)(b + o_colprod);
     p->colitem = (int32_t *)(b + o_colitem);
-    p->itemstart = (long long *)(b + o_istart);
-    p->itemlen = (int32_t *)(b + o_ilen);
+    p->itemoff = (int32_t *)(b + o_ioff);
     p->itemcnt = (int32_t *)(b + o_item);
     p->gcp = (long long *)(b + o_gcp);
     p->bsum = (long long *)(b + o_bsum);
@@ -268,11 +277,16 @@ KArgs make_args(spgemm_plan p) {
     a.E = p->E;
     a.colprod = p->colprod;
     a.colitem = p->colitem;
-    a.itemstart = p->itemstart;
-    a.itemlen = p->itemlen;
-    a.lrow = p->lrow;
-    a.lqp = p->lqp;
+    a.itemoff = p->itemoff;
     a.itemcnt = p->itemcnt;
+    a.prow = p->prow;
+    a.dst = p->dst;
+    a.later_cap = p->later_cap;
+    a.lk = p->lk;
+    a.lr = p->lr;
+    a.lo = p->lo;
+    a.lpid = p->lpid;
+    a.lv = p->lv;
     return a;
 }
 
@@ -304,57 +318,86 @@ hipError_t ensure_side_streams(spgemm_plan p) {
         if ((e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking))) return e;
         if ((e = hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming))) return e;
     }
-    if ((e = hipEventCreateWithFlags(&p->list_ev, hipEventDisableTiming))) return e;
     return hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
 }
 
-hipError_t launch_accumulators(spgemm_plan p, const KArgs &a, bool numeric, hipStream_t s) {
-    const bool f64 = p->dt == SPGEMM_F64;
-    const Hdr &h = p->hdr_host;
-    static const char *names[2][5] = {
-        {"esc_symbolic", "dense_symbolic", "hash_s_symbolic", "hash_l_symbolic", "hash_xl_symbolic"},
-        {"esc_numeric", "dense_numeric", "hash_s_numeric", "hash_l_numeric", "hash_xl_numeric"}};
-    const char *const *nm = names[numeric ? 1 : 0];
-    // The accumulator kinds work on disjoint columns: the sort-merge groups
-    // run on the caller's stream, dense + small hash, large hash and
-    // extra-large hash on three side streams, so their memory latencies overlap.
+// bin-list positions of the dense and hash columns
+void list_range(const Hdr &h, int &first, int &n, int &first_hash, int &nhash) {
+    first = 0;
+    for (int b = 0; b < BIN_DENSE; ++b) first += h.bin_count[b];
+    first_hash = first + h.bin_count[BIN_DENSE];
+    nhash = 0;
+    for (int b = BIN_HASH_S; b < NBINS; ++b) nhash += h.bin_count[b];
+    n = h.bin_count[BIN_DENSE] + nhash;
+}
+
+// side stream i, or the caller's stream when every kind runs on it
+hipStream_t side(spgemm_plan p, int i, hipStream_t s) {
+    return (p->flags & SPGEMM_ONE_STREAM) ? s : p->side[i];
+}
+
+hipError_t fork(spgemm_plan p, hipStream_t s) {
+    if (p->flags & SPGEMM_ONE_STREAM) return hipSuccess;
     hipError_t e;
     if ((e = hipEventRecord(p->fork_ev, s))) return e;
     for (int i = 0; i < spgemm_plan_s::kSide; ++i)
         if ((e = hipStreamWaitEvent(p->side[i], p->fork_ev, 0))) return e;
-    if (!numeric) {
-        // product lists first (side stream 0); the other side streams wait
-        int first = 0, nlist = 0;
-        for (int b = 0; b < BIN_DENSE; ++b) first += h.bin_count[b];
-        for (int b = BIN_DENSE; b < NBINS; ++b) nlist += h.bin_count[b];
-        {
-            ProfScope ps("lists", p->side[0]);
-            if ((e = launch_lists(a, first, nlist, p->itemcnt, p->bsum, p->nbsum, p->side[0])))
-                return e;
-        }
-        if ((e = hipEventRecord(p->list_ev, p->side[0]))) return e;
-        for (int i = 1; i < spgemm_plan_s::kSide; ++i)
-            if ((e = hipStreamWaitEvent(p->side[i], p->list_ev, 0))) return e;
-    }
-    {
-        ProfScope ps(nm[0], s);
-        if ((e = launch_esc(a, numeric, f64, ceil_div(esc_groups(h), kBlock / 64), s))) return e;
-    }
-    {
-        ProfScope ps(nm[1], p->side[0]);
-        if ((e = launch_window(a, numeric, f64, WIN_DENSE, h.bin_count[BIN_DENSE], p->side[0])))
-            return e;
-    }
-    for (int c = 0; c < kHashBins; ++c) {
-        if (!h.item_count[c]) continue;
-        hipStream_t sc = p->side[c];
-        ProfScope ps(nm[2 + c], sc);
-        if ((e = launch_window(a, numeric, f64, WIN_HASH_S + c, h.item_count[c], sc))) return e;
-    }
+    return hipSuccess;
+}
+
+hipError_t join(spgemm_plan p, hipStream_t s) {
+    if (p->flags & SPGEMM_ONE_STREAM) return hipSuccess;
+    hipError_t e;
     for (int i = 0; i < spgemm_plan_s::kSide; ++i) {
         if ((e = hipEventRecord(p->join_ev[i], p->side[i]))) return e;
         if ((e = hipStreamWaitEvent(s, p->join_ev[i], 0))) return e;
     }
+    return hipSuccess;
+}
+
+// Symbolic accumulators. The kinds work on disjoint columns: the sort-merge
+// groups run on the caller's stream, dense + small hash, large hash and
+// extra-large hash on three side streams, so their latencies overlap.
+hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream_t s) {
+    const Hdr &h = p->hdr_host;
+    hipError_t e;
+    if ((e = fork(p, s))) return e;
+    {
+        ProfScope ps("esc_symbolic", s);
+        if ((e = launch_esc(a, ceil_div(esc_groups(h), kBlock / 64), s))) return e;
+    }
+    {
+        ProfScope ps("dense_symbolic", side(p, 0, s));
+        if ((e = launch_window(a, WIN_DENSE, h.bin_count[BIN_DENSE], side(p, 0, s)))) return e;
+    }
+    static const char *names[kHashBins] = {"hash_s_symbolic", "hash_l_symbolic",
+                                           "hash_xl_symbolic"};
+    for (int c = 0; c < kHashBins; ++c) {
+        if (!h.item_count[c]) continue;
+        ProfScope ps(names[c], side(p, c, s));
+        if ((e = launch_window(a, WIN_HASH_S + c, h.item_count[c], side(p, c, s)))) return e;
+    }
+    if ((e = join(p, s))) return e;
+    int first, n, first_hash, nhash;
+    list_range(h, first, n, first_hash, nhash);
+    ProfScope ps("window_offsets", s);
+    return launch_item_offsets(a, first_hash, nhash, s);
+}
+
+// Numeric: one launch over the column tiles, then one small launch per
+// occurrence index of the later products.
+hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
+    const bool f64 = p->dt == SPGEMM_F64;
+    const Hdr &h = p->hdr_host;
+    hipError_t e;
+    {
+        ProfScope ps("numeric", s);
+        if ((e = launch_numeric(a, f64, s))) return e;
+    }
+    if (h.later_count == 0) return hipSuccess;
+    ProfScope ps("later_layers", s);
+    for (int k = 1; k <= h.later_maxk; ++k)
+        if ((e = launch_layer(a, f64, k, (long long)h.later_count, s))) return e;
     return hipSuccess;
 }
 
@@ -378,6 +421,11 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         const KArgs a = make_args(p);
         { ProfScope ps("classify", s); SPG_TRY(launch_classify(a, s)); }
         { ProfScope ps("place", s); SPG_TRY(launch_place(a, s)); }
+        {
+            // first product of every column: exclusive scan of Op_j
+            ProfScope ps("product_offsets", s);
+            SPG_TRY(launch_scan_i64(p->op, p->ncols, p->bsum, p->nbsum, p->colprod, s));
+        }
         // the bin sizes fix the grid of every accumulator launch: read them once
         SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, sizeof(Hdr), hipMemcpyDeviceToHost, s));
         SPG_TRY(hipStreamSynchronize(s));
@@ -392,21 +440,28 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         }
         if (err & ERR_CSC) return SPGEMM_ERR_CSC;
         if (err & ERR_OPOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
-        // product lists of the dense and hash columns
-        const size_t L = (size_t)p->hdr_host.list_products;
-        const size_t lneed = align_up(4 * std::max<size_t>(L, 1), 256) + 8 * std::max<size_t>(L, 1);
-        if (lneed > p->lists_bytes) {
-            if (p->lists) (void)hipFree(p->lists);
-            p->lists = nullptr;
-            p->lists_bytes = 0;
-            if (hipMalloc(&p->lists, lneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
-            p->lists_bytes = lneed;
+        // per-product arrays
+        const Hdr &hh = p->hdr_host;
+        const size_t P = (size_t)std::max<unsigned long long>(hh.total_op, 1);
+        const size_t q1 = align_up(4 * P, 256);
+        const size_t pneed = 4 * q1;
+        if (pneed > p->prod_bytes) {
+            if (p->prod) (void)hipFree(p->prod);
+            p->prod = nullptr;
+            p->prod_bytes = 0;
+            if (hipMalloc(&p->prod, pneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
+            p->prod_bytes = pneed;
         }
-        p->lrow = (int32_t *)p->lists;
-        p->lqp = (int2 *)((char *)p->lists + align_up(4 * std::max<size_t>(L, 1), 256));
+        p->prow = (int32_t *)p->prod;
+        p->dst = (uint32_t *)((char *)p->prod + q1);
+        p->lk = (int32_t *)((char *)p->prod + 2 * q1);
+        p->lr = (int32_t *)((char *)p->prod + 3 * q1);
+        // later places are 31-bit indices
+        p->later_cap = (long long)std::min<size_t>(P, 0x7fffffff);
         if (p->ncols > 0) {
             const KArgs al = make_args(p);
-            SPG_TRY(launch_accumulators(p, al, false, s));
+            { ProfScope ps("expand", s); SPG_TRY(launch_expand(al, s)); }
+            SPG_TRY(launch_symbolic_accumulators(p, al, s));
             ProfScope ps("scan", s);
             SPG_TRY(launch_scan(a, p->gcp, p->bsum, p->nblk, p->totals, s));
         }
@@ -422,6 +477,21 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         err = p->hdr_host.err;
         if (err & (ERR_CSC | ERR_GROUP)) return SPGEMM_ERR_CSC;
         if (err & (ERR_OPOVF | ERR_NNZOVF)) return SPGEMM_ERR_INDEX_OVERFLOW;
+        // staging of the later products
+        const size_t NL = (size_t)std::max<unsigned long long>(p->hdr_host.later_count, 1);
+        const size_t vsz = p->dt == SPGEMM_F64 ? 8 : 4;
+        const size_t o_pid = align_up(4 * NL, 256), o_v = o_pid + align_up(4 * NL, 256);
+        const size_t sneed = o_v + vsz * NL;
+        if (sneed > p->stage_bytes) {
+            if (p->stage) (void)hipFree(p->stage);
+            p->stage = nullptr;
+            p->stage_bytes = 0;
+            if (hipMalloc(&p->stage, sneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
+            p->stage_bytes = sneed;
+        }
+        p->lo = (int32_t *)p->stage;
+        p->lpid = (int32_t *)((char *)p->stage + o_pid);
+        p->lv = (char *)p->stage + o_v;
         if (p->ncols == 0) {
             // no columns at all: every problem's column pointer is {0}
             for (int i = 0; i < p->nprob; ++i)
@@ -436,7 +506,7 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
 
 spgemm_status run_numeric(spgemm_plan p, hipStream_t s) {
     const KArgs a = make_args(p);
-    SPG_TRY(launch_accumulators(p, a, true, s));
+    SPG_TRY(launch_numeric_phase(p, a, s));
     p->last_stream = s;
     return SPGEMM_OK;
 }
@@ -730,8 +800,8 @@ void spgemm_plan_destroy(spgemm_plan p) {
         if (p->join_ev[i]) (void)hipEventDestroy(p->join_ev[i]);
     }
     if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
-    if (p->list_ev) (void)hipEventDestroy(p->list_ev);
-    if (p->lists) (void)hipFree(p->lists);
+    if (p->prod) (void)hipFree(p->prod);
+    if (p->stage) (void)hipFree(p->stage);
     if (p->ws) (void)hipFree(p->ws);
     if (p->bt) (void)hipFree(p->bt);
     if (p->pinned) (void)hipHostFree(p->pinned);
