@@ -74,7 +74,8 @@ def csc_bytes(n, nnz, vb):
     return 4 * (n + 1) + (4 + vb) * nnz
 
 
-def per_column_work(A, B, m_dense_limit=4096, t_esc=256, t_dense=512, hash_cap=4096):
+def per_column_work(A, B, m_dense_limit=4096, t_esc=256, t_dense=512, hash_cap=4096,
+                    t_sort=4096):
     """Host accounting of the per-column work and of the accumulator each
     column goes to (the library's default rule), for algorithmic byte counts."""
     import numpy as np
@@ -82,16 +83,20 @@ def per_column_work(A, B, m_dense_limit=4096, t_esc=256, t_dense=512, hash_cap=4
     nb = np.diff(B.colptr.astype(np.int64))
     colB = np.repeat(np.arange(B.ncols), nb)
     op = np.bincount(colB, weights=za[B.rowidx], minlength=B.ncols).astype(np.int64)
-    w = np.maximum(op, nb)
-    esc = (op > 0) & (w <= t_esc)
+    esc = (op > 0) & (op <= t_esc)
     dense = (op > 0) & ~esc & (A.nrows <= m_dense_limit) & (op >= t_dense)
-    hsh = (op > 0) & ~esc & ~dense
+    srt = (op > 0) & ~esc & ~dense & (op <= t_sort)
+    hsh = (op > 0) & ~esc & ~dense & ~srt
+    # workgroup sort class: N = power of two >= op, at least 512
+    N = 2 ** np.ceil(np.log2(np.maximum(op, 512)))
     # hash table class: windows W = ceil(op / cap); table = power of two
     # >= 2 ceil(op / W), in [64, 8192]; classes <= 1024, <= 4096, larger
     W = np.maximum(1, -(-op // hash_cap))
     per = -(-op // W)
     H = np.clip(2 ** np.ceil(np.log2(np.maximum(2 * per, 1))), 64, 8192)
     return op, nb, {"esc": esc, "dense": dense,
+                    "sort512": srt & (N == 512), "sort1k": srt & (N == 1024),
+                    "sort2k": srt & (N == 2048), "sort4k": srt & (N == 4096),
                     "hash_s": hsh & (H <= 1024), "hash_l": hsh & (H > 1024) & (H <= 4096),
                     "hash_xl": hsh & (H > 4096)}
 

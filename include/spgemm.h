@@ -89,9 +89,9 @@ typedef struct spgemm_plan_s *spgemm_plan;
  * accumulator handles a column (the role of the paper's switch threshold t,
  * Section 3.3, and of its hash-size adaptation, Section 3.2). A zero field
  * takes the library default.
- *   t_esc       columns with at most this many products (and stored B
- *               entries) go to the wavefront sort-merge (ESC, Section 4)
- *               accumulator; 4..256, rounded up to a power of two; default 256.
+ *   t_esc       columns with at most this many products go to the wavefront
+ *               sort-merge (ESC, Section 4) accumulator; 4..256, rounded up
+ *               to a power of two; default 256.
  *   t_dense     columns above t_esc with at least this many products go to
  *               the dense LDS accumulator (SPA, Section 2.2) when A has at
  *               most dense_rows rows; default 512.
@@ -99,6 +99,10 @@ typedef struct spgemm_plan_s *spgemm_plan;
  *   hash_cap    planned distinct rows per LDS hash-table window, 128..4096;
  *               default 4096. Columns with more products are split into
  *               row windows.
+ *   t_sort      the remaining columns with at most this many products go to
+ *               the workgroup sort-merge accumulator, the others to the hash
+ *               accumulator (HASH, Section 3.2); -1 (none) or 1..4096;
+ *               default 4096.
  */
 typedef struct {
     int32_t t_esc;
@@ -106,6 +110,7 @@ typedef struct {
     int32_t dense_rows;
     int32_t hash_cap;
     uint32_t flags;
+    int32_t t_sort;
 } spgemm_options;
 
 /* Work statistics of a plan, for reports and tests. */
@@ -120,6 +125,9 @@ typedef struct {
     int32_t hash_items;         /* row windows of hash columns */
     int32_t esc_groups;         /* wavefront groups of sort-merge columns */
     int32_t nprob;              /* problems in the plan */
+    int32_t cols_sort;          /* columns in the workgroup sort-merge accumulator */
+    int32_t later_max;          /* most products adding into one output entry, minus 1 */
+    int64_t later_products;     /* products that are not the first of their output entry */
 } spgemm_plan_stats;
 
 /*

@@ -10,28 +10,33 @@ namespace spg {
 constexpr int kWave = 64;
 
 // ---------------------------------------------------------------- bins
-// A column's accumulator is chosen from its product count Op_j (Section 3.1)
-// and its number of stored B entries nB_j:
+// A column's accumulator is chosen from its product count Op_j (Section 3.1):
 //   EMPTY      Op_j == 0: no output entries
-//   ESC_i      max(Op_j, nB_j) <= 4 << i: wavefront sort-merge (Section 4),
-//              64 >> i columns per wavefront group (at most 256 products)
+//   ESC_i      Op_j <= 4 << i: wavefront sort-merge (Section 4), 64 >> i
+//              columns per wavefront group (at most 256 products)
+//   SORT_i     Op_j <= 512 << i (and <= t_sort): workgroup sort-merge, one
+//              column per workgroup of 128 << i threads
 //   DENSE      dense LDS accumulator over all rows (SPA, Section 2.2)
-//   HASH_S/L   LDS hash table per row window (HASH, Section 3.2); the two
-//              bins differ only in the largest table they hold, so the small
-//              one runs with a small LDS footprint (more workgroups per CU)
+//   HASH_S/L/XL LDS hash table per row window (HASH, Section 3.2); the bins
+//              differ only in the largest table they hold, so the smaller ones
+//              run with a smaller LDS footprint (more workgroups per CU)
 enum Bin : int {
     BIN_EMPTY = 0,
-    BIN_ESC0 = 1,  // w <= 4
-    BIN_ESC6 = 7,  // w <= 256
-    BIN_DENSE = 8,
-    BIN_HASH_S = 9,
-    BIN_HASH_L = 10,
-    BIN_HASH_XL = 11,
-    NBINS = 12
+    BIN_ESC0 = 1,  // Op <= 4
+    BIN_ESC6 = 7,  // Op <= 256
+    BIN_SORT0 = 8, // Op <= 512
+    BIN_SORT3 = 11, // Op <= 4096
+    BIN_DENSE = 12,
+    BIN_HASH_S = 13,
+    BIN_HASH_L = 14,
+    BIN_HASH_XL = 15,
+    NBINS = 16
 };
 constexpr int kHashBins = 3;
 constexpr int kEscBins = 7;
-constexpr int kEscMaxProducts = 256;  // products and B entries per wavefront group
+constexpr int kSortBins = 4;
+constexpr int kSortMax = 4096;        // products per workgroup sort
+constexpr int kEscMaxProducts = 256;  // products per wavefront group
 
 // dense accumulator: rows per LDS slice
 constexpr int kDenseRows = 4096;
@@ -92,6 +97,7 @@ struct Hdr {
 // Resolved tuning values.
 struct Tune {
     int32_t esc_bins;   // number of ESC sub-bins in use, 1..7 (t_esc = 4 << (esc_bins-1))
+    int32_t t_sort;     // largest product count of a workgroup-sort column (<= kSortMax)
     int32_t t_dense;
     int32_t dense_rows;
     int32_t hash_cap;
@@ -196,6 +202,8 @@ __host__ __device__ inline int hash_table_size(int op, int windows) {
 hipError_t launch_classify(const KArgs &a, hipStream_t s);
 hipError_t launch_place(const KArgs &a, hipStream_t s);
 hipError_t launch_esc(const KArgs &a, int grid, hipStream_t s);
+// workgroup sort of sort bin `cls`; wide: 64-bit keys (rows beyond 20 bits)
+hipError_t launch_sort(const KArgs &a, int cls, bool wide, int grid, hipStream_t s);
 // mode: dense, or one of the three hash table classes
 enum WinMode : int { WIN_DENSE = 0, WIN_HASH_S = 1, WIN_HASH_L = 2, WIN_HASH_XL = 3 };
 hipError_t launch_window(const KArgs &a, int mode, int grid, hipStream_t s);

@@ -108,15 +108,14 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     for (int c = tid; c < nt; c += kBlock) {
         const int g = d.col0 + j0 + c;
         unsigned long long op64 = s_op[c];
-        const int nb = s_bcp[c + 1] - s_bcp[c];
         if (op64 > 0x7fffffffull) { err = ERR_OPOVF; op64 = 0x7fffffffull; }
         tot += op64;
         const int op = (int)op64;
-        const int w = max(op, nb);
         int bin, W = 0;
         if (op == 0) bin = BIN_EMPTY;
-        else if (w <= esc_max) bin = BIN_ESC0 + max(ceil_log2(w), 2) - 2;
+        else if (op <= esc_max) bin = BIN_ESC0 + max(ceil_log2(op), 2) - 2;
         else if (d.m <= a.tune.dense_rows && op >= a.tune.t_dense) bin = BIN_DENSE;
+        else if (op <= a.tune.t_sort) bin = BIN_SORT0 + max(ceil_log2(op), 9) - 9;
         else {
             W = hash_windows(op, a.tune.hash_cap);
             bin = BIN_HASH_S + hash_class(hash_table_size(op, W));

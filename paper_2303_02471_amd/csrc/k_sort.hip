@@ -1,0 +1,237 @@
+// Block sort accumulator for medium columns (more products than the
+// wavefront sort-merge takes, at most 4096): the expand-sort-compress
+// scheme of Section 4 at workgroup scale, one workgroup per column.
+//
+// The workgroup reads the rows of the column's products from the product
+// space (Algorithm 1 order), forms the keys (row, e) with e the position in
+// that order, and sorts them with a bitonic network: exchanges at distance
+// below 64 move through DPP / ds_swizzle / ds_bpermute, distances 64..128
+// between the four registers a lane holds, and larger distances through LDS.
+// Every run of equal rows is one output entry; its rank is the run index and
+// the position of a key inside its run is the occurrence index k of that
+// product. The first product of a run gets the rank as its destination; the
+// others get places in the later-product list.
+//
+// Keys are 32-bit when the rows fit in 20 bits (row << 12 | e), else 64-bit.
+#include "devutil.h"
+
+namespace spg {
+
+template <typename K>
+struct KeyMax;
+template <>
+struct KeyMax<unsigned> {
+    static constexpr unsigned v = ~0u;
+};
+template <>
+struct KeyMax<unsigned long long> {
+    static constexpr unsigned long long v = ~0ull;
+};
+
+template <int J>
+__device__ __forceinline__ unsigned xshfl(unsigned v) {
+    return (unsigned)shfl_xor_c<J>((int)v);
+}
+template <int J>
+__device__ __forceinline__ unsigned long long xshfl(unsigned long long v) {
+    return shfl_xor_c64<J>(v);
+}
+
+// key[r] of lane l sits at position sb + 64 r + l. A position takes the
+// smaller key of its pair when (ascending block) == (lower element).
+template <typename K, int J>
+__device__ __forceinline__ void lane_step(K (&key)[4], int k, int sb, int lane) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int s = sb + r * 64 + lane;
+        const K o = xshfl<J>(key[r]);
+        const bool take_min = ((s & k) == 0) == ((lane & J) == 0);
+        const K mn = key[r] < o ? key[r] : o;
+        const K mx = key[r] < o ? o : key[r];
+        key[r] = take_min ? mn : mx;
+    }
+}
+
+template <typename K>
+__device__ __forceinline__ void reg_step(K (&key)[4], int k, int j, int sb, int lane) {
+    const int jr = j >> 6;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int rp = r ^ jr;
+        if (rp > r) {
+            const int s = sb + r * 64 + lane;
+            const bool asc = (s & k) == 0;
+            const K x = key[r], y = key[rp];
+            const bool sw = asc ? (x > y) : (x < y);
+            key[r] = sw ? y : x;
+            key[rp] = sw ? x : y;
+        }
+    }
+}
+
+// partner in another wavefront's 256 positions: exchange through LDS
+template <typename K>
+__device__ __forceinline__ void lds_step(K (&key)[4], K *buf, int k, int j, int sb, int lane) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) buf[sb + r * 64 + lane] = key[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int s = sb + r * 64 + lane;
+        const K o = buf[s ^ j];
+        const bool take_min = ((s & k) == 0) == ((s & j) == 0);
+        const K mn = key[r] < o ? key[r] : o;
+        const K mx = key[r] < o ? o : key[r];
+        key[r] = take_min ? mn : mx;
+    }
+    __syncthreads();
+}
+
+// ascending sort of the workgroup's N = 4 * threads keys
+template <typename K, int N>
+__device__ __forceinline__ void block_sort(K (&key)[4], K *buf) {
+    const int lane = lane_id(), sb = (threadIdx.x >> 6) * 256;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 256) {
+                lds_step(key, buf, k, j, sb, lane);
+            } else if (j >= 64) {
+                reg_step(key, k, j, sb, lane);
+            } else {
+                switch (j) {
+                    case 32: lane_step<K, 32>(key, k, sb, lane); break;
+                    case 16: lane_step<K, 16>(key, k, sb, lane); break;
+                    case 8: lane_step<K, 8>(key, k, sb, lane); break;
+                    case 4: lane_step<K, 4>(key, k, sb, lane); break;
+                    case 2: lane_step<K, 2>(key, k, sb, lane); break;
+                    default: lane_step<K, 1>(key, k, sb, lane); break;
+                }
+            }
+        }
+    }
+}
+
+template <typename K, int T>
+__global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
+    constexpr int N = 4 * T, NW = T / 64;
+    constexpr int EB = 12;  // bits of the product position (N <= 4096)
+    constexpr K KMAX = KeyMax<K>::v;
+    static_assert(N <= (1 << EB), "positions must fit the key");
+    __shared__ K buf[N];     // exchanges, then the sorted keys
+    __shared__ int rh[N];    // sorted position of every run head
+    __shared__ int wcnt[NW + 1];
+    __shared__ long long s_lbase;
+    __shared__ int s_kmax;
+    if (a.hdr->err) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, sb = wave * 256;
+    int start = 0;
+    for (int b = 0; b < bin; ++b) start += a.hdr->bin_count[b];
+    const int ncols = a.hdr->bin_count[bin];
+    for (int ci = blockIdx.x; ci < ncols; ci += gridDim.x) {
+        const int g = a.binlist[start + ci].x;
+        const int op = a.op[g];
+        const long long pbase = a.colprod[g];
+        if (op > N) {  // cannot happen: the classification bounds the bin
+            if (tid == 0) atomicOr(&a.hdr->err, ERR_GROUP);
+            continue;
+        }
+        K key[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int s = sb + r * 64 + lane;
+            key[r] = s < op ? (((K)a.prow[pbase + s] << EB) | (K)s) : KMAX;
+        }
+        block_sort<K, N>(key, buf);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) buf[sb + r * 64 + lane] = key[r];
+        __syncthreads();
+
+        // run heads and run indices (position order: wavefront, register, lane)
+        bool head[4];
+        int run[4];
+        int before = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int s = sb + r * 64 + lane;
+            head[r] = key[r] != KMAX && (s == 0 || (buf[s - 1] >> EB) != (key[r] >> EB));
+            const unsigned long long m = ballot(head[r]);
+            run[r] = before + popc64(m & mask_lt()) - (head[r] ? 0 : 1);
+            before += popc64(m);
+        }
+        if (lane == 0) wcnt[wave] = before;
+        __syncthreads();
+        if (tid == 0) {
+            int tot = 0;
+            for (int w = 0; w < NW; ++w) {
+                const int x = wcnt[w];
+                wcnt[w] = tot;
+                tot += x;
+            }
+            wcnt[NW] = tot;
+            s_kmax = 0;
+            if (op > tot)
+                s_lbase = (long long)atomicAdd(&a.hdr->later_count, (unsigned long long)(op - tot));
+            a.gnnz[g] = tot;
+        }
+        __syncthreads();
+        const int woff = wcnt[wave];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            run[r] += woff;
+            if (head[r]) rh[run[r]] = sb + r * 64 + lane;
+        }
+        __syncthreads();
+        int kloc = 0, bad = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (key[r] == KMAX) continue;
+            const int s = sb + r * 64 + lane;
+            const int e = (int)(key[r] & (K)((1 << EB) - 1));
+            const int k = s - rh[run[r]];
+            if (k == 0) {
+                a.dst[pbase + e] = (uint32_t)run[r];
+            } else {
+                const long long li = s_lbase + (s - run[r] - 1);
+                if (li < a.later_cap) {
+                    a.dst[pbase + e] = kDstLater | (uint32_t)li;
+                    a.lk[li] = k;
+                    a.lr[li] = run[r];
+                    kloc = max(kloc, k);
+                } else {
+                    bad = 1;
+                }
+            }
+        }
+        if (kloc) atomicMax(&s_kmax, kloc);
+        if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
+        __syncthreads();
+        if (tid == 0 && s_kmax) atomicMax(&a.hdr->later_maxk, s_kmax);
+    }
+}
+
+hipError_t launch_sort(const KArgs &a, int cls, bool wide, int grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    const int bin = BIN_SORT0 + cls;
+#define SPG_SORT(K, T) hipLaunchKernelGGL((k_bsort<K, T>), dim3(grid), dim3(T), 0, s, a, bin)
+    if (wide) {
+        switch (cls) {
+            case 0: SPG_SORT(unsigned long long, 128); break;
+            case 1: SPG_SORT(unsigned long long, 256); break;
+            case 2: SPG_SORT(unsigned long long, 512); break;
+            default: SPG_SORT(unsigned long long, 1024); break;
+        }
+    } else {
+        switch (cls) {
+            case 0: SPG_SORT(unsigned, 128); break;
+            case 1: SPG_SORT(unsigned, 256); break;
+            case 2: SPG_SORT(unsigned, 512); break;
+            default: SPG_SORT(unsigned, 1024); break;
+        }
+    }
+#undef SPG_SORT
+    return hipGetLastError();
+}
+
+}  // namespace spg

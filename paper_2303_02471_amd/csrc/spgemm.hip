@@ -86,6 +86,8 @@ struct spgemm_plan_s {
     bool bt_ready = false;
     int *bt_err = nullptr;
 
+    bool wide_keys = false;  // some problem has 2^20 rows or more: 64-bit sort keys
+
     hipStream_t last_stream = nullptr;
 };
 
@@ -138,7 +140,7 @@ spgemm_status hip_status(hipError_t e) {
     } while (0)
 
 spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flags) {
-    int t_esc = 256, t_dense = 512, dense_rows = kDenseRows, cap = kHashMax / 2;
+    int t_esc = 256, t_dense = 512, dense_rows = kDenseRows, cap = kHashMax / 2, t_sort = kSortMax;
     // (cap: the extra-large table class holds kHashMax / 2 distinct rows at load 1/2)
     flags = 0;
     if (opt) {
@@ -146,12 +148,15 @@ spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flag
         if (opt->t_dense) t_dense = opt->t_dense;
         if (opt->dense_rows) dense_rows = opt->dense_rows;
         if (opt->hash_cap) cap = opt->hash_cap;
+        if (opt->t_sort) t_sort = opt->t_sort;
         flags = opt->flags;
     }
     if (t_esc < 4 || t_esc > kEscMaxProducts) return SPGEMM_ERR_INVALID;
     if (t_dense < 1) return SPGEMM_ERR_INVALID;
     if (dense_rows < 64 || dense_rows > kDenseRows) return SPGEMM_ERR_INVALID;
     if (cap < 128 || cap > kHashMax / 2) return SPGEMM_ERR_INVALID;
+    if (t_sort != -1 && (t_sort < 1 || t_sort > kSortMax)) return SPGEMM_ERR_INVALID;
+    t.t_sort = t_sort < 0 ? 0 : t_sort;
     int bins = 1;
     while ((4 << (bins - 1)) < t_esc) ++bins;  // t_esc rounded up to a power of two
     t.esc_bins = bins;
@@ -365,6 +370,16 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
     {
         ProfScope ps("esc_symbolic", s);
         if ((e = launch_esc(a, ceil_div(esc_groups(h), kBlock / 64), s))) return e;
+    }
+    static const char *snames[kSortBins] = {"sort512_symbolic", "sort1k_symbolic",
+                                            "sort2k_symbolic", "sort4k_symbolic"};
+    for (int c = 0; c < kSortBins; ++c) {
+        const int n = h.bin_count[BIN_SORT0 + c];
+        if (!n) continue;
+        // small sorts with the sort-merge groups, the two larger on side streams
+        hipStream_t sc = c < 2 ? s : side(p, c - 1, s);
+        ProfScope ps(snames[c], sc);
+        if ((e = launch_sort(a, c, p->wide_keys, n, sc))) return e;
     }
     {
         ProfScope ps("dense_symbolic", side(p, 0, s));
@@ -583,6 +598,9 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
     p->tune = tune;
     p->flags = flags;
     p->probs = std::move(probs);
+    // 32-bit sort keys hold rows below 2^20 - 1
+    p->wide_keys = false;
+    for (const Prob &q : p->probs) p->wide_keys |= q.m >= (1 << 20);
     p->ncols = (int)ncols;
     p->total_nnzb = nnzb_total;
     p->ntiles = (int)tiles.size();
@@ -754,6 +772,9 @@ spgemm_status spgemm_plan_get_stats(spgemm_plan p, spgemm_plan_stats *out) {
     s.hash_items = h.item_count[0] + h.item_count[1] + h.item_count[2];
     s.esc_groups = esc_groups(h);
     s.nprob = p->nprob;
+    for (int i = 0; i < kSortBins; ++i) s.cols_sort += h.bin_count[BIN_SORT0 + i];
+    s.later_max = h.later_maxk;
+    s.later_products = (int64_t)h.later_count;
     *out = s;
     return SPGEMM_OK;
 }

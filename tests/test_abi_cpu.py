@@ -77,7 +77,8 @@ def test_options_validated_on_host(L):
     nnz = C.c_int64()
     for bad in (_lib.Options(2, 0, 0, 0, 0), _lib.Options(512, 0, 0, 0, 0),
                 _lib.Options(0, 0, 10, 0, 0), _lib.Options(0, 0, 0, 100000, 0),
-                _lib.Options(0, -1, 0, 0, 0)):
+                _lib.Options(0, -1, 0, 0, 0), _lib.Options(0, 0, 0, 0, 0, 5000),
+                _lib.Options(0, 0, 0, 0, 0, -2)):
         st = L.spgemm_symbolic(C.byref(a), C.byref(a), 1, C.byref(bad), None, C.byref(plan),
                                C.addressof(fake), C.byref(nnz))
         assert st == 9, (bad.t_esc, bad.t_dense, bad.dense_rows, bad.hash_cap)

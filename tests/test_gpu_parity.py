@@ -89,7 +89,9 @@ def test_powerlaw_reduced():
 
 @pytest.mark.parametrize("opts", [
     dict(t_esc=4), dict(t_esc=16, hash_cap=128), dict(t_esc=256, hash_cap=128),
-    dict(t_dense=1), dict(t_dense=100000), dict(dense_rows=64), dict(t_esc=4, t_dense=1)])
+    dict(t_dense=1), dict(t_dense=100000), dict(dense_rows=64), dict(t_esc=4, t_dense=1),
+    dict(t_sort=-1), dict(t_sort=-1, hash_cap=128), dict(t_esc=4, t_sort=600),
+    dict(t_esc=16, t_sort=1), dict(t_esc=4, t_sort=4096, t_dense=100000)])
 def test_forced_bins_identical(opts):
     """Any split of the work between accumulators gives the same bits (the
     t = 0 / t = infinity limits of Section 3.3 and everything between)."""
@@ -172,5 +174,11 @@ def test_stats_reported():
     assert st["total_products"] == int(op.sum())
     assert st["ncols"] == 20_000
     assert st["cols_empty"] == int((op == 0).sum())
-    assert st["cols_empty"] + st["cols_esc"] + st["cols_dense"] + st["cols_hash"] == 20_000
-    assert st["nnz_c"] == int(oracle.symbolic(A, B)[-1])
+    assert st["cols_empty"] + st["cols_esc"] + st["cols_sort"] + st["cols_dense"] + \
+        st["cols_hash"] == 20_000
+    assert st["cols_esc"] == int(((op > 0) & (op <= 256)).sum())
+    assert st["cols_sort"] == int(((op > 256) & (op <= 4096)).sum())
+    nnz_c = int(oracle.symbolic(A, B)[-1])
+    assert st["nnz_c"] == nnz_c
+    # products beyond the first of every output entry
+    assert st["later_products"] == int(op.sum()) - nnz_c
