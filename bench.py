@@ -177,7 +177,13 @@ def main():
         num, sym = kernel_bytes(op, nb, nnzc, bins[name], vb)
         kbytes[f"{name}_numeric"] = num
         kbytes[f"{name}_symbolic"] = sym
-    kbytes["numeric"] = sum(kbytes[f"{k}_numeric"] for k in bins)
+    # the tiles write columns of at most 2048 products without row windows
+    # in output order; the other columns go to the per-column numeric kernel
+    hash_cols = bins["hash_s"] | bins["hash_l"] | bins["hash_xl"]
+    windowed = hash_cols & (op > (args.hash_cap or 4096))
+    ordered = (op > 0) & (op <= 2048) & ~windowed
+    kbytes["numeric"] = kernel_bytes(op, nb, nnzc, ordered, vb)[0]
+    kbytes["numeric_big"] = kernel_bytes(op, nb, nnzc, (op > 0) & ~ordered, vb)[0]
     # expansion: (A column start, length) per stored B entry, A row read and
     # product row written per product
     kbytes["expand"] = 8 * B.nnz + 8 * int(op.sum())

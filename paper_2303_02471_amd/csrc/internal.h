@@ -36,6 +36,10 @@ constexpr int kHashBins = 3;
 constexpr int kEscBins = 7;
 constexpr int kSortBins = 4;
 constexpr int kSortMax = 4096;        // products per workgroup sort
+constexpr int kProdTile = 1024;       // products per product-balanced tile
+constexpr int kOrderMax = 2048;       // largest column the tiles write in output order
+// every column of the sort bins below the largest one is written in output order
+static_assert(kOrderMax == (512 << (kSortBins - 2)), "ordered columns end below the last sort bin");
 constexpr int kEscMaxProducts = 256;  // products per wavefront group
 
 // dense accumulator: rows per LDS slice
@@ -135,6 +139,16 @@ struct KArgs {
     long long *colprod;     // [ncols + 1] first product of every global column
     int32_t *prow;          // [products] row of every product (written once by the expansion)
     uint32_t *dst;          // [products] destination of every product (see below)
+    // Output order of the columns with at most kSortMax products and no row
+    // windows: perm[colprod[g] + r] = position in the column's product list of
+    // the first product of the column's output entry r, crow[colprod[g] + r] =
+    // the row of that entry.
+    int32_t *perm;          // [products]
+    int32_t *crow;          // [products]
+    // Product-balanced tiles: tile t holds the columns whose first product
+    // lies in [t * kProdTile, (t + 1) * kProdTile).
+    int32_t *tilestart;     // [nptiles + 1] first global column of every tile
+    int32_t nptiles;
     // Products that are not the first of their output entry ("later"
     // products), in a compact list: occurrence index k >= 1 and output rank
     // (symbolic), and the output position, problem and value staged by the
@@ -209,11 +223,16 @@ enum WinMode : int { WIN_DENSE = 0, WIN_HASH_S = 1, WIN_HASH_L = 2, WIN_HASH_XL 
 hipError_t launch_window(const KArgs &a, int mode, int grid, hipStream_t s);
 hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk,
                        long long *totals, hipStream_t s);
-// row of every product (prow), one workgroup per column tile
+// first column of every product-balanced tile
+hipError_t launch_tiles(const KArgs &a, hipStream_t s);
+// row of every product (prow), one workgroup per product-balanced tile
 hipError_t launch_expand(const KArgs &a, hipStream_t s);
-// numeric phase: every first product written to its output entry, later
-// products staged; one workgroup per column tile
+// numeric phase of the columns with an output order (one workgroup per
+// product-balanced tile) and of the others (one workgroup per column from
+// bin-list position `first`, `nbig` positions): first products written to
+// their output entries, later products staged
 hipError_t launch_numeric(const KArgs &a, bool f64, hipStream_t s);
+hipError_t launch_numeric_big(const KArgs &a, bool f64, int first, int nbig, hipStream_t s);
 // adds the staged later products of occurrence index k (n of them listed)
 hipError_t launch_layer(const KArgs &a, bool f64, int k, long long n, hipStream_t s);
 // itemoff of the `n` hash columns from bin-list position `first`

@@ -225,6 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
             const long long pe = S.cbase[cc] + (e - S.goff[cc]);
             if (k == 0) {
                 a.dst[pe] = (uint32_t)rank;
+                a.perm[S.cbase[cc] + rank] = e - S.goff[cc];
+                a.crow[S.cbase[cc] + rank] = (int)((key[r] >> 8) & 0xffffffffull);
             } else {
                 // later products of the group take places in sorted order
                 const long long li = lbase + (s - run[r] - 1);

@@ -1,35 +1,63 @@
-// Product expansion, window offsets, and the numeric phase.
+// Product expansion, tiles, window offsets, and the numeric phase.
 //
-// Expansion: one workgroup per tile of columns walks the tile's stored B
-// entries in storage order (they are contiguous), and writes the row of
-// every product -- the rows of the A column each entry selects, in storage
-// order -- to the product space. This is the only pass that expands the
-// products of Gustavson's column method (Section 2.1) from the inputs'
-// index arrays; the symbolic accumulators stream these rows.
+// Product-balanced tiles: tile t holds the columns whose first product lies in
+// [t * kProdTile, (t + 1) * kProdTile) of the product space, so every tile has
+// about kProdTile products (plus the tail of its last column).
 //
-// Numeric: the symbolic phase left a destination per product: the rank of its
-// output row inside its column (or row window), or, for a product that is not
-// the first of its output entry, its place in a list of such "later"
-// products together with its occurrence index k. The numeric phase walks the
-// tiles the same way, forms every product A(i,k) * B(k,j) from coalesced
-// reads of the selected A columns, writes every first product as 0 + product
-// to its output position, and stages the later ones. Layer kernels then add
-// the staged products of occurrence index 1, 2, ... in that order, so every
+// Expansion: one workgroup per tile walks the tile's stored B entries in
+// storage order (they are contiguous) and writes the row of every product --
+// the rows of the A column each entry selects, in storage order -- to the
+// product space. This is the only pass that expands the products of
+// Gustavson's column method (Section 2.1) from the inputs' index arrays; the
+// symbolic accumulators stream these rows.
+//
+// Numeric: the symbolic phase left, per product, a destination (the rank of
+// its output row, or for a product that is not the first of its output entry
+// a place in the list of such "later" products with its occurrence index k),
+// and, for columns of at most kSortMax products without row windows, the
+// output order (the first product and the row of every output entry). One
+// workgroup per tile forms the products A(i,k) * B(k,j) of its columns of at
+// most kOrderMax products from coalesced reads of the selected A columns into
+// LDS, then writes their output entries in order as 0 + first product. Larger
+// or windowed columns are done by one workgroup per column through the
+// destinations. Later products are staged; layer
+// kernels add those of occurrence index 1, 2, ... in that order, so every
 // output entry is summed in Algorithm 1's order and rounding, bit for bit.
 #include "devutil.h"
 
 namespace spg {
 
-__device__ __forceinline__ void tile_of(const KArgs &a, int &pid, int &j0, int &j1) {
-    if (a.nprob == 1) {
-        pid = 0;
-        j0 = blockIdx.x * kTile;
-        j1 = min(a.single.n, j0 + kTile);
-    } else {
-        const int4 tl = a.tiles[blockIdx.x];
-        pid = tl.x;
-        j0 = tl.y;
-        j1 = tl.z;
+// ---------------------------------------------------------------- tiles
+// thread per global column g: g is the first column of the tiles t with
+// P(g-1) < t * kProdTile <= P(g) (P = first product of a column)
+__global__ __launch_bounds__(kBlock) void k_tiles(KArgs a) {
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= a.ncols) return;
+    // tile t starts at the first column with P >= t * kProdTile: column g
+    // starts the tiles with P(g - 1) < t * kProdTile <= P(g)
+    const long long t_hi = a.colprod[g] / kProdTile;
+    const long long t_lo = g == 0 ? 0 : a.colprod[g - 1] / kProdTile + 1;
+    for (long long t = t_lo; t <= t_hi && t < a.nptiles; ++t) a.tilestart[t] = g;
+    if (g == a.ncols - 1)  // tiles after the last column's first product are empty
+        for (long long t = t_hi + 1; t <= a.nptiles; ++t) a.tilestart[t] = a.ncols;
+}
+
+hipError_t launch_tiles(const KArgs &a, hipStream_t s) {
+    if (a.ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tiles, dim3(ceil_div(a.ncols, kBlock)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// Calls f(pid, d, j0, j1) for the problem segments of tile columns [g0, g1).
+template <typename F>
+__device__ __forceinline__ void for_each_segment(const KArgs &a, int g0, int g1, F &&f) {
+    int g = g0;
+    while (g < g1) {
+        const int pid = find_prob(a, g);
+        const Prob d = get_prob(a, pid);
+        const int gend = min(g1, d.col0 + d.n);
+        f(pid, d, g - d.col0, gend - d.col0);
+        g = gend;
     }
 }
 
@@ -44,62 +72,62 @@ __global__ __launch_bounds__(kBlock) void k_expand(KArgs a) {
     constexpr int PER = 4;
     __shared__ ExpSmem S;
     if (a.hdr->err) return;
-    int pid, j0, j1;
-    tile_of(a, pid, j0, j1);
-    const Prob d = get_prob(a, pid);
     const int tid = threadIdx.x;
-    long long base = a.colprod[d.col0 + j0];
-    const int pb = d.bcp[j0], pe = d.bcp[j1];  // checked by the classification
-    const int2 *__restrict__ Ep = a.E + d.ebase;
-    const int *__restrict__ ari = d.ari;
+    const int g0 = a.tilestart[blockIdx.x], g1 = a.tilestart[blockIdx.x + 1];
     int *__restrict__ prow = a.prow;
     int bad = 0;
-    for (int bw = pb; bw < pe; bw += kBlock) {
-        const int t = bw + tid;
-        int z = 0, acp = 0;
-        if (t < pe) {
-            const int2 ez = Ep[t];
-            acp = ez.x;
-            z = ez.y;
-        }
-        int Ew;
-        const int ex = block_excl_scan(z, S.scan_tmp, Ew);
-        S.s_acp[tid] = acp;
-        S.s_eoff[tid] = ex;
-        __syncthreads();
-        const int nbw = min(kBlock, pe - bw);
-        for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
-            int r[PER];
+    for_each_segment(a, g0, g1, [&](int, const Prob &d, int j0, int j1) {
+        long long base = a.colprod[d.col0 + j0];
+        const int pb = d.bcp[j0], pe = d.bcp[j1];  // checked by the classification
+        const int2 *__restrict__ Ep = a.E + d.ebase;
+        const int *__restrict__ ari = d.ari;
+        for (int bw = pb; bw < pe; bw += kBlock) {
+            const int t = bw + tid;
+            int z = 0, acp = 0;
+            if (t < pe) {
+                const int2 ez = Ep[t];
+                acp = ez.x;
+                z = ez.y;
+            }
+            int Ew;
+            const int ex = block_excl_scan(z, S.scan_tmp, Ew);
+            S.s_acp[tid] = acp;
+            S.s_eoff[tid] = ex;
+            __syncthreads();
+            const int nbw = min(kBlock, pe - bw);
+            for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
+                int r[PER];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = e0 + u * kBlock + tid;
-                r[u] = 0;
-                if (e < Ew) {
-                    const int tt = last_le(S.s_eoff, nbw, e);
-                    r[u] = ari[S.s_acp[tt] + e - S.s_eoff[tt]];
+                for (int u = 0; u < PER; ++u) {
+                    const int e = e0 + u * kBlock + tid;
+                    r[u] = 0;
+                    if (e < Ew) {
+                        const int tt = last_le(S.s_eoff, nbw, e);
+                        r[u] = ari[S.s_acp[tt] + e - S.s_eoff[tt]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int e = e0 + u * kBlock + tid;
+                    if (e >= Ew) continue;
+                    int row = r[u];
+                    if (row < 0 || row >= d.m) {
+                        bad = 1;
+                        row = 0;
+                    }
+                    prow[base + e] = row;
                 }
             }
-#pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = e0 + u * kBlock + tid;
-                if (e >= Ew) continue;
-                int row = r[u];
-                if (row < 0 || row >= d.m) {
-                    bad = 1;
-                    row = 0;
-                }
-                prow[base + e] = row;
-            }
+            base += Ew;
+            __syncthreads();
         }
-        base += Ew;
-        __syncthreads();
-    }
+    });
     if (bad) atomicOr(&a.hdr->err, ERR_CSC);
 }
 
 hipError_t launch_expand(const KArgs &a, hipStream_t s) {
-    if (a.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand, dim3(a.ntiles), dim3(kBlock), 0, s, a);
+    if (a.nptiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand, dim3(a.nptiles), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -125,118 +153,261 @@ hipError_t launch_item_offsets(const KArgs &a, int first, int n, hipStream_t s) 
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- numeric
+// ---------------------------------------------------------------- numeric, tiles
+constexpr int kColWin = 256;                   // columns per window of a tile
+constexpr int kStage = kProdTile + kOrderMax;  // staged products of a tile
+
+// the tiles write a column in output order when it has at most kOrderMax
+// products and no row windows (its output order is then recorded)
+__device__ __forceinline__ bool has_order(int op, int binw) {
+    return op <= kOrderMax && (binw >> 8) <= 1;
+}
+
 template <typename V>
 struct NumSmem {
+    V val[kStage];           // products of the tile's ordered columns (by product offset)
     int s_acp[kBlock];       // A column start of each stored B entry of the B window
     int s_eoff[kBlock];      // first product of each stored B entry of the B window
-    int s_col[kBlock];       // tile column of each stored B entry of the B window
+    int s_col[kBlock];       // window column of each stored B entry of the B window
     V s_bv[kBlock];          // B value of each stored B entry of the B window
-    int s_bcp[kTile + 1];    // B column pointers of the tile
-    int s_c0[kTile + 1];     // C column pointers of the tile
-    int s_w[kTile];          // row windows of each tile column (0 or 1: whole column)
-    int s_it0[kTile];        // first work item of each windowed tile column
+    int s_bcp[kColWin + 1];  // B column pointers of the column window
+    int s_c0[kColWin + 1];   // C column pointers of the column window
+    int s_pb[kColWin + 1];   // first product of each column, relative to the tile
+    int s_ok[kColWin];       // column written in output order
     int scan_tmp[kBlock / 64 + 1];
 };
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
-    constexpr int PER = 2;
+    constexpr int PER = 4;   // products per thread per chunk
+    constexpr int OPER = 8;  // output entries per thread per chunk
     __shared__ NumSmem<V> S;
     if (a.hdr->err) return;
-    int pid, j0, j1;
-    tile_of(a, pid, j0, j1);
-    const Prob d = get_prob(a, pid);
     const int tid = threadIdx.x;
-    const int nt = j1 - j0;
-    const int g0 = d.col0 + j0;
-    for (int c = tid; c <= nt; c += kBlock) {
-        S.s_bcp[c] = d.bcp[j0 + c];
-        S.s_c0[c] = d.ccp[j0 + c];
-    }
-    for (int c = tid; c < nt; c += kBlock) {
-        const int W = a.binw[g0 + c] >> 8;
-        S.s_w[c] = W;
-        S.s_it0[c] = W > 1 ? a.colitem[g0 + c] : 0;
-    }
-    __syncthreads();
-    long long base = a.colprod[g0];
-    const int pb = S.s_bcp[0], pe = S.s_bcp[nt];
-    const int2 *__restrict__ Ep = a.E + d.ebase;
-    const int *__restrict__ ari = d.ari;
-    const V *__restrict__ av = (const V *)d.av;
-    const V *__restrict__ bv = (const V *)d.bv;
-    int *__restrict__ cri = d.cri;
-    V *__restrict__ cv = (V *)d.cv;
+    const int g0 = a.tilestart[blockIdx.x], g1 = a.tilestart[blockIdx.x + 1];
+    if (g0 >= g1) return;
+    const long long tbase = a.colprod[g0];
     V *__restrict__ lv = (V *)a.lv;
     int bad = 0;
-    for (int bw = pb; bw < pe; bw += kBlock) {
-        const int t = bw + tid;
-        int z = 0, acp = 0, col = 0;
-        V b = V(0);
-        if (t < pe) {
-            const int2 ez = Ep[t];
-            acp = ez.x;
-            z = ez.y;
-            b = bv[t];
-            col = last_le(S.s_bcp, nt + 1, t);
-        }
-        int Ew;
-        const int ex = block_excl_scan(z, S.scan_tmp, Ew);
-        S.s_acp[tid] = acp;
-        S.s_eoff[tid] = ex;
-        S.s_col[tid] = col;
-        S.s_bv[tid] = b;
-        __syncthreads();
-        const int nbw = min(kBlock, pe - bw);
-        for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
-            int row[PER], tt[PER];
-            V val[PER];
-            uint32_t dc[PER];
+    for_each_segment(a, g0, g1, [&](int pid, const Prob &d, int js, int je) {
+        const int2 *__restrict__ Ep = a.E + d.ebase;
+        const V *__restrict__ av = (const V *)d.av;
+        const V *__restrict__ bv = (const V *)d.bv;
+        int *__restrict__ cri = d.cri;
+        V *__restrict__ cv = (V *)d.cv;
+        for (int jw = js; jw < je; jw += kColWin) {
+            const int nc = min(kColWin, je - jw);
+            const int gw = d.col0 + jw;
+            for (int c = tid; c <= nc; c += kBlock) {
+                S.s_bcp[c] = d.bcp[jw + c];
+                S.s_c0[c] = d.ccp[jw + c];
+                const long long pc = c < nc ? a.colprod[gw + c]
+                                            : a.colprod[gw + nc - 1] + a.op[gw + nc - 1];
+                S.s_pb[c] = (int)(pc - tbase);
+                if (c < nc) S.s_ok[c] = has_order(a.op[gw + c], a.binw[gw + c]);
+            }
+            __syncthreads();
+            // ---- products of the window's ordered columns into LDS; later
+            // products staged for the layer kernels. The next B window's
+            // loads are issued before the current one is processed.
+            long long base = tbase + S.s_pb[0];
+            const int pb = S.s_bcp[0], pe = S.s_bcp[nc];
+            int2 nez = make_int2(0, 0);
+            V nb = V(0);
+            if (pb + tid < pe) {
+                nez = Ep[pb + tid];
+                nb = bv[pb + tid];
+            }
+            for (int bw = pb; bw < pe; bw += kBlock) {
+                const int t = bw + tid;
+                const int2 ez = nez;
+                const V b0 = nb;
+                if (t + kBlock < pe) {
+                    nez = Ep[t + kBlock];
+                    nb = bv[t + kBlock];
+                }
+                int z = 0, acp = 0, col = 0;
+                V b = V(0);
+                if (t < pe) {
+                    col = last_le(S.s_bcp, nc + 1, t);
+                    z = ez.y;
+                    if (S.s_ok[col]) {
+                        acp = ez.x;
+                        b = b0;
+                    }
+                }
+                int Ew;
+                const int ex = block_excl_scan(z, S.scan_tmp, Ew);
+                S.s_acp[tid] = acp;
+                S.s_eoff[tid] = ex;
+                S.s_col[tid] = col;
+                S.s_bv[tid] = b;
+                __syncthreads();
+                const int nbw = min(kBlock, pe - bw);
+                for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
+                    V v[PER];
+                    uint32_t dc[PER];
+                    int c[PER];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = e0 + u * kBlock + tid;
-                row[u] = -1;
-                if (e < Ew) {
-                    tt[u] = last_le(S.s_eoff, nbw, e);
-                    const int q = S.s_acp[tt[u]] + e - S.s_eoff[tt[u]];
-                    row[u] = ari[q];
-                    val[u] = av[q] * S.s_bv[tt[u]];
-                    dc[u] = a.dst[base + e];
+                    for (int u = 0; u < PER; ++u) {
+                        const int e = e0 + u * kBlock + tid;
+                        c[u] = -1;
+                        if (e < Ew) {
+                            const int tt = last_le(S.s_eoff, nbw, e);
+                            if (S.s_ok[S.s_col[tt]]) {
+                                c[u] = S.s_col[tt];
+                                const int q = S.s_acp[tt] + e - S.s_eoff[tt];
+                                v[u] = av[q] * S.s_bv[tt];
+                                dc[u] = a.dst[base + e];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < PER; ++u) {
+                        if (c[u] < 0) continue;
+                        const long long eg = base + e0 + u * kBlock + tid;
+                        S.val[eg - tbase] = v[u];
+                        if (dc[u] & kDstLater) {
+                            const int li = (int)(dc[u] & ~kDstLater);
+                            if (li >= a.later_cap) { bad = 1; continue; }
+                            const int o = a.lr[li];
+                            if (o < 0 || o >= S.s_c0[c[u] + 1] - S.s_c0[c[u]]) { bad = 1; continue; }
+                            a.lo[li] = S.s_c0[c[u]] + o;
+                            a.lpid[li] = pid;
+                            lv[li] = v[u];
+                        }
+                    }
+                }
+                base += Ew;
+                __syncthreads();
+            }
+            // ---- output entries of the window's ordered columns, in order
+            const int o0 = S.s_c0[0], o1 = S.s_c0[nc];
+            for (int oc = o0; oc < o1; oc += OPER * kBlock) {
+                int c[OPER], e[OPER], row[OPER];
+#pragma unroll
+                for (int u = 0; u < OPER; ++u) {
+                    const int o = oc + u * kBlock + tid;
+                    c[u] = -1;
+                    if (o < o1) {
+                        const int cc = last_le(S.s_c0, nc + 1, o);
+                        if (S.s_ok[cc]) {
+                            c[u] = cc;
+                            const long long po = tbase + S.s_pb[cc] + (o - S.s_c0[cc]);
+                            e[u] = a.perm[po];
+                            row[u] = a.crow[po];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < OPER; ++u) {
+                    if (c[u] < 0) continue;
+                    if (e[u] < 0 || e[u] >= S.s_pb[c[u] + 1] - S.s_pb[c[u]]) {
+                        bad = 1;
+                        continue;
+                    }
+                    const int o = oc + u * kBlock + tid;
+                    cri[o] = row[u];
+                    cv[o] = V(0) + S.val[S.s_pb[c[u]] + e[u]];
                 }
             }
-#pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                if (row[u] < 0) continue;
-                const int c = S.s_col[tt[u]];
-                const int c0 = S.s_c0[c], clen = S.s_c0[c + 1] - c0;
-                const bool later = (dc[u] & kDstLater) != 0;
-                const int li = (int)(dc[u] & ~kDstLater);
-                if (later && li >= a.later_cap) {  // destinations do not match the plan
-                    bad = 1;
-                    continue;
-                }
-                int o = later ? a.lr[li] : li;
-                const int W = S.s_w[c];
-                if (W > 1) o += a.itemoff[S.s_it0[c] + window_of(row[u], W, d.m)];
-                if (o < 0 || o >= clen || row[u] >= d.m) {
-                    bad = 1;
-                    continue;
-                }
-                if (!later) {
-                    cri[c0 + o] = row[u];
-                    cv[c0 + o] = V(0) + val[u];
-                } else {
-                    a.lo[li] = c0 + o;
-                    a.lpid[li] = pid;
-                    lv[li] = val[u];
-                }
-            }
+            __syncthreads();
         }
-        base += Ew;
-        __syncthreads();
-    }
+    });
     if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
+}
+
+// ---------------------------------------------------------------- numeric, other columns
+template <typename V>
+struct BigSmem {
+    int s_acp[kBlock];
+    int s_eoff[kBlock];
+    V s_bv[kBlock];
+    int scan_tmp[kBlock / 64 + 1];
+};
+
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int n) {
+    constexpr int PER = 4;
+    __shared__ BigSmem<V> S;
+    if (a.hdr->err) return;
+    const int tid = threadIdx.x;
+    V *__restrict__ lv = (V *)a.lv;
+    for (int li0 = blockIdx.x; li0 < n; li0 += gridDim.x) {
+        const int4 ent = a.binlist[first + li0];
+        const int g = ent.x, bs = ent.y, be = ent.y + ent.z;
+        const int bwin = a.binw[g];
+        if (has_order(a.op[g], bwin)) continue;  // done by the tiles
+        const int pid = find_prob(a, g);
+        const Prob d = get_prob(a, pid);
+        const int j = g - d.col0;
+        const int W = max(bwin >> 8, 1);
+        const int it0 = W > 1 ? a.colitem[g] : 0;
+        long long base = a.colprod[g];
+        const int c0 = d.ccp[j], clen = d.ccp[j + 1] - c0;
+        const int2 *__restrict__ Ep = a.E + d.ebase;
+        const V *__restrict__ av = (const V *)d.av;
+        const V *__restrict__ bv = (const V *)d.bv;
+        int *__restrict__ cri = d.cri + c0;
+        V *__restrict__ cv = (V *)d.cv + c0;
+        int bad = 0;
+        for (int bw = bs; bw < be; bw += kBlock) {
+            const int t = bw + tid;
+            int z = 0, acp = 0;
+            V b = V(0);
+            if (t < be) {
+                const int2 ez = Ep[t];
+                acp = ez.x;
+                z = ez.y;
+                b = bv[t];
+            }
+            int Ew;
+            const int ex = block_excl_scan(z, S.scan_tmp, Ew);
+            S.s_acp[tid] = acp;
+            S.s_eoff[tid] = ex;
+            S.s_bv[tid] = b;
+            __syncthreads();
+            const int nbw = min(kBlock, be - bw);
+            for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
+                int row[PER];
+                V v[PER];
+                uint32_t dc[PER];
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int e = e0 + u * kBlock + tid;
+                    row[u] = -1;
+                    if (e < Ew) {
+                        const int tt = last_le(S.s_eoff, nbw, e);
+                        const int q = S.s_acp[tt] + e - S.s_eoff[tt];
+                        row[u] = a.prow[base + e];
+                        v[u] = av[q] * S.s_bv[tt];
+                        dc[u] = a.dst[base + e];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    if (row[u] < 0) continue;
+                    const bool later = (dc[u] & kDstLater) != 0;
+                    const int li = (int)(dc[u] & ~kDstLater);
+                    if (later && li >= a.later_cap) { bad = 1; continue; }
+                    int o = later ? a.lr[li] : li;
+                    if (W > 1) o += a.itemoff[it0 + window_of(row[u], W, d.m)];
+                    if (o < 0 || o >= clen) { bad = 1; continue; }
+                    if (!later) {
+                        cri[o] = row[u];
+                        cv[o] = V(0) + v[u];
+                    } else {
+                        a.lo[li] = c0 + o;
+                        a.lpid[li] = pid;
+                        lv[li] = v[u];
+                    }
+                }
+            }
+            base += Ew;
+            __syncthreads();
+        }
+        if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
+    }
 }
 
 // later products of occurrence index k, added to their (already written)
@@ -255,9 +426,18 @@ __global__ __launch_bounds__(kBlock) void k_layer(KArgs a, int k, long long n) {
 }
 
 hipError_t launch_numeric(const KArgs &a, bool f64, hipStream_t s) {
-    if (a.ntiles <= 0) return hipSuccess;
-    if (f64) hipLaunchKernelGGL((k_numeric<double>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_numeric<float>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+    if (a.nptiles <= 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL((k_numeric<double>), dim3(a.nptiles), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_numeric<float>), dim3(a.nptiles), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_numeric_big(const KArgs &a, bool f64, int first, int nbig, hipStream_t s) {
+    if (nbig <= 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL((k_numeric_big<double>), dim3(nbig), dim3(kBlock), 0, s, a, first, nbig);
+    else
+        hipLaunchKernelGGL((k_numeric_big<float>), dim3(nbig), dim3(kBlock), 0, s, a, first, nbig);
     return hipGetLastError();
 }
 

@@ -192,6 +192,8 @@ __global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
             const int k = s - rh[run[r]];
             if (k == 0) {
                 a.dst[pbase + e] = (uint32_t)run[r];
+                a.perm[pbase + run[r]] = e;
+                a.crow[pbase + run[r]] = (int)(key[r] >> EB);
             } else {
                 const long long li = s_lbase + (s - run[r] - 1);
                 if (li < a.later_cap) {

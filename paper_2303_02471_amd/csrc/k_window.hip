@@ -303,7 +303,9 @@ __global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
             for (int sl = tid; sl < nslot; sl += T) S.cnt[sl] = 0;
             __syncthreads();
 
-            // ---- pass 2: destinations
+            // ---- pass 2: destinations (and the output order of a column with
+            // one window and at most kSortMax products)
+            const bool order_out = W == 1 && op <= kSortMax;
             int slot[PER], rk[PER];
             bool pend[PER];
             long long eg[PER];
@@ -321,6 +323,10 @@ __global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
                     pend[u] = true;
                 } else {
                     a.dst[e] = (uint32_t)rk[u];
+                    if (order_out) {
+                        a.perm[pbase + rk[u]] = (int)(e - pbase);
+                        a.crow[pbase + rk[u]] = DENSE ? x + sl : S.keys[sl];
+                    }
                 }
             };
             // occurrence indices of products sharing a slot, in list order
@@ -352,6 +358,11 @@ __global__ __launch_bounds__(WinCfg<MODE>::T) void k_window(KArgs a) {
                             S.cnt[slot[u]] = k + 1;
                             if (k == 0) {
                                 a.dst[eg[u]] = (uint32_t)rk[u];
+                                if (order_out) {
+                                    a.perm[pbase + rk[u]] = (int)(eg[u] - pbase);
+                                    a.crow[pbase + rk[u]] =
+                                        DENSE ? x + slot[u] : S.keys[slot[u]];
+                                }
                             } else {
                                 const long long lix = S.s_lbase + atomicAdd(&S.s_lcur, 1);
                                 if (lix < a.later_cap) {

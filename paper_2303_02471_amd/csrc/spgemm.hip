@@ -52,7 +52,8 @@ struct spgemm_plan_s {
     size_t prod_bytes = 0;
     int32_t *prow = nullptr;
     uint32_t *dst = nullptr;
-    int32_t *lk = nullptr, *lr = nullptr;
+    int32_t *lk = nullptr, *lr = nullptr, *perm = nullptr, *crow = nullptr, *tilestart = nullptr;
+    int nptiles = 0;
     long long later_cap = 0;
     // staging of the later products for the numeric phase (sized by their count)
     void *stage = nullptr;
@@ -286,6 +287,10 @@ KArgs make_args(spgemm_plan p) {
     a.itemcnt = p->itemcnt;
     a.prow = p->prow;
     a.dst = p->dst;
+    a.perm = p->perm;
+    a.crow = p->crow;
+    a.tilestart = p->tilestart;
+    a.nptiles = p->nptiles;
     a.later_cap = p->later_cap;
     a.lk = p->lk;
     a.lr = p->lr;
@@ -405,10 +410,22 @@ hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
     const bool f64 = p->dt == SPGEMM_F64;
     const Hdr &h = p->hdr_host;
     hipError_t e;
+    // columns the tiles do not write in output order can only be in the
+    // largest sort bin, the dense bin and the hash bins (bin-list order)
+    int first = 0, n = 0;
+    for (int b = 0; b < BIN_SORT3; ++b) first += h.bin_count[b];
+    for (int b = BIN_SORT3; b < NBINS; ++b) n += h.bin_count[b];
+    if ((e = fork(p, s))) return e;
     {
         ProfScope ps("numeric", s);
         if ((e = launch_numeric(a, f64, s))) return e;
     }
+    {
+        // columns with more than kOrderMax products or with row windows
+        ProfScope ps("numeric_big", side(p, 0, s));
+        if ((e = launch_numeric_big(a, f64, first, n, side(p, 0, s)))) return e;
+    }
+    if ((e = join(p, s))) return e;
     if (h.later_count == 0) return hipSuccess;
     ProfScope ps("later_layers", s);
     for (int k = 1; k <= h.later_maxk; ++k)
@@ -459,7 +476,8 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         const Hdr &hh = p->hdr_host;
         const size_t P = (size_t)std::max<unsigned long long>(hh.total_op, 1);
         const size_t q1 = align_up(4 * P, 256);
-        const size_t pneed = 4 * q1;
+        p->nptiles = (int)(hh.total_op / kProdTile) + 1;
+        const size_t pneed = 6 * q1 + 4 * ((size_t)p->nptiles + 1);
         if (pneed > p->prod_bytes) {
             if (p->prod) (void)hipFree(p->prod);
             p->prod = nullptr;
@@ -471,10 +489,14 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         p->dst = (uint32_t *)((char *)p->prod + q1);
         p->lk = (int32_t *)((char *)p->prod + 2 * q1);
         p->lr = (int32_t *)((char *)p->prod + 3 * q1);
+        p->perm = (int32_t *)((char *)p->prod + 4 * q1);
+        p->crow = (int32_t *)((char *)p->prod + 5 * q1);
+        p->tilestart = (int32_t *)((char *)p->prod + 6 * q1);
         // later places are 31-bit indices
         p->later_cap = (long long)std::min<size_t>(P, 0x7fffffff);
         if (p->ncols > 0) {
             const KArgs al = make_args(p);
+            { ProfScope ps("tiles", s); SPG_TRY(launch_tiles(al, s)); }
             { ProfScope ps("expand", s); SPG_TRY(launch_expand(al, s)); }
             SPG_TRY(launch_symbolic_accumulators(p, al, s));
             ProfScope ps("scan", s);
