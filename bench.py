@@ -24,6 +24,7 @@ import json
 import os
 import statistics
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -49,6 +50,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--t-esc", type=int, default=0, help="library option (0 = default)")
     ap.add_argument("--hash-cap", type=int, default=0, help="library option (0 = default)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="library defaults instead of autotuned thresholds")
     ap.add_argument("--one-stream", action="store_true",
                     help="library option: no overlap of accumulator kinds (per-kernel timings)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -139,7 +142,21 @@ def main():
     log(f"generated n={args.n} nnzA={A.nnz} nnzB={B.nnz} in {time.time() - t0:.1f}s")
     At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
     vb = 8
-    opts = api.options(t_esc=args.t_esc, hash_cap=args.hash_cap, one_stream=args.one_stream)
+    tuning = None
+    if args.no_autotune or args.t_esc or args.hash_cap:
+        opts = api.options(t_esc=args.t_esc, hash_cap=args.hash_cap, one_stream=args.one_stream)
+    else:
+        # thresholds chosen by the library's autotuner (outside the timed region;
+        # the options never change results)
+        with tempfile.TemporaryDirectory() as td:
+            opts, trep = api.autotune([(At, Bt)], torch.float64,
+                                      cache_path=os.path.join(td, "tune.json"))
+        if args.one_stream:
+            opts.flags |= 2
+        tuning = {"t_esc": opts.t_esc, "t_sort": opts.t_sort, "hash_cap": opts.hash_cap,
+                  "t_dense": opts.t_dense, "trials": trep["trials"],
+                  "default_ms": round(trep["default_ms"], 4), "tuned_ms": round(trep["best_ms"], 4)}
+        log(f"autotune: {tuning}")
     plan, colptr, nnz = api.symbolic(At, Bt, torch.float64, opts)
     rowidx = torch.empty(nnz, dtype=torch.int32, device=dev)
     val = torch.empty(nnz, dtype=torch.float64, device=dev)
@@ -171,7 +188,10 @@ def main():
 
     # ------------------------------------------------------------ roofline of the dominant kernel
     nnzc = np.diff(colptr.cpu().numpy().astype(np.int64))
-    op, nb, bins = per_column_work(A, B, t_esc=args.t_esc or 256, hash_cap=args.hash_cap or 4096)
+    t_sort = opts.t_sort if opts.t_sort else 4096
+    op, nb, bins = per_column_work(A, B, t_esc=opts.t_esc or 256, hash_cap=opts.hash_cap or 4096,
+                                   t_sort=t_sort if t_sort > 0 else 0,
+                                   t_dense=opts.t_dense or 512)
     kbytes = {}
     for name in bins:
         num, sym = kernel_bytes(op, nb, nnzc, bins[name], vb)
@@ -180,7 +200,7 @@ def main():
     # the tiles write columns of at most 2048 products without row windows
     # in output order; the other columns go to the per-column numeric kernel
     hash_cols = bins["hash_s"] | bins["hash_l"] | bins["hash_xl"]
-    windowed = hash_cols & (op > (args.hash_cap or 4096))
+    windowed = hash_cols & (op > (opts.hash_cap or 4096))
     ordered = (op > 0) & (op <= 2048) & ~windowed
     kbytes["numeric"] = kernel_bytes(op, nb, nnzc, ordered, vb)[0]
     kbytes["numeric_big"] = kernel_bytes(op, nb, nnzc, (op > 0) & ~ordered, vb)[0]
@@ -233,7 +253,8 @@ def main():
     extras = {}
     if not args.no_extras:
         extras["fwd_bwd"] = fwd_bwd(api, gen, np, torch)
-        extras["batched"] = batched(api, gen, np, torch, args.batch_count)
+        extras["batched"] = batched(api, gen, np, torch, args.batch_count,
+                                    tune=not args.no_autotune)
 
     out = {
         "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1,
@@ -247,6 +268,7 @@ def main():
         "hbm_compulsory_GBps": round(compulsory / (ms * 1e-3) / 1e9, 1),
         "hbm_compulsory_frac": round(compulsory / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
+        "tuning": tuning,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
@@ -286,26 +308,28 @@ def fwd_bwd(api, gen, np, torch, n=100_000, z=8, reps=20):
             "fwd_bwd_ms": round(tfb, 4), "fwd_bwd_over_fwd": round(tfb / tf, 3)}
 
 
-def batched(api, gen, np, torch, count, reps=5):
-    """One batched launch set against a loop of per-matrix calls, same kernels."""
+def batched(api, gen, np, torch, count, reps=5, tune=True):
+    """One batched launch set against a loop of per-matrix calls, same kernels
+    and options (autotuned on the batch); numeric also replayed as a HIP graph."""
     probs = gen.batched_problems(count, seed=0)
     pairs = [(api.CscTensor.from_host(a), api.CscTensor.from_host(b)) for a, b in probs]
-    outs, bplan = api.batched_matmul(pairs, return_plan=True)
+    opts = api.autotune(pairs, torch.float64)[0] if tune else None
+    outs, bplan = api.batched_matmul(pairs, opts, return_plan=True)
     nnzs = bplan.nnzs
     rowidxs = [o.rowidx for o in outs]
     vals = [o.val for o in outs]
     plans = []
     for (a, b), o in zip(pairs, outs):
-        _, p = api.matmul(a, b, return_plan=True)
+        _, p = api.matmul(a, b, opts, return_plan=True)
         plans.append(p)
 
     def t_batched():
-        bplan2, cps, _ = api.batched_symbolic(pairs, torch.float64, plan=bplan)
+        bplan2, cps, _ = api.batched_symbolic(pairs, torch.float64, opts, plan=bplan)
         api.batched_numeric(bplan, pairs, rowidxs, vals)
 
     def t_loop():
         for (a, b), p, ri, v in zip(pairs, plans, rowidxs, vals):
-            api.symbolic(a, b, torch.float64, plan=p, out_colptr=p.colptr)
+            api.symbolic(a, b, torch.float64, opts, plan=p, out_colptr=p.colptr)
             api.numeric(p, a.val, b.val, ri, v)
 
     def t_batched_num():
@@ -326,14 +350,25 @@ def batched(api, gen, np, torch, count, reps=5):
 
     tb, tl = timeit(t_batched), timeit(t_loop)
     tbn, tln = timeit(t_batched_num), timeit(t_loop_num)
-    log(f"batched {tb:.2f} ms vs loop {tl:.2f} ms; numeric {tbn:.2f} vs {tln:.2f}")
+    # numeric phase captured once in a HIP graph and replayed
+    t_batched_num()
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            api.batched_numeric(bplan, pairs, rowidxs, vals, stream=stream)
+    tgn = timeit(graph.replay)
+    log(f"batched {tb:.2f} ms vs loop {tl:.2f} ms; numeric {tbn:.2f} vs {tln:.2f}; "
+        f"numeric graph replay {tgn:.2f}")
     return {"workload": f"{count} problems, n log-uniform [500, 20000], 2..40 per column, FP64",
             "products": int(sum(p.stats()["total_products"] for p in plans)),
             "nnz_c": int(sum(nnzs)),
             "batched_ms": round(tb, 3), "per_matrix_loop_ms": round(tl, 3),
             "speedup": round(tl / tb, 3),
             "numeric_batched_ms": round(tbn, 3), "numeric_loop_ms": round(tln, 3),
-            "numeric_speedup": round(tln / tbn, 3)}
+            "numeric_speedup": round(tln / tbn, 3),
+            "numeric_graph_ms": round(tgn, 3), "numeric_graph_speedup": round(tln / tgn, 3)}
 
 
 if __name__ == "__main__":

@@ -62,7 +62,8 @@ typedef enum {
     SPGEMM_ERR_NO_MEMORY = 6,      /* device or host allocation failed */
     SPGEMM_ERR_HIP = 7,            /* a HIP runtime call failed */
     SPGEMM_ERR_PLAN = 8,           /* plan missing, of the wrong kind, or not in the needed state */
-    SPGEMM_ERR_INVALID = 9         /* invalid option value or argument combination */
+    SPGEMM_ERR_INVALID = 9,        /* invalid option value or argument combination */
+    SPGEMM_ERR_NOT_TUNED = 10      /* no tuning cache entry for the workload (lookup only) */
 } spgemm_status;
 
 typedef enum { SPGEMM_F32 = 0, SPGEMM_F64 = 1 } spgemm_dtype;
@@ -215,6 +216,51 @@ void spgemm_plan_destroy(spgemm_plan plan);
 
 /* Static text for a status code. */
 const char *spgemm_status_string(spgemm_status s);
+
+/*
+ * Autotuning. Chooses tuning options for a workload by timing candidate
+ * settings of t_esc, t_sort, hash_cap and t_dense (the role of the paper's
+ * switch threshold t, Section 3.3, and of its hash-size adaptation, Section
+ * 3.2): coordinate descent from the defaults, each candidate timed as
+ * symbolic + numeric (best of three runs after a warm-up). Options never
+ * change results, so neither does tuning.
+ *   count, A_host, B_host  the problems as for spgemm_batched (count == 1:
+ *               a single product); value arrays are needed for the timing.
+ *   cache_path  JSON file keyed by device and workload signature, or NULL.
+ *               A hit returns the cached options without timing; after a
+ *               search the choice is stored. A file that does not parse is
+ *               treated as empty and rewritten.
+ *   tune_flags  SPGEMM_TUNE_LOOKUP_ONLY: never time (SPGEMM_ERR_NOT_TUNED
+ *               without a cache entry); SPGEMM_TUNE_REFRESH: ignore the entry.
+ * Allocates device memory for the trial outputs and frees it; blocks.
+ */
+#define SPGEMM_TUNE_LOOKUP_ONLY 1u
+#define SPGEMM_TUNE_REFRESH 2u
+typedef struct {
+    int32_t trials;      /* candidate settings timed (0 when served from the cache) */
+    int32_t from_cache;  /* 1 when the options came from the cache */
+    double default_ms;   /* symbolic + numeric time with the default options */
+    double best_ms;      /* the same with the chosen options */
+} spgemm_tune_report;
+
+spgemm_status spgemm_autotune(int32_t count, const spgemm_csc *A_host, const spgemm_csc *B_host,
+                              spgemm_dtype dt, void *stream, const char *cache_path,
+                              uint32_t tune_flags, spgemm_options *opts_out,
+                              spgemm_tune_report *report_out);
+
+/* Cache key of a workload: the device tag (any text; the autotuner uses
+ * "<architecture>:<compute units>"), the value type and half-octave buckets
+ * of the problem count and of the summed sizes and nonzeros. Host only. */
+spgemm_status spgemm_tune_key(int32_t count, const spgemm_csc *A_host, const spgemm_csc *B_host,
+                              spgemm_dtype dt, const char *device_tag, char *key_out,
+                              int32_t key_len);
+
+/* Cache access, host only: load returns SPGEMM_ERR_NOT_TUNED when the file is
+ * missing, does not parse, or has no entry for the key; store replaces the
+ * key's entry (rewriting a corrupt file). */
+spgemm_status spgemm_tune_cache_load(const char *path, const char *key, spgemm_options *opts_out);
+spgemm_status spgemm_tune_cache_store(const char *path, const char *key,
+                                      const spgemm_options *opts, double ms);
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int32_t spgemm_version(void);

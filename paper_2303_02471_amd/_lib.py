@@ -11,11 +11,14 @@ SPGEMM_F32 = 0
 SPGEMM_F64 = 1
 SPGEMM_VALIDATE = 1
 SPGEMM_ONE_STREAM = 2
+SPGEMM_TUNE_LOOKUP_ONLY = 1
+SPGEMM_TUNE_REFRESH = 2
 
 STATUS = {
     0: "SPGEMM_OK", 1: "SPGEMM_ERR_NULL", 2: "SPGEMM_ERR_SHAPE", 3: "SPGEMM_ERR_CSC",
     4: "SPGEMM_ERR_DTYPE", 5: "SPGEMM_ERR_INDEX_OVERFLOW", 6: "SPGEMM_ERR_NO_MEMORY",
     7: "SPGEMM_ERR_HIP", 8: "SPGEMM_ERR_PLAN", 9: "SPGEMM_ERR_INVALID",
+    10: "SPGEMM_ERR_NOT_TUNED",
 }
 
 # every symbol include/spgemm.h declares
@@ -23,6 +26,7 @@ EXPORTS = (
     "spgemm_symbolic", "spgemm_numeric", "spgemm_backward", "spgemm_batched",
     "spgemm_plan_get_stats", "spgemm_plan_destroy", "spgemm_status_string", "spgemm_version",
     "spgemm_profile_enable", "spgemm_profile_read",
+    "spgemm_autotune", "spgemm_tune_key", "spgemm_tune_cache_load", "spgemm_tune_cache_store",
 )
 
 
@@ -48,6 +52,14 @@ class PlanStats(C.Structure):
                 ("cols_hash", C.c_int32), ("hash_items", C.c_int32), ("esc_groups", C.c_int32),
                 ("nprob", C.c_int32), ("cols_sort", C.c_int32), ("later_max", C.c_int32),
                 ("later_products", C.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("trials", C.c_int32), ("from_cache", C.c_int32), ("default_ms", C.c_double),
+                ("best_ms", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -86,8 +98,16 @@ def lib() -> C.CDLL:
     L.spgemm_profile_read.argtypes = [C.POINTER(KernelTime), C.c_int32, C.POINTER(C.c_int32)]
     L.spgemm_version.argtypes = []
     L.spgemm_version.restype = C.c_int32
+    L.spgemm_autotune.argtypes = [i32, C.POINTER(Csc), C.POINTER(Csc), C.c_int, vp, C.c_char_p,
+                                  C.c_uint32, C.POINTER(Options), C.POINTER(TuneReport)]
+    L.spgemm_tune_key.argtypes = [i32, C.POINTER(Csc), C.POINTER(Csc), C.c_int, C.c_char_p,
+                                  C.c_char_p, i32]
+    L.spgemm_tune_cache_load.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(Options)]
+    L.spgemm_tune_cache_store.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(Options), C.c_double]
     for name in ("spgemm_symbolic", "spgemm_numeric", "spgemm_backward", "spgemm_batched",
-                 "spgemm_plan_get_stats", "spgemm_profile_enable", "spgemm_profile_read"):
+                 "spgemm_plan_get_stats", "spgemm_profile_enable", "spgemm_profile_read",
+                 "spgemm_autotune", "spgemm_tune_key", "spgemm_tune_cache_load",
+                 "spgemm_tune_cache_store"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

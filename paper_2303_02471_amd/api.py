@@ -17,7 +17,8 @@ from . import _lib
 __all__ = [
     "CscTensor", "Plan", "options", "symbolic", "numeric", "matmul", "backward",
     "SpGEMMFunction", "batched_symbolic", "batched_numeric", "batched_matmul",
-    "profile_enable", "profile_read",
+    "profile_enable", "profile_read", "autotune", "tune_key", "tune_cache_load",
+    "tune_cache_store",
 ]
 
 
@@ -270,3 +271,56 @@ def batched_matmul(pairs: Sequence[tuple], opts=None, return_plan: bool = False)
     out = [CscTensor(a.nrows, b.ncols, cp, ri, v)
            for (a, b), cp, ri, v in zip(pairs, colptrs, rowidxs, vals)]
     return (out, plan) if return_plan else out
+
+
+def _descs(pairs: Sequence[tuple], with_val: bool):
+    n = len(pairs)
+    As = (_lib.Csc * max(n, 1))(*[_desc(a, with_val) for a, _ in pairs])
+    Bs = (_lib.Csc * max(n, 1))(*[_desc(b, with_val) for _, b in pairs])
+    return As, Bs
+
+
+def autotune(pairs: Sequence[tuple], dtype=torch.float64, cache_path: Optional[str] = None,
+             refresh: bool = False, lookup_only: bool = False, stream=None):
+    """Tuning options for the products A_i x B_i (one pair: a single product),
+    chosen by timing candidate thresholds in the library (or read from the JSON
+    cache). Returns (options, report dict). The options never change results."""
+    As, Bs = _descs(pairs, True)
+    opts = _lib.Options()
+    rep = _lib.TuneReport()
+    flags = (_lib.SPGEMM_TUNE_REFRESH if refresh else 0) | \
+        (_lib.SPGEMM_TUNE_LOOKUP_ONLY if lookup_only else 0)
+    st = _lib.lib().spgemm_autotune(len(pairs), As, Bs, _code(dtype), _stream(stream),
+                                    cache_path.encode() if cache_path else None, flags,
+                                    C.byref(opts), C.byref(rep))
+    _lib.check(st, "spgemm_autotune")
+    return opts, rep.as_dict()
+
+
+def tune_key(shapes: Sequence[tuple], dtype=torch.float64, device_tag: str = "dev") -> str:
+    """Cache key of a workload given (m, k, n, nnzA, nnzB) per problem (host only)."""
+    n = len(shapes)
+    As = (_lib.Csc * max(n, 1))(*[_lib.Csc(m, k, za, None, None, None)
+                                   for m, k, _, za, _ in shapes])
+    Bs = (_lib.Csc * max(n, 1))(*[_lib.Csc(k, nn, zb, None, None, None)
+                                   for _, k, nn, _, zb in shapes])
+    buf = C.create_string_buffer(512)
+    st = _lib.lib().spgemm_tune_key(n, As, Bs, _code(dtype), device_tag.encode(), buf, 512)
+    _lib.check(st, "spgemm_tune_key")
+    return buf.value.decode()
+
+
+def tune_cache_load(path: str, key: str) -> Optional[_lib.Options]:
+    """Cached options for `key`, or None (missing file or entry, or a file that
+    does not parse)."""
+    opts = _lib.Options()
+    st = _lib.lib().spgemm_tune_cache_load(path.encode(), key.encode(), C.byref(opts))
+    if st == 10:
+        return None
+    _lib.check(st, "spgemm_tune_cache_load")
+    return opts
+
+
+def tune_cache_store(path: str, key: str, opts: _lib.Options, ms: float) -> None:
+    st = _lib.lib().spgemm_tune_cache_store(path.encode(), key.encode(), C.byref(opts), ms)
+    _lib.check(st, "spgemm_tune_cache_store")

@@ -569,6 +569,7 @@ const char *spgemm_status_string(spgemm_status s) {
         case SPGEMM_ERR_HIP: return "HIP runtime error";
         case SPGEMM_ERR_PLAN: return "invalid plan";
         case SPGEMM_ERR_INVALID: return "invalid argument";
+        case SPGEMM_ERR_NOT_TUNED: return "no tuning cache entry for the workload";
     }
     return "unknown status";
 }
