@@ -223,8 +223,9 @@ enum WinMode : int { WIN_DENSE = 0, WIN_HASH_S = 1, WIN_HASH_L = 2, WIN_HASH_XL 
 hipError_t launch_window(const KArgs &a, int mode, int grid, hipStream_t s);
 hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk,
                        long long *totals, hipStream_t s);
-// first column of every product-balanced tile
-hipError_t launch_tiles(const KArgs &a, hipStream_t s);
+// first product of every global column (colprod) and first column of every
+// product-balanced tile (tilestart); bsum holds nbsum scan partials
+hipError_t launch_prod_offsets(const KArgs &a, long long *bsum, int nbsum, hipStream_t s);
 // row of every product (prow), one workgroup per product-balanced tile
 hipError_t launch_expand(const KArgs &a, hipStream_t s);
 // numeric phase of the columns with an output order (one workgroup per
@@ -235,11 +236,6 @@ hipError_t launch_numeric(const KArgs &a, bool f64, hipStream_t s);
 hipError_t launch_numeric_big(const KArgs &a, bool f64, int first, int nbig, hipStream_t s);
 // adds the staged later products of occurrence index k (n of them listed)
 hipError_t launch_layer(const KArgs &a, bool f64, int k, long long n, hipStream_t s);
-// itemoff of the `n` hash columns from bin-list position `first`
-hipError_t launch_item_offsets(const KArgs &a, int first, int n, hipStream_t s);
-// exclusive scan of int32 values into int64
-hipError_t launch_scan_i64(const int32_t *in, int n, long long *bsum, int nbsum, long long *out,
-                           hipStream_t s);
 hipError_t launch_btranspose(const Prob &p, int32_t *rowptr, int32_t *fill, int32_t *colj,
                              int32_t *pos, long long *scratch, int nscratch, hipStream_t s);
 hipError_t launch_backward(const Prob &p, bool f64, const void *av, const void *bv,

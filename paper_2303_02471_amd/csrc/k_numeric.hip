@@ -27,27 +27,6 @@
 
 namespace spg {
 
-// ---------------------------------------------------------------- tiles
-// thread per global column g: g is the first column of the tiles t with
-// P(g-1) < t * kProdTile <= P(g) (P = first product of a column)
-__global__ __launch_bounds__(kBlock) void k_tiles(KArgs a) {
-    const int g = blockIdx.x * kBlock + threadIdx.x;
-    if (g >= a.ncols) return;
-    // tile t starts at the first column with P >= t * kProdTile: column g
-    // starts the tiles with P(g - 1) < t * kProdTile <= P(g)
-    const long long t_hi = a.colprod[g] / kProdTile;
-    const long long t_lo = g == 0 ? 0 : a.colprod[g - 1] / kProdTile + 1;
-    for (long long t = t_lo; t <= t_hi && t < a.nptiles; ++t) a.tilestart[t] = g;
-    if (g == a.ncols - 1)  // tiles after the last column's first product are empty
-        for (long long t = t_hi + 1; t <= a.nptiles; ++t) a.tilestart[t] = a.ncols;
-}
-
-hipError_t launch_tiles(const KArgs &a, hipStream_t s) {
-    if (a.ncols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tiles, dim3(ceil_div(a.ncols, kBlock)), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
 // Calls f(pid, d, j0, j1) for the problem segments of tile columns [g0, g1).
 template <typename F>
 __device__ __forceinline__ void for_each_segment(const KArgs &a, int g0, int g1, F &&f) {
@@ -128,28 +107,6 @@ __global__ __launch_bounds__(kBlock) void k_expand(KArgs a) {
 hipError_t launch_expand(const KArgs &a, hipStream_t s) {
     if (a.nptiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_expand, dim3(a.nptiles), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- window offsets
-// one thread per hash column: exclusive prefix of its windows' distinct rows
-__global__ __launch_bounds__(kBlock) void k_item_offsets(KArgs a, int first, int n) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int g = a.binlist[first + i].x;
-    const int W = a.binw[g] >> 8;
-    const int it0 = a.colitem[g];
-    int run = 0;
-    for (int w = 0; w < W; ++w) {
-        const int c = a.itemcnt[it0 + w];
-        a.itemoff[it0 + w] = run;
-        run += c;
-    }
-}
-
-hipError_t launch_item_offsets(const KArgs &a, int first, int n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_item_offsets, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, a, first, n);
     return hipGetLastError();
 }
 

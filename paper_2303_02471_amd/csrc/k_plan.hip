@@ -237,10 +237,13 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
     if (tid == 0 && !room && blockIdx.x == 0) atomicOr(&a.hdr->err, ERR_ITEMCAP);
 }
 
-// ---------------------------------------------------------------- scan of nnz
-// Exclusive prefix sum of the per-column counts over all problems, in 64-bit,
-// in three launches: block sums, a scan of the block sums, and the final
-// per-block scan that writes every problem's column pointers.
+// ---------------------------------------------------------------- scans
+// Exclusive prefix sums in 64-bit, in two launches: per-block sums, then a
+// down-sweep in which every block adds up the sums of the blocks before it
+// itself (at most a few thousand values) and scans its kScanBlock elements.
+// The down-sweeps also do per-element follow-up work: the product-space scan
+// marks the tile starts, the column-pointer scan computes the hash windows'
+// offsets.
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ in, int n,
                                                         long long *__restrict__ bsum) {
     __shared__ long long s[kBlock / 64];
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restric
         int i = base + u * kBlock + threadIdx.x;
         if (i < n) v += in[i];
     }
-    // wave reduction through 32-bit halves would overflow; reduce in LDS
+    // wave reduction through 32-bit halves
     for (int d = 32; d >= 1; d >>= 1) {
         int lo = (int)(unsigned)v, hi = (int)(unsigned)((unsigned long long)v >> 32);
         lo = __builtin_amdgcn_ds_bpermute((lane_id() ^ d) << 2, lo);
@@ -267,50 +270,41 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restric
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_top(long long *bsum, int nblk) {
-    __shared__ long long s[1024];
-    __shared__ long long carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < nblk; base += 1024) {
-        int i = base + threadIdx.x;
-        long long v = i < nblk ? bsum[i] : 0;
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {
-            long long t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-            __syncthreads();
-            s[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < nblk) bsum[i] = carry + s[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += s[1023];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) bsum[nblk] = carry;
-}
+// Block-level scan of kScanBlock int32 values starting at `base` (zero past
+// n). Returns, per thread, the exclusive prefixes of its PER consecutive
+// elements (global: including the sums of the earlier blocks) and the total
+// of all blocks up to this one.
+struct ScanOut {
+    static constexpr int PER = kScanBlock / kBlock;
+    long long pre[PER];
+    long long block_end;  // prefix after this block's last element
+};
 
-// Final pass. For one problem the int32 column pointers are written directly
-// (with an overflow check); for several problems the 64-bit global prefix is
-// kept in gcp and k_scan_finish cuts it per problem.
-__global__ __launch_bounds__(kBlock) void k_scan_down(KArgs a, long long *__restrict__ gcp,
-                                                      const long long *__restrict__ bsum,
-                                                      long long *__restrict__ totals) {
-    __shared__ long long s[kScanBlock];
-    const int n = a.ncols;
+__device__ __forceinline__ void block_scan_down(const int32_t *__restrict__ in, int n,
+                                                const long long *__restrict__ bsum,
+                                                long long *s, ScanOut &o) {
+    constexpr int PER = ScanOut::PER;
     const int base = blockIdx.x * kScanBlock;
-    for (int u = 0; u < kScanBlock / kBlock; ++u) {
+    // sums of the earlier blocks
+    long long before = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kBlock) before += bsum[b];
+    s[threadIdx.x] = before;
+    __syncthreads();
+    for (int d = kBlock / 2; d >= 1; d >>= 1) {
+        if ((int)threadIdx.x < d) s[threadIdx.x] += s[threadIdx.x + d];
+        __syncthreads();
+    }
+    before = s[0];
+    __syncthreads();
+    for (int u = 0; u < PER; ++u) {
         int i = base + u * kBlock + threadIdx.x;
-        s[u * kBlock + threadIdx.x] = i < n ? a.gnnz[i] : 0;
+        s[u * kBlock + threadIdx.x] = i < n ? in[i] : 0;
     }
     __syncthreads();
-    // thread t scans elements [4t, 4t+4), then a scan over threads
-    constexpr int PER = kScanBlock / kBlock;
-    long long loc[PER], run = 0;
+    long long run = 0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        loc[u] = run;
+        o.pre[u] = run;
         run += s[threadIdx.x * PER + u];
     }
     __syncthreads();
@@ -322,22 +316,49 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(KArgs a, long long *__rest
         s[threadIdx.x] += t;
         __syncthreads();
     }
-    const long long off = bsum[blockIdx.x] + s[threadIdx.x] - run;
+    const long long off = before + s[threadIdx.x] - run;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) o.pre[u] += off;
+    o.block_end = before + s[kBlock - 1];
+}
+
+// C column pointers from the per-column counts, and the row-window offsets of
+// the hash columns. For one problem the int32 column pointers are written
+// directly (with an overflow check); for several problems the 64-bit global
+// prefix is kept in gcp and k_scan_finish cuts it per problem.
+__global__ __launch_bounds__(kBlock) void k_scan_down(KArgs a, long long *__restrict__ gcp,
+                                                      const long long *__restrict__ bsum,
+                                                      long long *__restrict__ totals) {
+    __shared__ long long s[kScanBlock];
+    const int n = a.ncols;
+    ScanOut o;
+    block_scan_down(a.gnnz, n, bsum, s, o);
     int err = 0;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        int i = base + threadIdx.x * PER + u;
+    for (int u = 0; u < ScanOut::PER; ++u) {
+        const int i = blockIdx.x * kScanBlock + threadIdx.x * ScanOut::PER + u;
         if (i >= n) break;
-        long long v = off + loc[u];
+        const long long v = o.pre[u];
         if (a.nprob == 1) {
             if (v > 0x7fffffffll) err = ERR_NNZOVF;
             a.single.ccp[i] = (int32_t)v;
         } else {
             gcp[i] = v;
         }
+        // distinct rows of a windowed hash column's earlier windows
+        const int W = a.binw[i] >> 8;
+        if (W > 1) {
+            const int it0 = a.colitem[i];
+            int r = 0;
+            for (int w = 0; w < W; ++w) {
+                const int c = a.itemcnt[it0 + w];
+                a.itemoff[it0 + w] = r;
+                r += c;
+            }
+        }
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-        long long total = bsum[gridDim.x];
+        const long long total = o.block_end;
         if (a.nprob == 1) {
             if (total > 0x7fffffffll) err = ERR_NNZOVF;
             a.single.ccp[n] = (int32_t)total;
@@ -367,98 +388,64 @@ __global__ __launch_bounds__(kBlock) void k_scan_finish(KArgs a, const long long
     }
 }
 
+// First product of every global column (exclusive scan of Op_j), and the
+// product-balanced tiles: column g starts the tiles t with
+// P(g - 1) < t * kProdTile <= P(g); the tiles after the last column's first
+// product are empty.
+__global__ __launch_bounds__(kBlock) void k_prod_down(KArgs a, const long long *__restrict__ bsum) {
+    __shared__ long long s[kScanBlock];
+    const int n = a.ncols;
+    ScanOut o;
+    block_scan_down(a.op, n, bsum, s, o);
+#pragma unroll
+    for (int u = 0; u < ScanOut::PER; ++u) {
+        const int g = blockIdx.x * kScanBlock + threadIdx.x * ScanOut::PER + u;
+        if (g >= n) break;
+        const long long pg = o.pre[u];
+        a.colprod[g] = pg;
+        const long long t_hi = pg / kProdTile;
+        const long long t_lo = g == 0 ? 0 : (pg - a.op[g - 1]) / kProdTile + 1;
+        for (long long t = t_lo; t <= t_hi && t < a.nptiles; ++t) a.tilestart[t] = g;
+        if (g == n - 1)
+            for (long long t = t_hi + 1; t <= a.nptiles; ++t) a.tilestart[t] = n;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) a.colprod[n] = o.block_end;
+}
+
 // generic exclusive scan of int32 values into int32 (in place allowed)
 __global__ __launch_bounds__(kBlock) void k_scan_down_i32(const int32_t *in, int n,
                                                           const long long *__restrict__ bsum,
                                                           int32_t *out) {
     __shared__ long long s[kScanBlock];
-    const int base = blockIdx.x * kScanBlock;
-    for (int u = 0; u < kScanBlock / kBlock; ++u) {
-        int i = base + u * kBlock + threadIdx.x;
-        s[u * kBlock + threadIdx.x] = i < n ? in[i] : 0;
-    }
-    __syncthreads();
-    constexpr int PER = kScanBlock / kBlock;
-    long long loc[PER], run = 0;
+    ScanOut o;
+    block_scan_down(in, n, bsum, s, o);
+    __syncthreads();  // every block element is read before any is written (in place)
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        loc[u] = run;
-        run += s[threadIdx.x * PER + u];
-    }
-    __syncthreads();
-    s[threadIdx.x] = run;
-    __syncthreads();
-    for (int d = 1; d < kBlock; d <<= 1) {
-        long long t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    const long long off = bsum[blockIdx.x] + s[threadIdx.x] - run;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        int i = base + threadIdx.x * PER + u;
-        if (i < n) out[i] = (int32_t)(off + loc[u]);
-    }
-}
-
-// exclusive scan of int32 values into int64 (block sums already scanned)
-__global__ __launch_bounds__(kBlock) void k_scan_down_i64(const int32_t *__restrict__ in, int n,
-                                                          const long long *__restrict__ bsum,
-                                                          long long *__restrict__ out) {
-    __shared__ long long s[kScanBlock];
-    const int base = blockIdx.x * kScanBlock;
-    for (int u = 0; u < kScanBlock / kBlock; ++u) {
-        int i = base + u * kBlock + threadIdx.x;
-        s[u * kBlock + threadIdx.x] = i < n ? in[i] : 0;
-    }
-    __syncthreads();
-    constexpr int PER = kScanBlock / kBlock;
-    long long loc[PER], run = 0;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        loc[u] = run;
-        run += s[threadIdx.x * PER + u];
-    }
-    __syncthreads();
-    s[threadIdx.x] = run;
-    __syncthreads();
-    for (int d = 1; d < kBlock; d <<= 1) {
-        long long t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    const long long off = bsum[blockIdx.x] + s[threadIdx.x] - run;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        int i = base + threadIdx.x * PER + u;
-        if (i < n) out[i] = off + loc[u];
+    for (int u = 0; u < ScanOut::PER; ++u) {
+        const int i = blockIdx.x * kScanBlock + threadIdx.x * ScanOut::PER + u;
+        if (i < n) out[i] = (int32_t)o.pre[u];
     }
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_scan_i64(const int32_t *in, int n, long long *bsum, int nbsum, long long *out,
-                           hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int nblk = ceil_div(n, kScanBlock);
-    if (nblk + 1 > nbsum) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kBlock), 0, s, in, n, bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nblk);
-    hipLaunchKernelGGL(k_scan_down_i64, dim3(nblk), dim3(kBlock), 0, s, in, n,
-                       (const long long *)bsum, out);
-    return hipGetLastError();
-}
-
 hipError_t launch_scan_i32(const int32_t *in, int n, long long *bsum, int nbsum, int32_t *out,
                            hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int nblk = ceil_div(n, kScanBlock);
-    if (nblk + 1 > nbsum) return hipErrorInvalidValue;
+    if (nblk > nbsum) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kBlock), 0, s, in, n, bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nblk);
     hipLaunchKernelGGL(k_scan_down_i32, dim3(nblk), dim3(kBlock), 0, s, in, n,
                        (const long long *)bsum, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_prod_offsets(const KArgs &a, long long *bsum, int nbsum, hipStream_t s) {
+    if (a.ncols <= 0) return hipSuccess;
+    const int nblk = ceil_div(a.ncols, kScanBlock);
+    if (nblk > nbsum) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kBlock), 0, s, (const int32_t *)a.op,
+                       a.ncols, bsum);
+    hipLaunchKernelGGL(k_prod_down, dim3(nblk), dim3(kBlock), 0, s, a, (const long long *)bsum);
     return hipGetLastError();
 }
 
@@ -479,7 +466,6 @@ hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk
     if (a.ncols > 0) {
         hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kBlock), 0, s,
                            (const int32_t *)a.gnnz, a.ncols, bsum);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nblk);
         hipLaunchKernelGGL(k_scan_down, dim3(nblk), dim3(kBlock), 0, s, a, gcp,
                            (const long long *)bsum, totals);
     }

@@ -331,15 +331,6 @@ hipError_t ensure_side_streams(spgemm_plan p) {
     return hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
 }
 
-// bin-list positions of the dense and hash columns
-void list_range(const Hdr &h, int &first, int &n, int &first_hash, int &nhash) {
-    first = 0;
-    for (int b = 0; b < BIN_DENSE; ++b) first += h.bin_count[b];
-    first_hash = first + h.bin_count[BIN_DENSE];
-    nhash = 0;
-    for (int b = BIN_HASH_S; b < NBINS; ++b) nhash += h.bin_count[b];
-    n = h.bin_count[BIN_DENSE] + nhash;
-}
 
 // side stream i, or the caller's stream when every kind runs on it
 hipStream_t side(spgemm_plan p, int i, hipStream_t s) {
@@ -365,43 +356,46 @@ hipError_t join(spgemm_plan p, hipStream_t s) {
     return hipSuccess;
 }
 
-// Symbolic accumulators. The kinds work on disjoint columns: the sort-merge
-// groups run on the caller's stream, dense + small hash, large hash and
-// extra-large hash on three side streams, so their latencies overlap.
+// Symbolic accumulators. The kinds work on disjoint columns and run
+// concurrently so their latencies overlap: the hash row windows (few, long
+// work items) start first on their own side stream, the two larger sorts
+// share a second one, dense and the smaller hash classes a third, and the
+// sort-merge groups with the two smaller sorts run on the caller's stream.
 hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream_t s) {
     const Hdr &h = p->hdr_host;
     hipError_t e;
     if ((e = fork(p, s))) return e;
-    {
-        ProfScope ps("esc_symbolic", s);
-        if ((e = launch_esc(a, ceil_div(esc_groups(h), kBlock / 64), s))) return e;
+    static const char *names[kHashBins] = {"hash_s_symbolic", "hash_l_symbolic",
+                                           "hash_xl_symbolic"};
+    for (int c = kHashBins - 1; c >= 0; --c) {
+        if (!h.item_count[c]) continue;
+        hipStream_t sc = side(p, c == kHashBins - 1 ? 2 : 0, s);
+        ProfScope ps(names[c], sc);
+        if ((e = launch_window(a, WIN_HASH_S + c, h.item_count[c], sc))) return e;
     }
     static const char *snames[kSortBins] = {"sort512_symbolic", "sort1k_symbolic",
                                             "sort2k_symbolic", "sort4k_symbolic"};
-    for (int c = 0; c < kSortBins; ++c) {
+    for (int c = kSortBins - 1; c >= 2; --c) {
         const int n = h.bin_count[BIN_SORT0 + c];
         if (!n) continue;
-        // small sorts with the sort-merge groups, the two larger on side streams
-        hipStream_t sc = c < 2 ? s : side(p, c - 1, s);
-        ProfScope ps(snames[c], sc);
-        if ((e = launch_sort(a, c, p->wide_keys, n, sc))) return e;
+        ProfScope ps(snames[c], side(p, 1, s));
+        if ((e = launch_sort(a, c, p->wide_keys, n, side(p, 1, s)))) return e;
     }
     {
         ProfScope ps("dense_symbolic", side(p, 0, s));
         if ((e = launch_window(a, WIN_DENSE, h.bin_count[BIN_DENSE], side(p, 0, s)))) return e;
     }
-    static const char *names[kHashBins] = {"hash_s_symbolic", "hash_l_symbolic",
-                                           "hash_xl_symbolic"};
-    for (int c = 0; c < kHashBins; ++c) {
-        if (!h.item_count[c]) continue;
-        ProfScope ps(names[c], side(p, c, s));
-        if ((e = launch_window(a, WIN_HASH_S + c, h.item_count[c], side(p, c, s)))) return e;
+    {
+        ProfScope ps("esc_symbolic", s);
+        if ((e = launch_esc(a, ceil_div(esc_groups(h), kBlock / 64), s))) return e;
     }
-    if ((e = join(p, s))) return e;
-    int first, n, first_hash, nhash;
-    list_range(h, first, n, first_hash, nhash);
-    ProfScope ps("window_offsets", s);
-    return launch_item_offsets(a, first_hash, nhash, s);
+    for (int c = 0; c < 2; ++c) {
+        const int n = h.bin_count[BIN_SORT0 + c];
+        if (!n) continue;
+        ProfScope ps(snames[c], s);
+        if ((e = launch_sort(a, c, p->wide_keys, n, s))) return e;
+    }
+    return join(p, s);
 }
 
 // Numeric: one launch over the column tiles, then one small launch per
@@ -453,11 +447,6 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         const KArgs a = make_args(p);
         { ProfScope ps("classify", s); SPG_TRY(launch_classify(a, s)); }
         { ProfScope ps("place", s); SPG_TRY(launch_place(a, s)); }
-        {
-            // first product of every column: exclusive scan of Op_j
-            ProfScope ps("product_offsets", s);
-            SPG_TRY(launch_scan_i64(p->op, p->ncols, p->bsum, p->nbsum, p->colprod, s));
-        }
         // the bin sizes fix the grid of every accumulator launch: read them once
         SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, sizeof(Hdr), hipMemcpyDeviceToHost, s));
         SPG_TRY(hipStreamSynchronize(s));
@@ -496,7 +485,11 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         p->later_cap = (long long)std::min<size_t>(P, 0x7fffffff);
         if (p->ncols > 0) {
             const KArgs al = make_args(p);
-            { ProfScope ps("tiles", s); SPG_TRY(launch_tiles(al, s)); }
+            {
+                // first product of every column (exclusive scan of Op_j), tiles
+                ProfScope ps("product_offsets", s);
+                SPG_TRY(launch_prod_offsets(al, p->bsum, p->nbsum, s));
+            }
             { ProfScope ps("expand", s); SPG_TRY(launch_expand(al, s)); }
             SPG_TRY(launch_symbolic_accumulators(p, al, s));
             ProfScope ps("scan", s);
