@@ -77,31 +77,27 @@ def csc_bytes(n, nnz, vb):
     return 4 * (n + 1) + (4 + vb) * nnz
 
 
-def per_column_work(A, B, m_dense_limit=4096, t_esc=256, t_dense=512, hash_cap=4096,
-                    t_sort=4096):
+def per_column_work(A, B, t_esc=256, t_block=4096):
     """Host accounting of the per-column work and of the accumulator each
-    column goes to (the library's default rule), for algorithmic byte counts."""
+    column goes to (the library's rule), for algorithmic byte counts."""
     import numpy as np
     za = np.diff(A.colptr.astype(np.int64))
     nb = np.diff(B.colptr.astype(np.int64))
     colB = np.repeat(np.arange(B.ncols), nb)
     op = np.bincount(colB, weights=za[B.rowidx], minlength=B.ncols).astype(np.int64)
-    esc = (op > 0) & (op <= t_esc)
-    dense = (op > 0) & ~esc & (A.nrows <= m_dense_limit) & (op >= t_dense)
-    srt = (op > 0) & ~esc & ~dense & (op <= t_sort)
-    hsh = (op > 0) & ~esc & ~dense & ~srt
-    # workgroup sort class: N = power of two >= op, at least 512
-    N = 2 ** np.ceil(np.log2(np.maximum(op, 512)))
-    # hash table class: windows W = ceil(op / cap); table = power of two
-    # >= 2 ceil(op / W), in [64, 8192]; classes <= 1024, <= 4096, larger
-    W = np.maximum(1, -(-op // hash_cap))
-    per = -(-op // W)
-    H = np.clip(2 ** np.ceil(np.log2(np.maximum(2 * per, 1))), 64, 8192)
-    return op, nb, {"esc": esc, "dense": dense,
-                    "sort512": srt & (N == 512), "sort1k": srt & (N == 1024),
-                    "sort2k": srt & (N == 2048), "sort4k": srt & (N == 4096),
-                    "hash_s": hsh & (H <= 1024), "hash_l": hsh & (H > 1024) & (H <= 4096),
-                    "hash_xl": hsh & (H > 4096)}
+    esc_max = 4
+    while esc_max < t_esc:
+        esc_max *= 2
+    esc = (op > 0) & (op <= esc_max)
+    srt = (op > esc_max) & (op <= t_block)
+    blk = op > max(esc_max, t_block)
+    return op, nb, {"esc": esc,
+                    "sort512": srt & (op <= 512), "sort1k": srt & (op > 512) & (op <= 1024),
+                    "sort2k": srt & (op > 1024) & (op <= 2048),
+                    "sort4k": srt & (op > 2048) & (op <= 4096),
+                    "block512": blk & (op <= 512), "block1k": blk & (op > 512) & (op <= 1024),
+                    "block2k": blk & (op > 1024) & (op <= 2048),
+                    "block4k": blk & (op > 2048) & (op <= 4096), "block_xl": blk & (op > 4096)}
 
 
 def kernel_bytes(op, nb, nnzc, sel, vb):
@@ -153,8 +149,9 @@ def main():
                                       cache_path=os.path.join(td, "tune.json"))
         if args.one_stream:
             opts.flags |= 2
-        tuning = {"t_esc": opts.t_esc, "t_sort": opts.t_sort, "hash_cap": opts.hash_cap,
-                  "t_dense": opts.t_dense, "trials": trep["trials"],
+        tuning = {"t_esc": opts.t_esc, "t_block": opts.t_block, "t_split": opts.t_split,
+                  "hash_cap": opts.hash_cap,
+                  "dense_rows": opts.dense_rows, "trials": trep["trials"],
                   "default_ms": round(trep["default_ms"], 4), "tuned_ms": round(trep["best_ms"], 4)}
         log(f"autotune: {tuning}")
     plan, colptr, nnz = api.symbolic(At, Bt, torch.float64, opts)
@@ -188,22 +185,20 @@ def main():
 
     # ------------------------------------------------------------ roofline of the dominant kernel
     nnzc = np.diff(colptr.cpu().numpy().astype(np.int64))
-    t_sort = opts.t_sort if opts.t_sort else 4096
-    op, nb, bins = per_column_work(A, B, t_esc=opts.t_esc or 256, hash_cap=opts.hash_cap or 4096,
-                                   t_sort=t_sort if t_sort > 0 else 0,
-                                   t_dense=opts.t_dense or 512)
+    t_block = opts.t_block if opts.t_block else 4096
+    op, nb, bins = per_column_work(A, B, t_esc=opts.t_esc or 256,
+                                   t_block=t_block if t_block > 0 else 0)
     kbytes = {}
     for name in bins:
         num, sym = kernel_bytes(op, nb, nnzc, bins[name], vb)
         kbytes[f"{name}_numeric"] = num
         kbytes[f"{name}_symbolic"] = sym
-    # the tiles write columns of at most 2048 products without row windows
-    # in output order; the other columns go to the per-column numeric kernel
-    hash_cols = bins["hash_s"] | bins["hash_l"] | bins["hash_xl"]
-    windowed = hash_cols & (op > (opts.hash_cap or 4096))
-    ordered = (op > 0) & (op <= 2048) & ~windowed
-    kbytes["numeric"] = kernel_bytes(op, nb, nnzc, ordered, vb)[0]
-    kbytes["numeric_big"] = kernel_bytes(op, nb, nnzc, (op > 0) & ~ordered, vb)[0]
+    # the tiles do the columns of at most t_split products, the chunked
+    # kernel the others
+    t_split = opts.t_split if opts.t_split else 2048
+    small = (op > 0) & (op <= t_split) if t_split > 0 else (op > 0)
+    kbytes["numeric"] = kernel_bytes(op, nb, nnzc, small, vb)[0]
+    kbytes["numeric_big"] = kernel_bytes(op, nb, nnzc, (op > 0) & ~small, vb)[0]
     # expansion: (A column start, length) per stored B entry, A row read and
     # product row written per product
     kbytes["expand"] = 8 * B.nnz + 8 * int(op.sum())

@@ -87,23 +87,28 @@ typedef struct spgemm_plan_s *spgemm_plan;
 
 /*
  * Tuning options. Results never depend on them: they only choose which
- * accumulator handles a column (the role of the paper's switch threshold t,
- * Section 3.3, and of its hash-size adaptation, Section 3.2). A zero field
- * takes the library default.
+ * accumulator handles a column and how the work is cut (the role of the
+ * paper's switch threshold t, Section 3.3, and of its hash-size adaptation,
+ * Section 3.2). A zero field takes the library default.
  *   t_esc       columns with at most this many products go to the wavefront
  *               sort-merge (ESC, Section 4) accumulator; 4..256, rounded up
  *               to a power of two; default 256.
- *   t_dense     columns above t_esc with at least this many products go to
- *               the dense LDS accumulator (SPA, Section 2.2) when A has at
- *               most dense_rows rows; default 512.
- *   dense_rows  row limit of the dense LDS accumulator, 64..4096; default 4096.
- *   hash_cap    planned distinct rows per LDS hash-table window, 128..4096;
- *               default 4096. Columns with more products are split into
- *               row windows.
- *   t_sort      the remaining columns with at most this many products go to
- *               the workgroup sort-merge accumulator, the others to the hash
- *               accumulator (HASH, Section 3.2); -1 (none) or 1..4096;
- *               default 4096.
+ *   t_block     the other columns with at most this many products go to the
+ *               workgroup sort-merge accumulator, the rest to the workgroup
+ *               hash accumulator (HASH, Section 3.2, with direct indexing for
+ *               row windows that fit); -1 (none) or 1..4096; default 4096.
+ *   t_dense     hash-accumulator columns with at least this many products
+ *               may accumulate a row window by direct indexing (the SPA of
+ *               Section 2.2) when its row span fits the LDS table; >= 1;
+ *               default 1.
+ *   dense_rows  largest row span of a directly indexed window; 0 = the
+ *               table's capacity.
+ *   hash_cap    planned distinct rows per row window of the workgroup
+ *               accumulator (columns with more products are cut into row
+ *               windows); 16..1048576, or 0 = half the LDS table.
+ *   t_split     numeric phase: columns with more products than this are
+ *               split over several workgroups (chunks of stored B entries);
+ *               >= 1, -1 = never; default 2048.
  */
 typedef struct {
     int32_t t_esc;
@@ -111,26 +116,27 @@ typedef struct {
     int32_t dense_rows;
     int32_t hash_cap;
     uint32_t flags;
-    int32_t t_sort;
+    int32_t t_split;
+    int32_t t_block;
 } spgemm_options;
-
 /* Work statistics of a plan, for reports and tests. */
 typedef struct {
     int64_t total_products;     /* sum of Op_j (Section 3.1) */
     int64_t nnz_c;              /* total stored entries of C */
     int32_t ncols;              /* columns of C (summed over problems) */
     int32_t cols_empty;         /* columns with no product */
-    int32_t cols_esc;           /* columns in the sort-merge accumulator */
-    int32_t cols_dense;         /* columns in the dense accumulator */
-    int32_t cols_hash;          /* columns in the hash accumulator */
-    int32_t hash_items;         /* row windows of hash columns */
+    int32_t cols_esc;           /* columns in the wavefront sort-merge accumulator */
+    int32_t cols_block;         /* columns in the workgroup hash accumulator */
     int32_t esc_groups;         /* wavefront groups of sort-merge columns */
     int32_t nprob;              /* problems in the plan */
-    int32_t cols_sort;          /* columns in the workgroup sort-merge accumulator */
     int32_t later_max;          /* most products adding into one output entry, minus 1 */
+    int32_t pad;
     int64_t later_products;     /* products that are not the first of their output entry */
+    int32_t cols_direct;        /* workgroup columns with a directly indexed row window */
+    int32_t cols_hash;          /* workgroup columns with a hash-table row window */
+    int32_t cols_split;         /* workgroup columns with a window split after overflowing */
+    int32_t cols_sort;          /* columns in the workgroup sort-merge accumulator */
 } spgemm_plan_stats;
-
 /*
  * Symbolic phase of C = A x B (structure only).
  *   A, B        host pointers to descriptors of device arrays; values unused.
@@ -208,7 +214,8 @@ spgemm_status spgemm_profile_enable(int32_t on);
  * (host pointers). Waits for the recorded events. */
 spgemm_status spgemm_profile_read(spgemm_kernel_time *out_host, int32_t max, int32_t *n_host);
 
-/* Statistics of a plan after its symbolic phase. */
+/* Statistics of a plan after its symbolic phase (reads per-column flags back
+ * from the device: synchronous). */
 spgemm_status spgemm_plan_get_stats(spgemm_plan plan, spgemm_plan_stats *out);
 
 /* Frees the plan and its workspace (synchronises with the plan's last stream). */

@@ -43,15 +43,16 @@ class Csc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("t_esc", C.c_int32), ("t_dense", C.c_int32), ("dense_rows", C.c_int32),
-                ("hash_cap", C.c_int32), ("flags", C.c_uint32), ("t_sort", C.c_int32)]
+                ("hash_cap", C.c_int32), ("flags", C.c_uint32), ("t_split", C.c_int32),
+                ("t_block", C.c_int32)]
 
 
 class PlanStats(C.Structure):
     _fields_ = [("total_products", C.c_int64), ("nnz_c", C.c_int64), ("ncols", C.c_int32),
-                ("cols_empty", C.c_int32), ("cols_esc", C.c_int32), ("cols_dense", C.c_int32),
-                ("cols_hash", C.c_int32), ("hash_items", C.c_int32), ("esc_groups", C.c_int32),
-                ("nprob", C.c_int32), ("cols_sort", C.c_int32), ("later_max", C.c_int32),
-                ("later_products", C.c_int64)]
+                ("cols_empty", C.c_int32), ("cols_esc", C.c_int32), ("cols_block", C.c_int32),
+                ("esc_groups", C.c_int32), ("nprob", C.c_int32), ("later_max", C.c_int32),
+                ("pad", C.c_int32), ("later_products", C.c_int64), ("cols_direct", C.c_int32),
+                ("cols_hash", C.c_int32), ("cols_split", C.c_int32), ("cols_sort", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -70,11 +70,12 @@ class CscTensor:
 
 
 def options(t_esc: int = 0, t_dense: int = 0, dense_rows: int = 0, hash_cap: int = 0,
-            t_sort: int = 0, validate: bool = False, one_stream: bool = False) -> _lib.Options:
+            t_split: int = 0, t_block: int = 0, validate: bool = False,
+            one_stream: bool = False) -> _lib.Options:
     """Tuning options (zero = library default). They never change results."""
     flags = (_lib.SPGEMM_VALIDATE if validate else 0) | \
         (_lib.SPGEMM_ONE_STREAM if one_stream else 0)
-    return _lib.Options(t_esc, t_dense, dense_rows, hash_cap, flags, t_sort)
+    return _lib.Options(t_esc, t_dense, dense_rows, hash_cap, flags, t_split, t_block)
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:

@@ -6,15 +6,15 @@
 // Options only decide which accumulator takes a column; every accumulator
 // computes Algorithm 1's values bit for bit, so tuning never changes results.
 //
-// Search: coordinate descent from the defaults over t_esc, t_sort, hash_cap
-// and t_dense; a candidate replaces the current best when it is at least 2%
+// Search: coordinate descent from the defaults over t_esc, t_block, t_split,
+// hash_cap and dense_rows; a candidate replaces the current best when it is at least 2%
 // faster. Each candidate is timed as symbolic + numeric, best of three runs
 // after one warm-up run.
 //
 // Cache file: {"spgemm_tune_cache": 1, "entries": [{"key": "...", "t_esc": ..,
-// "t_dense": .., "dense_rows": .., "hash_cap": .., "t_sort": .., "ms": ..},
-// ...]}. A file that does not parse as such is treated as empty and is
-// rewritten by the next store.
+// "t_dense": .., "dense_rows": .., "hash_cap": .., "t_split": .., "t_block": ..,
+// "ms": ..}, ...]}. A file that does not parse as such is treated as empty and
+// is rewritten by the next store.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -115,7 +115,8 @@ struct Reader {
             else if (k == "t_dense") f = &e.o.t_dense;
             else if (k == "dense_rows") f = &e.o.dense_rows;
             else if (k == "hash_cap") f = &e.o.hash_cap;
-            else if (k == "t_sort") f = &e.o.t_sort;
+            else if (k == "t_split") f = &e.o.t_split;
+            else if (k == "t_block") f = &e.o.t_block;
             if (f || k == "ms") {
                 if (!num(v)) return false;
                 if (f) {
@@ -202,9 +203,9 @@ bool save_cache(const char *path, const std::vector<Entry> &es) {
         const Entry &e = es[i];
         std::fprintf(f,
                      "%s\n  {\"key\": %s, \"t_esc\": %d, \"t_dense\": %d, \"dense_rows\": %d, "
-                     "\"hash_cap\": %d, \"t_sort\": %d, \"ms\": %.6g}",
+                     "\"hash_cap\": %d, \"t_split\": %d, \"t_block\": %d, \"ms\": %.6g}",
                      i ? "," : "", quote(e.key).c_str(), e.o.t_esc, e.o.t_dense, e.o.dense_rows,
-                     e.o.hash_cap, e.o.t_sort, e.ms);
+                     e.o.hash_cap, e.o.t_split, e.o.t_block, e.ms);
     }
     std::fprintf(f, "\n]}\n");
     const bool good = std::fflush(f) == 0;
@@ -310,11 +311,19 @@ struct Trial {
 spgemm_options defaults() {
     spgemm_options o{};
     o.t_esc = 256;
-    o.t_dense = 512;
-    o.dense_rows = 4096;
-    o.hash_cap = 4096;
-    o.t_sort = 4096;
+    o.t_dense = 1;
+    o.dense_rows = 0;
+    o.hash_cap = 0;
+    o.t_split = 2048;
+    o.t_block = 4096;
     return o;
+}
+
+// option values a cache entry may hold (the ranges spgemm_symbolic accepts)
+bool usable(const spgemm_options &o) {
+    return o.t_esc >= 4 && o.t_esc <= 256 && o.t_dense >= 1 && o.dense_rows >= 0 &&
+           (o.hash_cap == 0 || (o.hash_cap >= 16 && o.hash_cap <= (1 << 20))) &&
+           (o.t_split == -1 || o.t_split >= 1) && o.t_block >= -1 && o.t_block <= 4096;
 }
 
 }  // namespace
@@ -351,17 +360,14 @@ spgemm_status spgemm_tune_cache_load(const char *path, const char *key, spgemm_o
     for (const Entry &e : es) {
         if (e.key != key) continue;
         // values outside the options' ranges make the entry unusable
-        const spgemm_options &o = e.o;
-        if (o.t_esc < 4 || o.t_esc > 256 || o.t_dense < 1 || o.dense_rows < 64 ||
-            o.dense_rows > 4096 || o.hash_cap < 128 || o.hash_cap > 4096 ||
-            (o.t_sort != -1 && (o.t_sort < 1 || o.t_sort > 4096)))
-            return SPGEMM_ERR_NOT_TUNED;
+        if (!usable(e.o)) return SPGEMM_ERR_NOT_TUNED;
         *opts_out = defaults();
         opts_out->t_esc = e.o.t_esc;
         opts_out->t_dense = e.o.t_dense;
         opts_out->dense_rows = e.o.dense_rows;
         opts_out->hash_cap = e.o.hash_cap;
-        opts_out->t_sort = e.o.t_sort;
+        opts_out->t_split = e.o.t_split;
+        opts_out->t_block = e.o.t_block;
         return SPGEMM_OK;
     }
     return SPGEMM_ERR_NOT_TUNED;
@@ -432,11 +438,12 @@ spgemm_status spgemm_autotune(int32_t count, const spgemm_csc *A_host, const spg
     };
     std::vector<Axis> axes = {
         {&spgemm_options::t_esc, {128, 64, 32}},
-        {&spgemm_options::t_sort, {2048, 1024, -1}},
+        {&spgemm_options::t_block, {2048, 1024}},
+        {&spgemm_options::t_split, {1024, 4096, -1}},
         {&spgemm_options::hash_cap, {2048, 1024}},
     };
-    // the dense accumulator applies only when the rows fit its LDS slice
-    if (m_max <= 4096) axes.push_back({&spgemm_options::t_dense, {2048, 1 << 30}});
+    // direct indexing applies only when a window's rows fit the LDS table
+    if (m_max <= 16384) axes.push_back({&spgemm_options::dense_rows, {1}});
     for (const Axis &ax : axes) {
         spgemm_options cur = best;
         for (int32_t v : ax.values) {

@@ -98,6 +98,31 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int &total) {
     return ex;
 }
 
+// Exclusive prefix over a workgroup of T threads; `tmp` holds T / 64 + 1 ints
+// of LDS; `total` gets the workgroup sum. Contains barriers: every thread must
+// call it.
+template <int T>
+__device__ __forceinline__ int wg_excl_scan(int v, int *tmp, int &total) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    int inc = wave_incl_scan(v);
+    if (l == 63) tmp[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int i = 0; i < T / 64; ++i) {
+            int x = tmp[i];
+            tmp[i] = run;
+            run += x;
+        }
+        tmp[T / 64] = run;
+    }
+    __syncthreads();
+    int ex = tmp[w] + inc - v;
+    total = tmp[T / 64];
+    __syncthreads();
+    return ex;
+}
+
 // Largest index i in [0, n) with a[i] <= x, for non-decreasing a with a[0] <= x.
 __device__ __forceinline__ int last_le(const int *a, int n, int x) {
     int lo = 0, hi = n;

@@ -13,8 +13,9 @@
 //      and the position of a key inside its run is the occurrence index k of
 //      that product among the products Algorithm 1 adds into the entry.
 // It counts the runs per column and records the destination of every
-// product: the rank of its row for the first product of a run, a place in the
-// list of later products (with k and the rank) for the others.
+// product: the rank of its row, marked for all but the first product of a run,
+// whose occurrence index k and index among the column's later products are
+// stored at the product's position.
 #include "devutil.h"
 
 namespace spg {
@@ -23,7 +24,6 @@ struct EscSmem {
     int goff[65];    // first product of each column inside the group
     long long cbase[64];  // first product of each column in the product space
     int cnt[65];     // first run index of each column
-    long long lbase; // first place of the group's later products in the later list
     unsigned long long sk[kEscMaxProducts];  // sorted keys
     int rh[kEscMaxProducts];                 // sorted position of every run head
 };
@@ -197,22 +197,19 @@ __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
         if (lane == 0) S.cnt[ncols] = before;
         wave_sync_lds();
         if (lane < ncols) a.gnnz[g] = S.cnt[lane + 1] - S.cnt[lane];
-        // later products of the group: one reservation in the later list
+        // the largest occurrence index of the group (a device atomic only when
+        // it raises the value already there)
         const int nlater = E - before;
-        long long lbase = 0;
         if (nlater > 0) {
             int kmax = 0;
-            if (lane == 0)
-                S.lbase = (long long)atomicAdd(&a.hdr->later_count, (unsigned long long)nlater);
-            wave_sync_lds();
-            lbase = S.lbase;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 if (r < R && key[r] != kNoKey) kmax = max(kmax, r * 64 + lane - S.rh[run[r]]);
 #pragma unroll
             for (int dd = 32; dd >= 1; dd >>= 1)
                 kmax = max(kmax, __builtin_amdgcn_ds_bpermute((lane ^ dd) << 2, kmax));
-            if (lane == 0) atomicMax(&a.hdr->later_maxk, kmax);
+            if (lane == 0 && kmax > __atomic_load_n(&a.hdr->later_maxk, __ATOMIC_RELAXED))
+                atomicMax(&a.hdr->later_maxk, kmax);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -225,18 +222,13 @@ __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
             const long long pe = S.cbase[cc] + (e - S.goff[cc]);
             if (k == 0) {
                 a.dst[pe] = (uint32_t)rank;
-                a.perm[S.cbase[cc] + rank] = e - S.goff[cc];
-                a.crow[S.cbase[cc] + rank] = (int)((key[r] >> 8) & 0xffffffffull);
             } else {
-                // later products of the group take places in sorted order
-                const long long li = lbase + (s - run[r] - 1);
-                if (li < a.later_cap) {
-                    a.dst[pe] = kDstLater | (uint32_t)li;
-                    a.lk[li] = k;
-                    a.lr[li] = rank;
-                } else {
-                    atomicOr(&a.hdr->err, ERR_GROUP);
-                }
+                // index among the column's later products: later keys before
+                // this one in sorted order, minus those of the earlier columns
+                // of the group (their products minus their entries)
+                a.dst[pe] = kDstLater | (uint32_t)rank;
+                a.lk[pe] = k;
+                a.lr[pe] = (s - run[r] - 1) - (S.goff[cc] - S.cnt[cc]);
             }
         }
     }

@@ -1,4 +1,4 @@
-// Product expansion, tiles, window offsets, and the numeric phase.
+// Product expansion and the numeric phase.
 //
 // Product-balanced tiles: tile t holds the columns whose first product lies in
 // [t * kProdTile, (t + 1) * kProdTile) of the product space, so every tile has
@@ -7,22 +7,20 @@
 // Expansion: one workgroup per tile walks the tile's stored B entries in
 // storage order (they are contiguous) and writes the row of every product --
 // the rows of the A column each entry selects, in storage order -- to the
-// product space. This is the only pass that expands the products of
-// Gustavson's column method (Section 2.1) from the inputs' index arrays; the
-// symbolic accumulators stream these rows.
+// product space. The symbolic accumulators stream these rows.
 //
-// Numeric: the symbolic phase left, per product, a destination (the rank of
-// its output row, or for a product that is not the first of its output entry
-// a place in the list of such "later" products with its occurrence index k),
-// and, for columns of at most kSortMax products without row windows, the
-// output order (the first product and the row of every output entry). One
-// workgroup per tile forms the products A(i,k) * B(k,j) of its columns of at
-// most kOrderMax products from coalesced reads of the selected A columns into
-// LDS, then writes their output entries in order as 0 + first product. Larger
-// or windowed columns are done by one workgroup per column through the
-// destinations. Later products are staged; layer
-// kernels add those of occurrence index 1, 2, ... in that order, so every
-// output entry is summed in Algorithm 1's order and rounding, bit for bit.
+// Numeric: the symbolic phase left, per product, a destination: the rank of
+// its output row inside its column, or for a product that is not the first of
+// its output entry a place in the list of such "later" products with its
+// occurrence index k. The numeric kernels form every product A(i,k) * B(k,j)
+// from coalesced reads of the selected A columns (rows and values) and write
+// the first product of each entry as 0 + product straight to its output
+// position; later products are staged, and layer kernels add those of
+// occurrence index 1, 2, ... in that order, so every output entry is summed in
+// Algorithm 1's order and rounding, bit for bit. Columns of at most t_split
+// products go by product-balanced tiles, larger ones by chunks of kChunkB
+// stored B entries (one workgroup each), so no workgroup holds a whole large
+// column.
 #include "devutil.h"
 
 namespace spg {
@@ -50,7 +48,8 @@ struct ExpSmem {
 __global__ __launch_bounds__(kBlock) void k_expand(KArgs a) {
     constexpr int PER = 4;
     __shared__ ExpSmem S;
-    if (a.hdr->err) return;
+    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
+        return;  // every thread takes the same branch
     const int tid = threadIdx.x;
     const int g0 = a.tilestart[blockIdx.x], g1 = a.tilestart[blockIdx.x + 1];
     int *__restrict__ prow = a.prow;
@@ -110,65 +109,124 @@ hipError_t launch_expand(const KArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- numeric, tiles
-constexpr int kColWin = 256;                   // columns per window of a tile
-constexpr int kStage = kProdTile + kOrderMax;  // staged products of a tile
-
-// the tiles write a column in output order when it has at most kOrderMax
-// products and no row windows (its output order is then recorded)
-__device__ __forceinline__ bool has_order(int op, int binw) {
-    return op <= kOrderMax && (binw >> 8) <= 1;
+// ---------------------------------------------------------------- numeric
+// Forms the products of `nbw` stored B entries (window arrays in LDS: A
+// column start, first product of the entry in the window's product numbering,
+// window column, B value) and writes each product through its destination:
+// the first product of an entry as 0 + product at C position c0 + rank, a
+// later product into the staging of the later list. `pos(tt, e)` gives the
+// product-space index of product e (window numbering) of entry tt,
+// `cinfo(c, c0, clen, lb)` the column's output start and length and the start
+// of its later products in the compact list.
+template <typename V, int PER, typename Pos, typename Cinfo>
+__device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Prob &d,
+                                               const int *s_acp, const int *s_eoff,
+                                               const int *s_col, const V *s_bv, int nbw, int Ew,
+                                               Pos &&pos, Cinfo &&cinfo, int &bad) {
+    const V *__restrict__ av = (const V *)d.av;
+    const int *__restrict__ ari = d.ari;
+    int *__restrict__ cri = d.cri;
+    V *__restrict__ cv = (V *)d.cv;
+    V *__restrict__ lv = (V *)a.lv;
+    const int tid = threadIdx.x;
+    for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
+        V v[PER];
+        int row[PER], c[PER];
+        uint32_t dc[PER];
+        long long pp[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = e0 + u * kBlock + tid;
+            c[u] = -1;
+            if (e < Ew) {
+                const int tt = last_le(s_eoff, nbw, e);
+                const int q = s_acp[tt] + e - s_eoff[tt];
+                c[u] = s_col[tt];
+                pp[u] = pos(tt, e);
+                v[u] = av[q] * s_bv[tt];
+                row[u] = ari[q];
+                dc[u] = a.dst[pp[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (c[u] < 0) continue;
+            int c0, clen;
+            long long lb;
+            cinfo(c[u], c0, clen, lb);
+            const int o = (int)(dc[u] & ~kDstLater);
+            if (o >= clen) { bad = 1; continue; }
+            if (!(dc[u] & kDstLater)) {
+                cri[c0 + o] = row[u];
+                cv[c0 + o] = V(0) + v[u];
+            } else {
+                const long long li = lb + a.lr[pp[u]];
+                if (li < 0 || li >= a.later_n) { bad = 1; continue; }
+                a.lo[li] = c0 + o;
+                a.lpid[li] = pid;
+                a.lkc[li] = a.lk[pp[u]];
+                lv[li] = v[u];
+            }
+        }
+    }
 }
+
+constexpr int kColWin = 256;  // columns per window of a tile
+constexpr int kNumPer = 8;    // products per thread per pass
 
 template <typename V>
 struct NumSmem {
-    V val[kStage];           // products of the tile's ordered columns (by product offset)
-    int s_acp[kBlock];       // A column start of each stored B entry of the B window
-    int s_eoff[kBlock];      // first product of each stored B entry of the B window
-    int s_col[kBlock];       // window column of each stored B entry of the B window
-    V s_bv[kBlock];          // B value of each stored B entry of the B window
-    int s_bcp[kColWin + 1];  // B column pointers of the column window
-    int s_c0[kColWin + 1];   // C column pointers of the column window
-    int s_pb[kColWin + 1];   // first product of each column, relative to the tile
-    int s_ok[kColWin];       // column written in output order
+    int s_bcp[kColWin + 1];     // B column pointers of the column window
+    int s_c0[kColWin + 1];      // C column pointers of the column window
+    int s_ceff[kColWin + 1];    // first product of each column among the window's tile columns
+    long long s_pcol[kColWin];  // first product of each column in the product space
+    int s_ok[kColWin];          // column done by the tile (at most t_split products)
+    long long s_lb[kColWin];    // start of each column's later products in the compact list
+    int s_acp[kBlock];          // A column start of each stored B entry of the B window
+    int s_eoff[kBlock];         // first product of each stored B entry of the B window
+    int s_col[kBlock];          // window column of each stored B entry of the B window
+    V s_bv[kBlock];             // B value of each stored B entry of the B window
     int scan_tmp[kBlock / 64 + 1];
 };
 
+// One workgroup per product-balanced tile; columns with more than t_split
+// products are left to k_numeric_big (their products count zero here).
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
-    constexpr int PER = 4;   // products per thread per chunk
-    constexpr int OPER = 8;  // output entries per thread per chunk
     __shared__ NumSmem<V> S;
-    if (a.hdr->err) return;
+    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
+        return;  // every thread takes the same branch
     const int tid = threadIdx.x;
     const int g0 = a.tilestart[blockIdx.x], g1 = a.tilestart[blockIdx.x + 1];
     if (g0 >= g1) return;
-    const long long tbase = a.colprod[g0];
-    V *__restrict__ lv = (V *)a.lv;
     int bad = 0;
     for_each_segment(a, g0, g1, [&](int pid, const Prob &d, int js, int je) {
         const int2 *__restrict__ Ep = a.E + d.ebase;
-        const V *__restrict__ av = (const V *)d.av;
         const V *__restrict__ bv = (const V *)d.bv;
-        int *__restrict__ cri = d.cri;
-        V *__restrict__ cv = (V *)d.cv;
         for (int jw = js; jw < je; jw += kColWin) {
             const int nc = min(kColWin, je - jw);
             const int gw = d.col0 + jw;
+            int eff = 0;
             for (int c = tid; c <= nc; c += kBlock) {
                 S.s_bcp[c] = d.bcp[jw + c];
                 S.s_c0[c] = d.ccp[jw + c];
-                const long long pc = c < nc ? a.colprod[gw + c]
-                                            : a.colprod[gw + nc - 1] + a.op[gw + nc - 1];
-                S.s_pb[c] = (int)(pc - tbase);
-                if (c < nc) S.s_ok[c] = has_order(a.op[gw + c], a.binw[gw + c]);
             }
+            if (tid < nc) {
+                const int op = a.op[gw + tid];
+                const int ok = op <= a.tune.t_split;
+                S.s_ok[tid] = ok;
+                const long long pc = a.colprod[gw + tid];
+                S.s_pcol[tid] = pc;
+                S.s_lb[tid] = pc - (a.nprob == 1 ? (long long)d.ccp[jw + tid] : a.gcp[gw + tid]);
+                eff = ok ? op : 0;
+            }
+            int tot;
+            const int ex = block_excl_scan(eff, S.scan_tmp, tot);
+            if (tid < nc) S.s_ceff[tid] = ex;
+            if (tid == 0) S.s_ceff[nc] = tot;
             __syncthreads();
-            // ---- products of the window's ordered columns into LDS; later
-            // products staged for the layer kernels. The next B window's
-            // loads are issued before the current one is processed.
-            long long base = tbase + S.s_pb[0];
             const int pb = S.s_bcp[0], pe = S.s_bcp[nc];
+            int base = 0;  // first product of the B window among the tile columns
             int2 nez = make_int2(0, 0);
             V nb = V(0);
             if (pb + tid < pe) {
@@ -183,188 +241,102 @@ __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
                     nez = Ep[t + kBlock];
                     nb = bv[t + kBlock];
                 }
-                int z = 0, acp = 0, col = 0;
-                V b = V(0);
+                int z = 0, col = 0;
                 if (t < pe) {
                     col = last_le(S.s_bcp, nc + 1, t);
-                    z = ez.y;
-                    if (S.s_ok[col]) {
-                        acp = ez.x;
-                        b = b0;
-                    }
+                    if (S.s_ok[col]) z = ez.y;
                 }
                 int Ew;
-                const int ex = block_excl_scan(z, S.scan_tmp, Ew);
-                S.s_acp[tid] = acp;
-                S.s_eoff[tid] = ex;
+                const int ez0 = block_excl_scan(z, S.scan_tmp, Ew);
+                S.s_acp[tid] = ez.x;
+                S.s_eoff[tid] = ez0;
                 S.s_col[tid] = col;
-                S.s_bv[tid] = b;
+                S.s_bv[tid] = b0;
                 __syncthreads();
                 const int nbw = min(kBlock, pe - bw);
-                for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
-                    V v[PER];
-                    uint32_t dc[PER];
-                    int c[PER];
-#pragma unroll
-                    for (int u = 0; u < PER; ++u) {
-                        const int e = e0 + u * kBlock + tid;
-                        c[u] = -1;
-                        if (e < Ew) {
-                            const int tt = last_le(S.s_eoff, nbw, e);
-                            if (S.s_ok[S.s_col[tt]]) {
-                                c[u] = S.s_col[tt];
-                                const int q = S.s_acp[tt] + e - S.s_eoff[tt];
-                                v[u] = av[q] * S.s_bv[tt];
-                                dc[u] = a.dst[base + e];
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < PER; ++u) {
-                        if (c[u] < 0) continue;
-                        const long long eg = base + e0 + u * kBlock + tid;
-                        S.val[eg - tbase] = v[u];
-                        if (dc[u] & kDstLater) {
-                            const int li = (int)(dc[u] & ~kDstLater);
-                            if (li >= a.later_cap) { bad = 1; continue; }
-                            const int o = a.lr[li];
-                            if (o < 0 || o >= S.s_c0[c[u] + 1] - S.s_c0[c[u]]) { bad = 1; continue; }
-                            a.lo[li] = S.s_c0[c[u]] + o;
-                            a.lpid[li] = pid;
-                            lv[li] = v[u];
-                        }
-                    }
-                }
+                numeric_window<V, kNumPer>(
+                    a, pid, d, S.s_acp, S.s_eoff, S.s_col, S.s_bv, nbw, Ew,
+                    [&](int tt, int e) {
+                        const int c = S.s_col[tt];
+                        return S.s_pcol[c] + (base + e - S.s_ceff[c]);
+                    },
+                    [&](int c, int &c0, int &clen, long long &lb) {
+                        c0 = S.s_c0[c];
+                        clen = S.s_c0[c + 1] - c0;
+                        lb = S.s_lb[c];
+                    },
+                    bad);
                 base += Ew;
                 __syncthreads();
             }
-            // ---- output entries of the window's ordered columns, in order
-            const int o0 = S.s_c0[0], o1 = S.s_c0[nc];
-            for (int oc = o0; oc < o1; oc += OPER * kBlock) {
-                int c[OPER], e[OPER], row[OPER];
-#pragma unroll
-                for (int u = 0; u < OPER; ++u) {
-                    const int o = oc + u * kBlock + tid;
-                    c[u] = -1;
-                    if (o < o1) {
-                        const int cc = last_le(S.s_c0, nc + 1, o);
-                        if (S.s_ok[cc]) {
-                            c[u] = cc;
-                            const long long po = tbase + S.s_pb[cc] + (o - S.s_c0[cc]);
-                            e[u] = a.perm[po];
-                            row[u] = a.crow[po];
-                        }
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < OPER; ++u) {
-                    if (c[u] < 0) continue;
-                    if (e[u] < 0 || e[u] >= S.s_pb[c[u] + 1] - S.s_pb[c[u]]) {
-                        bad = 1;
-                        continue;
-                    }
-                    const int o = oc + u * kBlock + tid;
-                    cri[o] = row[u];
-                    cv[o] = V(0) + S.val[S.s_pb[c[u]] + e[u]];
-                }
-            }
-            __syncthreads();
         }
     });
     if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
 }
 
-// ---------------------------------------------------------------- numeric, other columns
+// ---------------------------------------------------------------- numeric, large columns
 template <typename V>
 struct BigSmem {
     int s_acp[kBlock];
     int s_eoff[kBlock];
+    int s_col[kBlock];
     V s_bv[kBlock];
     int scan_tmp[kBlock / 64 + 1];
+    long long s_pre;
 };
 
+// One workgroup per chunk of kChunkB stored B entries of a column with more
+// than t_split products (blockIdx.x: column in the bin list, blockIdx.y: chunk).
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int n) {
-    constexpr int PER = 4;
     __shared__ BigSmem<V> S;
-    if (a.hdr->err) return;
+    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
+        return;  // every thread takes the same branch
     const int tid = threadIdx.x;
-    V *__restrict__ lv = (V *)a.lv;
-    for (int li0 = blockIdx.x; li0 < n; li0 += gridDim.x) {
-        const int4 ent = a.binlist[first + li0];
-        const int g = ent.x, bs = ent.y, be = ent.y + ent.z;
-        const int bwin = a.binw[g];
-        if (has_order(a.op[g], bwin)) continue;  // done by the tiles
-        const int pid = find_prob(a, g);
-        const Prob d = get_prob(a, pid);
-        const int j = g - d.col0;
-        const int W = max(bwin >> 8, 1);
-        const int it0 = W > 1 ? a.colitem[g] : 0;
-        long long base = a.colprod[g];
-        const int c0 = d.ccp[j], clen = d.ccp[j + 1] - c0;
-        const int2 *__restrict__ Ep = a.E + d.ebase;
-        const V *__restrict__ av = (const V *)d.av;
-        const V *__restrict__ bv = (const V *)d.bv;
-        int *__restrict__ cri = d.cri + c0;
-        V *__restrict__ cv = (V *)d.cv + c0;
-        int bad = 0;
-        for (int bw = bs; bw < be; bw += kBlock) {
-            const int t = bw + tid;
-            int z = 0, acp = 0;
-            V b = V(0);
-            if (t < be) {
-                const int2 ez = Ep[t];
-                acp = ez.x;
-                z = ez.y;
-                b = bv[t];
-            }
-            int Ew;
-            const int ex = block_excl_scan(z, S.scan_tmp, Ew);
-            S.s_acp[tid] = acp;
-            S.s_eoff[tid] = ex;
-            S.s_bv[tid] = b;
-            __syncthreads();
-            const int nbw = min(kBlock, be - bw);
-            for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
-                int row[PER];
-                V v[PER];
-                uint32_t dc[PER];
-#pragma unroll
-                for (int u = 0; u < PER; ++u) {
-                    const int e = e0 + u * kBlock + tid;
-                    row[u] = -1;
-                    if (e < Ew) {
-                        const int tt = last_le(S.s_eoff, nbw, e);
-                        const int q = S.s_acp[tt] + e - S.s_eoff[tt];
-                        row[u] = a.prow[base + e];
-                        v[u] = av[q] * S.s_bv[tt];
-                        dc[u] = a.dst[base + e];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < PER; ++u) {
-                    if (row[u] < 0) continue;
-                    const bool later = (dc[u] & kDstLater) != 0;
-                    const int li = (int)(dc[u] & ~kDstLater);
-                    if (later && li >= a.later_cap) { bad = 1; continue; }
-                    int o = later ? a.lr[li] : li;
-                    if (W > 1) o += a.itemoff[it0 + window_of(row[u], W, d.m)];
-                    if (o < 0 || o >= clen) { bad = 1; continue; }
-                    if (!later) {
-                        cri[o] = row[u];
-                        cv[o] = V(0) + v[u];
-                    } else {
-                        a.lo[li] = c0 + o;
-                        a.lpid[li] = pid;
-                        lv[li] = v[u];
-                    }
-                }
-            }
-            base += Ew;
-            __syncthreads();
-        }
-        if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
+    const int4 ent = a.binlist[first + blockIdx.x];
+    const int g = ent.x, bs = ent.y, nb = ent.z;
+    const int op = a.op[g];
+    const int b0 = bs + (int)blockIdx.y * kChunkB;
+    if (op <= a.tune.t_split || b0 >= bs + nb) return;  // tile column, or no such chunk
+    const int b1 = min(bs + nb, b0 + kChunkB);
+    const int pid = find_prob(a, g);
+    const Prob d = get_prob(a, pid);
+    const int j = g - d.col0;
+    const int2 *__restrict__ Ep = a.E + d.ebase;
+    // this chunk's first product: the products of the column's earlier entries
+    const int t = b0 + tid;
+    int2 ez = make_int2(0, 0);
+    V b = V(0);
+    if (t < b1) {
+        ez = Ep[t];
+        b = ((const V *)d.bv)[t];
     }
+    long long pre = 0;
+    for (int x = bs + tid; x < b0; x += kBlock) pre += Ep[x].y;
+    if (tid == 0) S.s_pre = 0;
+    __syncthreads();
+    if (pre) atomicAdd((unsigned long long *)&S.s_pre, (unsigned long long)pre);
+    const int c0 = d.ccp[j], clen = d.ccp[j + 1] - c0;
+    const long long lb0 = a.colprod[g] - (a.nprob == 1 ? (long long)c0 : a.gcp[g]);
+    int Ew;
+    const int ex = block_excl_scan(t < b1 ? ez.y : 0, S.scan_tmp, Ew);
+    S.s_acp[tid] = ez.x;
+    S.s_eoff[tid] = ex;
+    S.s_col[tid] = 0;
+    S.s_bv[tid] = b;
+    __syncthreads();
+    const long long pbase = a.colprod[g] + S.s_pre;
+    int bad = 0;
+    numeric_window<V, kNumPer>(
+        a, pid, d, S.s_acp, S.s_eoff, S.s_col, S.s_bv, b1 - b0, Ew,
+        [&](int, int e) { return pbase + e; },
+        [&](int, int &o0, int &ol, long long &lb) {
+            o0 = c0;
+            ol = clen;
+            lb = lb0;
+        },
+        bad);
+    if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
 }
 
 // later products of occurrence index k, added to their (already written)
@@ -374,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_layer(KArgs a, int k, long long n) {
     const V *__restrict__ lv = (const V *)a.lv;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (long long)gridDim.x * kBlock) {
-        if (a.lk[i] != k) continue;
+        if (a.lkc[i] != k) continue;
         const Prob d = get_prob(a, a.lpid[i]);
         V *cv = (V *)d.cv;
         const int o = a.lo[i];
@@ -389,12 +361,12 @@ hipError_t launch_numeric(const KArgs &a, bool f64, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_numeric_big(const KArgs &a, bool f64, int first, int nbig, hipStream_t s) {
-    if (nbig <= 0) return hipSuccess;
-    if (f64)
-        hipLaunchKernelGGL((k_numeric_big<double>), dim3(nbig), dim3(kBlock), 0, s, a, first, nbig);
-    else
-        hipLaunchKernelGGL((k_numeric_big<float>), dim3(nbig), dim3(kBlock), 0, s, a, first, nbig);
+hipError_t launch_numeric_big(const KArgs &a, bool f64, int first, int nbig, int maxchunks,
+                              hipStream_t s) {
+    if (nbig <= 0 || maxchunks <= 0) return hipSuccess;
+    const dim3 grid(nbig, maxchunks);
+    if (f64) hipLaunchKernelGGL((k_numeric_big<double>), grid, dim3(kBlock), 0, s, a, first, nbig);
+    else hipLaunchKernelGGL((k_numeric_big<float>), grid, dim3(kBlock), 0, s, a, first, nbig);
     return hipGetLastError();
 }
 

@@ -14,9 +14,8 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     __shared__ int s_bcp[kTile + 1];
     __shared__ unsigned long long s_op[kTile];
     __shared__ int s_hist[NBINS];
-    __shared__ int s_items[kHashBins];
-    __shared__ int s_err;
-    __shared__ unsigned long long s_tot, s_ltot;
+    __shared__ int s_err, s_maxch;
+    __shared__ unsigned long long s_tot;
 
     int pid, j0, j1;
     if (a.nprob == 1) {
@@ -34,8 +33,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     for (int c = tid; c <= nt; c += kBlock) s_bcp[c] = d.bcp[j0 + c];
     for (int c = tid; c < nt; c += kBlock) s_op[c] = 0;
     if (tid < NBINS) s_hist[tid] = 0;
-    if (tid < kHashBins) s_items[tid] = 0;
-    if (tid == 0) { s_err = 0; s_tot = 0; s_ltot = 0; }
+    if (tid == 0) { s_err = 0; s_tot = 0; s_maxch = 0; }
     __syncthreads();
 
     // column pointers of B: monotone, inside [0, nnz], 0 first, nnz last
@@ -103,7 +101,8 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     }
 
     const int esc_max = 4 << (a.tune.esc_bins - 1);
-    unsigned long long tot = 0, ltot = 0;
+    unsigned long long tot = 0;
+    int maxch = 0;
     err = 0;
     for (int c = tid; c < nt; c += kBlock) {
         const int g = d.col0 + j0 + c;
@@ -111,50 +110,40 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
         if (op64 > 0x7fffffffull) { err = ERR_OPOVF; op64 = 0x7fffffffull; }
         tot += op64;
         const int op = (int)op64;
-        int bin, W = 0;
+        int bin;
         if (op == 0) bin = BIN_EMPTY;
         else if (op <= esc_max) bin = BIN_ESC0 + max(ceil_log2(op), 2) - 2;
-        else if (d.m <= a.tune.dense_rows && op >= a.tune.t_dense) bin = BIN_DENSE;
-        else if (op <= a.tune.t_sort) bin = BIN_SORT0 + max(ceil_log2(op), 9) - 9;
-        else {
-            W = hash_windows(op, a.tune.hash_cap);
-            bin = BIN_HASH_S + hash_class(hash_table_size(op, W));
-        }
+        else if (op <= a.tune.t_block) bin = BIN_SORT0 + max(ceil_log2(op), 9) - 9;
+        else bin = BIN_BLK0 + blk_class(op);
+        if (op > a.tune.t_split) maxch = max(maxch, ceil_div(s_bcp[c + 1] - s_bcp[c], kChunkB));
         a.op[g] = op;
-        a.binw[g] = bin | (W << 8);
+        a.binw[g] = bin;
         a.gnnz[g] = 0;
-        if (bin >= BIN_DENSE) ltot += op64;
         atomicAdd(&s_hist[bin], 1);
-        if (W) atomicAdd(&s_items[bin - BIN_HASH_S], W);
     }
     if (err) atomicOr(&s_err, err);
-    // tile totals of products (all, and those of list columns)
+    // tile total of products
     atomicAdd(&s_tot, tot);
-    if (ltot) atomicAdd(&s_ltot, ltot);
+    if (maxch) atomicMax(&s_maxch, maxch);
     __syncthreads();
     if (tid < NBINS && s_hist[tid]) atomicAdd(&a.hdr->bin_count[tid], s_hist[tid]);
-    if (tid < kHashBins && s_items[tid]) atomicAdd(&a.hdr->item_count[tid], s_items[tid]);
     if (tid == 0) {
         atomicAdd(&a.hdr->total_op, s_tot);
-        if (s_ltot) atomicAdd(&a.hdr->list_products, s_ltot);
+        if (s_maxch) atomicMax(&a.hdr->big_chunks, s_maxch);
         if (s_err) atomicOr(&a.hdr->err, s_err);
     }
 }
 
 // ---------------------------------------------------------------- place
 // Same tiling. Each tile reserves a contiguous range in every bin list with
-// one global atomic per bin, then writes its columns there. Hash columns also
-// reserve their row windows (work items); column and window cursors advance
-// in one 64-bit atomic per hash bin, so the windows of one column are
-// consecutive items.
+// one global atomic per bin, then writes its columns there.
 __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
     __shared__ int s_start[NBINS];
     __shared__ int s_cnt[NBINS];
     __shared__ int s_base[NBINS];
-    __shared__ unsigned long long s_hpack[kHashBins];
-    __shared__ unsigned long long s_hbase[kHashBins];
 
-    if (a.hdr->err & (ERR_CSC | ERR_OPOVF)) return;
+    if (__syncthreads_or((__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) & (ERR_CSC | ERR_OPOVF)) != 0))
+        return;  // every thread takes the same branch
     int pid, j0, j1;
     if (a.nprob == 1) {
         pid = 0;
@@ -173,77 +162,41 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
             s_start[b] = run;
             run += a.hdr->bin_count[b];
         }
-        for (int h = 0; h < kHashBins; ++h) s_hpack[h] = 0;
     }
     if (tid < NBINS) s_cnt[tid] = 0;
     __syncthreads();
-    int item0[kHashBins];
-    int nitems = 0;
-#pragma unroll
-    for (int h = 0; h < kHashBins; ++h) {
-        item0[h] = nitems;
-        nitems += a.hdr->item_count[h];
-    }
 
     constexpr int PER = kTile / kBlock;
-    int rank[PER], binv[PER], wv[PER];
-    unsigned long long hold[PER];
+    int rank[PER], binv[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         int c = tid + u * kBlock;
         binv[u] = -1;
         if (c < nt) {
-            int bw = a.binw[col0 + j0 + c];
-            int bin = bw & 255, W = bw >> 8;
-            binv[u] = bin;
-            wv[u] = W;
-            if (bin >= BIN_HASH_S)
-                hold[u] = atomicAdd(&s_hpack[bin - BIN_HASH_S], ((unsigned long long)W << 32) | 1ull);
-            else
-                rank[u] = atomicAdd(&s_cnt[bin], 1);
+            binv[u] = a.binw[col0 + j0 + c];
+            rank[u] = atomicAdd(&s_cnt[binv[u]], 1);
         }
     }
     __syncthreads();
-    if (tid < BIN_HASH_S && s_cnt[tid])
+    if (tid < NBINS && s_cnt[tid])
         s_base[tid] = s_start[tid] + atomicAdd(&a.hdr->bin_cursor[tid], s_cnt[tid]);
-    if (tid >= BIN_HASH_S && tid < NBINS && s_hpack[tid - BIN_HASH_S])
-        s_hbase[tid - BIN_HASH_S] =
-            atomicAdd(&a.hdr->hash_cursor[tid - BIN_HASH_S], s_hpack[tid - BIN_HASH_S]);
     __syncthreads();
-    const bool room = nitems <= a.item_cap;
     const int32_t *bcp = a.nprob == 1 ? a.single.bcp : a.table[pid].bcp;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         int c = tid + u * kBlock;
         if (c >= nt) continue;
         const int g = col0 + j0 + c;
-        const int bin = binv[u];
         const int bs = bcp[j0 + c], nb = bcp[j0 + c + 1] - bs;
-        const int4 ent = make_int4(g, bs, nb, 0);
-        if (bin >= BIN_HASH_S) {
-            const int h = bin - BIN_HASH_S;
-            unsigned long long pos = s_hbase[h] + hold[u];
-            int hcol = (int)(pos & 0xffffffffull);
-            int item = item0[h] + (int)(pos >> 32);
-            const int lpos = s_start[bin] + hcol;
-            a.binlist[lpos] = ent;
-            a.colitem[g] = item;
-            if (room)
-                for (int w = 0; w < wv[u]; ++w) a.items[item + w] = make_int4(g, lpos, bs, nb);
-        } else {
-            a.binlist[s_base[bin] + rank[u]] = ent;
-        }
+        a.binlist[s_base[binv[u]] + rank[u]] = make_int4(g, bs, nb, 0);
     }
-    if (tid == 0 && !room && blockIdx.x == 0) atomicOr(&a.hdr->err, ERR_ITEMCAP);
 }
 
 // ---------------------------------------------------------------- scans
 // Exclusive prefix sums in 64-bit, in two launches: per-block sums, then a
 // down-sweep in which every block adds up the sums of the blocks before it
 // itself (at most a few thousand values) and scans its kScanBlock elements.
-// The down-sweeps also do per-element follow-up work: the product-space scan
-// marks the tile starts, the column-pointer scan computes the hash windows'
-// offsets.
+// The product-space down-sweep also marks the tile starts.
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ in, int n,
                                                         long long *__restrict__ bsum) {
     __shared__ long long s[kBlock / 64];
@@ -322,8 +275,7 @@ __device__ __forceinline__ void block_scan_down(const int32_t *__restrict__ in, 
     o.block_end = before + s[kBlock - 1];
 }
 
-// C column pointers from the per-column counts, and the row-window offsets of
-// the hash columns. For one problem the int32 column pointers are written
+// C column pointers from the per-column counts. For one problem the int32 column pointers are written
 // directly (with an overflow check); for several problems the 64-bit global
 // prefix is kept in gcp and k_scan_finish cuts it per problem.
 __global__ __launch_bounds__(kBlock) void k_scan_down(KArgs a, long long *__restrict__ gcp,
@@ -344,17 +296,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(KArgs a, long long *__rest
             a.single.ccp[i] = (int32_t)v;
         } else {
             gcp[i] = v;
-        }
-        // distinct rows of a windowed hash column's earlier windows
-        const int W = a.binw[i] >> 8;
-        if (W > 1) {
-            const int it0 = a.colitem[i];
-            int r = 0;
-            for (int w = 0; w < W; ++w) {
-                const int c = a.itemcnt[it0 + w];
-                a.itemoff[it0 + w] = r;
-                r += c;
-            }
         }
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {

@@ -9,8 +9,9 @@
 // between the four registers a lane holds, and larger distances through LDS.
 // Every run of equal rows is one output entry; its rank is the run index and
 // the position of a key inside its run is the occurrence index k of that
-// product. The first product of a run gets the rank as its destination; the
-// others get places in the later-product list.
+// product. Every product gets the rank as its destination, marked for all but
+// the first of a run, whose occurrence index k and index among the column's
+// later products are stored at the product's position.
 //
 // Keys are 32-bit when the rows fit in 20 bits (row << 12 | e), else 64-bit.
 #include "devutil.h"
@@ -122,9 +123,9 @@ __global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
     __shared__ K buf[N];     // exchanges, then the sorted keys
     __shared__ int rh[N];    // sorted position of every run head
     __shared__ int wcnt[NW + 1];
-    __shared__ long long s_lbase;
     __shared__ int s_kmax;
-    if (a.hdr->err) return;
+    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
+        return;  // every thread takes the same branch
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, sb = wave * 256;
     int start = 0;
     for (int b = 0; b < bin; ++b) start += a.hdr->bin_count[b];
@@ -171,8 +172,6 @@ __global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
             }
             wcnt[NW] = tot;
             s_kmax = 0;
-            if (op > tot)
-                s_lbase = (long long)atomicAdd(&a.hdr->later_count, (unsigned long long)(op - tot));
             a.gnnz[g] = tot;
         }
         __syncthreads();
@@ -183,7 +182,7 @@ __global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
             if (head[r]) rh[run[r]] = sb + r * 64 + lane;
         }
         __syncthreads();
-        int kloc = 0, bad = 0;
+        int kloc = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             if (key[r] == KMAX) continue;
@@ -192,30 +191,25 @@ __global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
             const int k = s - rh[run[r]];
             if (k == 0) {
                 a.dst[pbase + e] = (uint32_t)run[r];
-                a.perm[pbase + run[r]] = e;
-                a.crow[pbase + run[r]] = (int)(key[r] >> EB);
             } else {
-                const long long li = s_lbase + (s - run[r] - 1);
-                if (li < a.later_cap) {
-                    a.dst[pbase + e] = kDstLater | (uint32_t)li;
-                    a.lk[li] = k;
-                    a.lr[li] = run[r];
-                    kloc = max(kloc, k);
-                } else {
-                    bad = 1;
-                }
+                // index among the column's later products: the later keys
+                // before this one in sorted order
+                a.dst[pbase + e] = kDstLater | (uint32_t)run[r];
+                a.lk[pbase + e] = k;
+                a.lr[pbase + e] = s - run[r] - 1;
+                kloc = max(kloc, k);
             }
         }
         if (kloc) atomicMax(&s_kmax, kloc);
-        if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
         __syncthreads();
-        if (tid == 0 && s_kmax) atomicMax(&a.hdr->later_maxk, s_kmax);
+        if (tid == 0 && s_kmax > __atomic_load_n(&a.hdr->later_maxk, __ATOMIC_RELAXED))
+            atomicMax(&a.hdr->later_maxk, s_kmax);
     }
 }
 
 hipError_t launch_sort(const KArgs &a, int cls, bool wide, int grid, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
-    const int bin = BIN_SORT0 + cls;
+    const int bin = BIN_SORT0 + cls;  // columns of at most 512 << cls products
 #define SPG_SORT(K, T) hipLaunchKernelGGL((k_bsort<K, T>), dim3(grid), dim3(T), 0, s, a, bin)
     if (wide) {
         switch (cls) {

@@ -3,8 +3,8 @@
 //
 // Symbolic:  classify (Op_j, accumulator bin) -> place (bin lists) ->
 //            product-space offsets -> expansion (row of every product) ->
-//            ESC / dense / hash: distinct rows per column and the destination
-//            of every product -> window offsets -> prefix scan into the column
+//            ESC / workgroup accumulators: distinct rows per column and the
+//            destination of every product -> prefix scan into the column
 //            pointers -> one device-to-host copy of the totals.
 // Numeric:   every product formed and written or staged through its
 //            destination, then the staged later products added in order.
@@ -31,20 +31,18 @@ struct spgemm_plan_s {
     Tune tune{};
     uint32_t flags = 0;
     std::vector<Prob> probs;  // host copy of the problem table
-    int ncols = 0, ntiles = 0, item_cap = 0, nblk = 0;
+    int ncols = 0, ntiles = 0, nblk = 0;
     bool symbolic_ok = false;
 
     // device workspace (one allocation, carved)
     void *ws = nullptr;
     size_t ws_bytes = 0;
     Hdr *hdr = nullptr;
-    int32_t *op = nullptr, *binw = nullptr, *gnnz = nullptr,
-            *itemcnt = nullptr, *col0s = nullptr;
-    int4 *binlist = nullptr, *items = nullptr;
+    int32_t *op = nullptr, *binw = nullptr, *gnnz = nullptr, *col0s = nullptr;
+    int4 *binlist = nullptr;
     int2 *E = nullptr;
     long long total_nnzb = 0;
     long long *colprod = nullptr;
-    int32_t *colitem = nullptr, *itemoff = nullptr;
     // per-product arrays (own allocation: the product count is known only
     // after the classification): row and destination of every product, and
     // the later list's occurrence indices and ranks
@@ -52,14 +50,14 @@ struct spgemm_plan_s {
     size_t prod_bytes = 0;
     int32_t *prow = nullptr;
     uint32_t *dst = nullptr;
-    int32_t *lk = nullptr, *lr = nullptr, *perm = nullptr, *crow = nullptr, *tilestart = nullptr;
+    int32_t *lk = nullptr, *lr = nullptr, *tilestart = nullptr;
     int nptiles = 0;
-    long long later_cap = 0;
     // staging of the later products for the numeric phase (sized by their count)
     void *stage = nullptr;
     size_t stage_bytes = 0;
-    int32_t *lo = nullptr, *lpid = nullptr;
+    int32_t *lo = nullptr, *lpid = nullptr, *lkc = nullptr;
     void *lv = nullptr;
+    long long later_total = 0;  // products that are not the first of their entry
     long long *gcp = nullptr, *bsum = nullptr, *totals = nullptr;
     Prob *table = nullptr;
     int4 *tiles = nullptr;
@@ -141,29 +139,31 @@ spgemm_status hip_status(hipError_t e) {
     } while (0)
 
 spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flags) {
-    int t_esc = 256, t_dense = 512, dense_rows = kDenseRows, cap = kHashMax / 2, t_sort = kSortMax;
-    // (cap: the extra-large table class holds kHashMax / 2 distinct rows at load 1/2)
+    int t_esc = 256, t_dense = 1, dense_rows = 0, cap = 0, t_split = 2048, t_block = kSortMax;
     flags = 0;
     if (opt) {
         if (opt->t_esc) t_esc = opt->t_esc;
         if (opt->t_dense) t_dense = opt->t_dense;
-        if (opt->dense_rows) dense_rows = opt->dense_rows;
-        if (opt->hash_cap) cap = opt->hash_cap;
-        if (opt->t_sort) t_sort = opt->t_sort;
+        dense_rows = opt->dense_rows;
+        cap = opt->hash_cap;
+        if (opt->t_split) t_split = opt->t_split;
+        if (opt->t_block) t_block = opt->t_block;
         flags = opt->flags;
     }
     if (t_esc < 4 || t_esc > kEscMaxProducts) return SPGEMM_ERR_INVALID;
     if (t_dense < 1) return SPGEMM_ERR_INVALID;
-    if (dense_rows < 64 || dense_rows > kDenseRows) return SPGEMM_ERR_INVALID;
-    if (cap < 128 || cap > kHashMax / 2) return SPGEMM_ERR_INVALID;
-    if (t_sort != -1 && (t_sort < 1 || t_sort > kSortMax)) return SPGEMM_ERR_INVALID;
-    t.t_sort = t_sort < 0 ? 0 : t_sort;
+    if (dense_rows < 0) return SPGEMM_ERR_INVALID;
+    if (cap != 0 && (cap < 16 || cap > (1 << 20))) return SPGEMM_ERR_INVALID;
+    if (t_split < -1) return SPGEMM_ERR_INVALID;
+    if (t_block < -1 || t_block > kSortMax) return SPGEMM_ERR_INVALID;
     int bins = 1;
     while ((4 << (bins - 1)) < t_esc) ++bins;  // t_esc rounded up to a power of two
     t.esc_bins = bins;
     t.t_dense = t_dense;
     t.dense_rows = dense_rows;
     t.hash_cap = cap;
+    t.t_split = t_split < 0 ? 0x7fffffff : t_split;
+    t.t_block = t_block < 0 ? 0 : t_block;
     return SPGEMM_OK;
 }
 
@@ -210,11 +210,8 @@ spgemm_status ensure_workspace(spgemm_plan p) {
     const size_t o_hdr = take(sizeof(Hdr));
     const size_t o_op = take(4 * n), o_binw = take(4 * n), o_binlist = take(16 * n),
                  o_gnnz = take(4 * n);
-    const size_t o_items = take(16 * (size_t)p->item_cap);
     const size_t o_E = take(8 * (size_t)std::max(p->total_nnzb, 1ll));
-    const size_t o_colprod = take(8 * (n + 1)), o_colitem = take(4 * n);
-    const size_t o_ioff = take(4 * (size_t)p->item_cap);
-    const size_t o_item = take(4 * (size_t)p->item_cap);
+    const size_t o_colprod = take(8 * (n + 1));
     const size_t o_gcp = take(8 * (n + 1));
     const size_t o_bsum = take(8 * (size_t)p->nbsum);
     const size_t o_tot = take(8 * (size_t)std::max(p->nprob, 1));
@@ -239,12 +236,8 @@ spgemm_status ensure_workspace(spgemm_plan p) {
     p->binw = (int32_t *)(b + o_binw);
     p->binlist = (int4 *)(b + o_binlist);
     p->gnnz = (int32_t *)(b + o_gnnz);
-    p->items = (int4 *)(b + o_items);
     p->E = (int2 *)(b + o_E);
     p->colprod = (long long *)(b + o_colprod);
-    p->colitem = (int32_t *)(b + o_colitem);
-    p->itemoff = (int32_t *)(b + o_ioff);
-    p->itemcnt = (int32_t *)(b + o_item);
     p->gcp = (long long *)(b + o_gcp);
     p->bsum = (long long *)(b + o_bsum);
     p->totals = (long long *)(b + o_tot);
@@ -271,7 +264,6 @@ KArgs make_args(spgemm_plan p) {
     a.nprob = p->nprob;
     a.ncols = p->ncols;
     a.ntiles = p->ntiles;
-    a.item_cap = p->item_cap;
     a.tiles = p->tiles;
     a.tune = p->tune;
     a.hdr = p->hdr;
@@ -279,21 +271,17 @@ KArgs make_args(spgemm_plan p) {
     a.binw = p->binw;
     a.binlist = p->binlist;
     a.gnnz = p->gnnz;
-    a.items = p->items;
     a.E = p->E;
     a.colprod = p->colprod;
-    a.colitem = p->colitem;
-    a.itemoff = p->itemoff;
-    a.itemcnt = p->itemcnt;
     a.prow = p->prow;
     a.dst = p->dst;
-    a.perm = p->perm;
-    a.crow = p->crow;
     a.tilestart = p->tilestart;
     a.nptiles = p->nptiles;
-    a.later_cap = p->later_cap;
     a.lk = p->lk;
     a.lr = p->lr;
+    a.gcp = p->gcp;
+    a.later_n = p->later_total;
+    a.lkc = p->lkc;
     a.lo = p->lo;
     a.lpid = p->lpid;
     a.lv = p->lv;
@@ -356,22 +344,31 @@ hipError_t join(spgemm_plan p, hipStream_t s) {
     return hipSuccess;
 }
 
+// first bin-list position of bin b
+int bin_start(const Hdr &h, int b) {
+    int f = 0;
+    for (int i = 0; i < b; ++i) f += h.bin_count[i];
+    return f;
+}
+
 // Symbolic accumulators. The kinds work on disjoint columns and run
-// concurrently so their latencies overlap: the hash row windows (few, long
-// work items) start first on their own side stream, the two larger sorts
-// share a second one, dense and the smaller hash classes a third, and the
-// sort-merge groups with the two smaller sorts run on the caller's stream.
+// concurrently so their latencies overlap: the workgroup hash classes (few,
+// long work items) start first on two side streams, the two larger sorts
+// share a third, and the wavefront sort-merge groups with the two smaller
+// sorts run on the caller's stream.
 hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream_t s) {
     const Hdr &h = p->hdr_host;
     hipError_t e;
     if ((e = fork(p, s))) return e;
-    static const char *names[kHashBins] = {"hash_s_symbolic", "hash_l_symbolic",
-                                           "hash_xl_symbolic"};
-    for (int c = kHashBins - 1; c >= 0; --c) {
-        if (!h.item_count[c]) continue;
-        hipStream_t sc = side(p, c == kHashBins - 1 ? 2 : 0, s);
-        ProfScope ps(names[c], sc);
-        if ((e = launch_window(a, WIN_HASH_S + c, h.item_count[c], sc))) return e;
+    static const char *bnames[kBlkBins] = {"block512_symbolic", "block1k_symbolic",
+                                           "block2k_symbolic", "block4k_symbolic",
+                                           "block_xl_symbolic"};
+    for (int c = kBlkBins - 1; c >= 0; --c) {
+        const int n = h.bin_count[BIN_BLK0 + c];
+        if (!n) continue;
+        hipStream_t sc = side(p, c == kBlkBins - 1 ? 2 : 0, s);
+        ProfScope ps(bnames[c], sc);
+        if ((e = launch_block(a, c, bin_start(h, BIN_BLK0 + c), n, sc))) return e;
     }
     static const char *snames[kSortBins] = {"sort512_symbolic", "sort1k_symbolic",
                                             "sort2k_symbolic", "sort4k_symbolic"};
@@ -380,10 +377,6 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
         if (!n) continue;
         ProfScope ps(snames[c], side(p, 1, s));
         if ((e = launch_sort(a, c, p->wide_keys, n, side(p, 1, s)))) return e;
-    }
-    {
-        ProfScope ps("dense_symbolic", side(p, 0, s));
-        if ((e = launch_window(a, WIN_DENSE, h.bin_count[BIN_DENSE], side(p, 0, s)))) return e;
     }
     {
         ProfScope ps("esc_symbolic", s);
@@ -398,32 +391,41 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
     return join(p, s);
 }
 
-// Numeric: one launch over the column tiles, then one small launch per
-// occurrence index of the later products.
+// Numeric: one launch over the tiles and one over the chunks of the columns
+// above t_split (concurrently), then one small launch per occurrence index of
+// the later products.
 hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
     const bool f64 = p->dt == SPGEMM_F64;
     const Hdr &h = p->hdr_host;
     hipError_t e;
-    // columns the tiles do not write in output order can only be in the
-    // largest sort bin, the dense bin and the hash bins (bin-list order)
-    int first = 0, n = 0;
-    for (int b = 0; b < BIN_SORT3; ++b) first += h.bin_count[b];
-    for (int b = BIN_SORT3; b < NBINS; ++b) n += h.bin_count[b];
+    // columns above t_split: the bins from the first one whose largest
+    // product count exceeds t_split on (bin-list order)
+    int fb = BIN_ESC0;
+    while (fb < NBINS) {
+        const long long bmax = fb < BIN_SORT0  ? (4ll << (fb - BIN_ESC0))
+                               : fb < BIN_BLK0 ? (512ll << (fb - BIN_SORT0))
+                               : fb < BIN_BLK4 ? (512ll << (fb - BIN_BLK0))
+                                               : 0x7fffffffll;
+        if (bmax > p->tune.t_split) break;
+        ++fb;
+    }
+    const int first = bin_start(h, fb);
+    int n = 0;
+    for (int b = fb; b < NBINS; ++b) n += h.bin_count[b];
     if ((e = fork(p, s))) return e;
+    if (n > 0 && h.big_chunks > 0) {
+        ProfScope ps("numeric_big", side(p, 0, s));
+        if ((e = launch_numeric_big(a, f64, first, n, h.big_chunks, side(p, 0, s)))) return e;
+    }
     {
         ProfScope ps("numeric", s);
         if ((e = launch_numeric(a, f64, s))) return e;
     }
-    {
-        // columns with more than kOrderMax products or with row windows
-        ProfScope ps("numeric_big", side(p, 0, s));
-        if ((e = launch_numeric_big(a, f64, first, n, side(p, 0, s)))) return e;
-    }
     if ((e = join(p, s))) return e;
-    if (h.later_count == 0) return hipSuccess;
+    if (p->later_total == 0) return hipSuccess;
     ProfScope ps("later_layers", s);
     for (int k = 1; k <= h.later_maxk; ++k)
-        if ((e = launch_layer(a, f64, k, (long long)h.later_count, s))) return e;
+        if ((e = launch_layer(a, f64, k, p->later_total, s))) return e;
     return hipSuccess;
 }
 
@@ -452,13 +454,6 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         SPG_TRY(hipStreamSynchronize(s));
         std::memcpy(&p->hdr_host, p->pinned, sizeof(Hdr));
         int err = p->hdr_host.err;
-        if (err & ERR_ITEMCAP) {
-            // more hash row windows than planned: grow and redo once
-            int items = 0;
-            for (int h = 0; h < kHashBins; ++h) items += p->hdr_host.item_count[h];
-            p->item_cap = items + 1024;
-            continue;
-        }
         if (err & ERR_CSC) return SPGEMM_ERR_CSC;
         if (err & ERR_OPOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
         // per-product arrays
@@ -466,7 +461,7 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         const size_t P = (size_t)std::max<unsigned long long>(hh.total_op, 1);
         const size_t q1 = align_up(4 * P, 256);
         p->nptiles = (int)(hh.total_op / kProdTile) + 1;
-        const size_t pneed = 6 * q1 + 4 * ((size_t)p->nptiles + 1);
+        const size_t pneed = 4 * q1 + 4 * ((size_t)p->nptiles + 1);
         if (pneed > p->prod_bytes) {
             if (p->prod) (void)hipFree(p->prod);
             p->prod = nullptr;
@@ -478,11 +473,7 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         p->dst = (uint32_t *)((char *)p->prod + q1);
         p->lk = (int32_t *)((char *)p->prod + 2 * q1);
         p->lr = (int32_t *)((char *)p->prod + 3 * q1);
-        p->perm = (int32_t *)((char *)p->prod + 4 * q1);
-        p->crow = (int32_t *)((char *)p->prod + 5 * q1);
-        p->tilestart = (int32_t *)((char *)p->prod + 6 * q1);
-        // later places are 31-bit indices
-        p->later_cap = (long long)std::min<size_t>(P, 0x7fffffff);
+        p->tilestart = (int32_t *)((char *)p->prod + 4 * q1);
         if (p->ncols > 0) {
             const KArgs al = make_args(p);
             {
@@ -507,10 +498,16 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         err = p->hdr_host.err;
         if (err & (ERR_CSC | ERR_GROUP)) return SPGEMM_ERR_CSC;
         if (err & (ERR_OPOVF | ERR_NNZOVF)) return SPGEMM_ERR_INDEX_OVERFLOW;
-        // staging of the later products
-        const size_t NL = (size_t)std::max<unsigned long long>(p->hdr_host.later_count, 1);
+        // staging of the later products: every product beyond the first of
+        // its entry
+        long long nnz_all = 0;
+        for (long long t : p->totals_host) nnz_all += t;
+        p->later_total = (long long)p->hdr_host.total_op - nnz_all;
+        if (p->later_total < 0) return SPGEMM_ERR_CSC;  // cannot happen
+        const size_t NL = (size_t)std::max<long long>(p->later_total, 1);
         const size_t vsz = p->dt == SPGEMM_F64 ? 8 : 4;
-        const size_t o_pid = align_up(4 * NL, 256), o_v = o_pid + align_up(4 * NL, 256);
+        const size_t o_pid = align_up(4 * NL, 256), o_k = o_pid + align_up(4 * NL, 256);
+        const size_t o_v = o_k + align_up(4 * NL, 256);
         const size_t sneed = o_v + vsz * NL;
         if (sneed > p->stage_bytes) {
             if (p->stage) (void)hipFree(p->stage);
@@ -521,6 +518,7 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         }
         p->lo = (int32_t *)p->stage;
         p->lpid = (int32_t *)((char *)p->stage + o_pid);
+        p->lkc = (int32_t *)((char *)p->stage + o_k);
         p->lv = (char *)p->stage + o_v;
         if (p->ncols == 0) {
             // no columns at all: every problem's column pointer is {0}
@@ -614,13 +612,12 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
     p->tune = tune;
     p->flags = flags;
     p->probs = std::move(probs);
-    // 32-bit sort keys hold rows below 2^20 - 1
+    // 32-bit sort keys hold rows below 2^20
     p->wide_keys = false;
-    for (const Prob &q : p->probs) p->wide_keys |= q.m >= (1 << 20);
+    for (const Prob &q : p->probs) p->wide_keys |= q.m > (1 << 20);
     p->ncols = (int)ncols;
     p->total_nnzb = nnzb_total;
     p->ntiles = (int)tiles.size();
-    p->item_cap = std::max(p->item_cap, 2 * p->ncols + 4096);
     p->symbolic_ok = false;
     p->bt_ready = false;
     (void)hipGetDevice(&p->device);
@@ -783,14 +780,24 @@ spgemm_status spgemm_plan_get_stats(spgemm_plan p, spgemm_plan_stats *out) {
     s.ncols = p->ncols;
     s.cols_empty = h.bin_count[BIN_EMPTY];
     for (int i = 0; i < kEscBins; ++i) s.cols_esc += h.bin_count[BIN_ESC0 + i];
-    s.cols_dense = h.bin_count[BIN_DENSE];
-    s.cols_hash = h.bin_count[BIN_HASH_S] + h.bin_count[BIN_HASH_L] + h.bin_count[BIN_HASH_XL];
-    s.hash_items = h.item_count[0] + h.item_count[1] + h.item_count[2];
+    for (int i = 0; i < kSortBins; ++i) s.cols_sort += h.bin_count[BIN_SORT0 + i];
+    for (int i = 0; i < kBlkBins; ++i) s.cols_block += h.bin_count[BIN_BLK0 + i];
     s.esc_groups = esc_groups(h);
     s.nprob = p->nprob;
-    for (int i = 0; i < kSortBins; ++i) s.cols_sort += h.bin_count[BIN_SORT0 + i];
+    // window flags of the workgroup columns
+    if (p->ncols > 0 && s.cols_block > 0) {
+        std::vector<int32_t> bw((size_t)p->ncols);
+        if (hipMemcpy(bw.data(), p->binw, 4 * bw.size(), hipMemcpyDeviceToHost) != hipSuccess)
+            return SPGEMM_ERR_HIP;
+        for (int32_t v : bw) {
+            const int f = v >> 8;
+            s.cols_direct += (f & WF_DIRECT) != 0;
+            s.cols_hash += (f & WF_HASH) != 0;
+            s.cols_split += (f & WF_SPLIT) != 0;
+        }
+    }
     s.later_max = h.later_maxk;
-    s.later_products = (int64_t)h.later_count;
+    s.later_products = (int64_t)p->later_total;
     *out = s;
     return SPGEMM_OK;
 }

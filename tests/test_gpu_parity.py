@@ -88,10 +88,11 @@ def test_powerlaw_reduced():
 
 
 @pytest.mark.parametrize("opts", [
-    dict(t_esc=4), dict(t_esc=16, hash_cap=128), dict(t_esc=256, hash_cap=128),
-    dict(t_dense=1), dict(t_dense=100000), dict(dense_rows=64), dict(t_esc=4, t_dense=1),
-    dict(t_sort=-1), dict(t_sort=-1, hash_cap=128), dict(t_esc=4, t_sort=600),
-    dict(t_esc=16, t_sort=1), dict(t_esc=4, t_sort=4096, t_dense=100000)])
+    dict(t_esc=4), dict(t_esc=16, hash_cap=128), dict(t_esc=256, hash_cap=16, t_block=-1),
+    dict(t_dense=100000, t_block=-1), dict(dense_rows=1, t_block=600), dict(t_esc=4, dense_rows=64),
+    dict(t_split=-1), dict(t_split=1), dict(t_esc=4, t_split=300, hash_cap=64, t_block=-1),
+    dict(t_esc=16, t_split=1, t_dense=100000, t_block=1000), dict(hash_cap=16, t_dense=100000),
+    dict(t_esc=4, hash_cap=16, dense_rows=1, t_block=-1), dict(t_block=-1), dict(t_block=512)])
 def test_forced_bins_identical(opts):
     """Any split of the work between accumulators gives the same bits (the
     t = 0 / t = infinity limits of Section 3.3 and everything between)."""
@@ -174,11 +175,71 @@ def test_stats_reported():
     assert st["total_products"] == int(op.sum())
     assert st["ncols"] == 20_000
     assert st["cols_empty"] == int((op == 0).sum())
-    assert st["cols_empty"] + st["cols_esc"] + st["cols_sort"] + st["cols_dense"] + \
-        st["cols_hash"] == 20_000
+    assert st["cols_empty"] + st["cols_esc"] + st["cols_sort"] + st["cols_block"] == 20_000
     assert st["cols_esc"] == int(((op > 0) & (op <= 256)).sum())
     assert st["cols_sort"] == int(((op > 256) & (op <= 4096)).sum())
+    assert st["cols_block"] == int((op > 4096).sum())
+    # every workgroup column has at least one row window
+    assert st["cols_direct"] + st["cols_hash"] >= st["cols_block"]
     nnz_c = int(oracle.symbolic(A, B)[-1])
     assert st["nnz_c"] == nnz_c
     # products beyond the first of every output entry
     assert st["later_products"] == int(op.sum()) - nnz_c
+
+
+def _csc_from_columns(m, cols, rng, dtype=np.float64):
+    """CSC with the given row lists per column (storage order kept), U[-1, 1]."""
+    counts = np.array([len(c) for c in cols], dtype=np.int64)
+    cp = np.zeros(len(cols) + 1, dtype=np.int64)
+    np.cumsum(counts, out=cp[1:])
+    ri = np.concatenate([np.asarray(c, dtype=np.int64) for c in cols]) if len(cols) else \
+        np.zeros(0, np.int64)
+    val = rng.uniform(-1.0, 1.0, size=len(ri)).astype(dtype)
+    return gen.CSC(m, len(cols), cp.astype(np.int32), ri.astype(np.int32), val)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(t_dense=100000), dict(hash_cap=512)])
+def test_heavy_columns_streamed(opts):
+    """Columns above the workgroup accumulator's register capacity (more than
+    12288 products) stream their rows again for every pass; with many repeated
+    rows (20000 products over 20000 rows) most products are later products."""
+    from paper_2303_02471_amd import api
+    _say(f"heavy streamed columns {opts}")
+    rng = np.random.default_rng(11)
+    A = gen.uniform_z(20000, 40, seed=11)
+    degs = [8] * 200 + [100, 200, 310, 500, 600, 600]
+    cols = [rng.choice(20000, size=d, replace=False) for d in degs]
+    B = _csc_from_columns(20000, cols, rng)
+    ocp, ori, ov = oracle.spgemm(A, B)
+    (cp, ri, v), plan, _ = gpu_product(A, B, api.options(**opts), return_plan=True)
+    assert_same_structure(cp, ri, ocp, ori, str(opts))
+    assert_values_exact(v, ov, str(opts))
+    st = plan.stats()
+    plan.close()
+    assert st["later_max"] >= 2
+
+
+def test_clustered_rows_split():
+    """Rows packed at the end of a wide row span crowd a few home slots of the
+    order-preserving hash: the window overruns its table and is split in
+    halves until the rows fit; results are unchanged."""
+    from paper_2303_02471_amd import api
+    _say("clustered rows: window splits")
+    rng = np.random.default_rng(12)
+    m = 100_000
+    acols = []
+    for _ in range(2000):
+        rows = np.concatenate([rng.choice(np.arange(m - 300, m), size=40, replace=False), [0]])
+        rng.shuffle(rows)
+        acols.append(rows)
+    A = _csc_from_columns(m, acols, rng)
+    B = _csc_from_columns(2000, [rng.choice(2000, size=60, replace=False) for _ in range(200)],
+                          rng)
+    ocp, ori, ov = oracle.spgemm(A, B)
+    for opts in (dict(t_block=-1), dict(t_block=-1, t_dense=100000)):
+        (cp, ri, v), plan, _ = gpu_product(A, B, api.options(**opts), return_plan=True)
+        assert_same_structure(cp, ri, ocp, ori, f"clustered {opts}")
+        assert_values_exact(v, ov, f"clustered {opts}")
+        st = plan.stats()
+        plan.close()
+        assert st["cols_split"] > 0

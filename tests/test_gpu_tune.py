@@ -37,7 +37,7 @@ def test_autotune_single_cached(tmp_path):
     assert_values_exact(v, ov, "tuned")
     opts2, rep2 = api.autotune([(At, Bt)], torch.float64, cache_path=path)
     assert rep2["from_cache"] == 1 and rep2["trials"] == 0
-    for f in ("t_esc", "t_dense", "dense_rows", "hash_cap", "t_sort"):
+    for f in ("t_esc", "t_dense", "dense_rows", "hash_cap", "t_split", "t_block"):
         assert getattr(opts2, f) == getattr(opts, f)
     # lookup only with an unknown workload: not tuned, nothing timed
     C = gen.uniform_z(5000, 3, seed=1)

@@ -6,13 +6,13 @@ import pytest
 from paper_2303_02471_amd import _lib, api
 
 
-def _opts(t_esc=128, t_dense=512, dense_rows=4096, hash_cap=2048, t_sort=-1):
-    return _lib.Options(t_esc, t_dense, dense_rows, hash_cap, 0, t_sort)
+def _opts(t_esc=128, t_dense=512, dense_rows=4096, hash_cap=2048, t_split=-1, t_block=2048):
+    return _lib.Options(t_esc, t_dense, dense_rows, hash_cap, 0, t_split, t_block)
 
 
 def _same(a, b):
     return all(getattr(a, f) == getattr(b, f)
-               for f in ("t_esc", "t_dense", "dense_rows", "hash_cap", "t_sort"))
+               for f in ("t_esc", "t_dense", "dense_rows", "hash_cap", "t_split", "t_block"))
 
 
 def test_key_buckets():
@@ -32,11 +32,11 @@ def test_store_load_roundtrip(tmp_path):
     path = str(tmp_path / "tune.json")
     assert api.tune_cache_load(path, "a") is None  # no file
     api.tune_cache_store(path, "a", _opts(t_esc=64), 1.5)
-    api.tune_cache_store(path, "b|x\"y", _opts(t_sort=2048), 2.5)
+    api.tune_cache_store(path, "b|x\"y", _opts(t_split=2048), 2.5)
     got = api.tune_cache_load(path, "a")
     assert got is not None and _same(got, _opts(t_esc=64))
     got = api.tune_cache_load(path, "b|x\"y")
-    assert got is not None and _same(got, _opts(t_sort=2048))
+    assert got is not None and _same(got, _opts(t_split=2048))
     assert api.tune_cache_load(path, "c") is None
     # replacing an entry keeps the others; the file is plain JSON
     api.tune_cache_store(path, "a", _opts(t_esc=32), 0.5)
@@ -67,9 +67,9 @@ def test_out_of_range_entry_unused(tmp_path):
     with open(path, "w") as f:
         json.dump({"spgemm_tune_cache": 1, "entries": [
             {"key": "a", "t_esc": 3, "t_dense": 512, "dense_rows": 4096, "hash_cap": 4096,
-             "t_sort": 4096, "ms": 1.0},
+             "t_split": 4096, "ms": 1.0},
             {"key": "b", "t_esc": 64, "t_dense": 512, "dense_rows": 4096, "hash_cap": 4096,
-             "t_sort": 4096, "ms": 1.0, "extra": [1, {"x": None}]}]}, f)
+             "t_split": 4096, "ms": 1.0, "extra": [1, {"x": None}]}]}, f)
     assert api.tune_cache_load(path, "a") is None
     got = api.tune_cache_load(path, "b")
     assert got is not None and got.t_esc == 64
