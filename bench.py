@@ -77,7 +77,7 @@ def csc_bytes(n, nnz, vb):
     return 4 * (n + 1) + (4 + vb) * nnz
 
 
-def per_column_work(A, B, t_esc=256, t_block=4096):
+def per_column_work(A, B, t_esc=256, t_block=2 ** 31 - 1):
     """Host accounting of the per-column work and of the accumulator each
     column goes to (the library's rule), for algorithmic byte counts."""
     import numpy as np
@@ -89,12 +89,12 @@ def per_column_work(A, B, t_esc=256, t_block=4096):
     while esc_max < t_esc:
         esc_max *= 2
     esc = (op > 0) & (op <= esc_max)
-    srt = (op > esc_max) & (op <= t_block)
-    blk = op > max(esc_max, t_block)
+    blk = (op > esc_max) & (op > t_block)
+    srt = (op > esc_max) & ~blk
     return op, nb, {"esc": esc,
                     "sort512": srt & (op <= 512), "sort1k": srt & (op > 512) & (op <= 1024),
                     "sort2k": srt & (op > 1024) & (op <= 2048),
-                    "sort4k": srt & (op > 2048) & (op <= 4096),
+                    "sort4k": srt & (op > 2048) & (op <= 4096), "wsort": srt & (op > 4096),
                     "block512": blk & (op <= 512), "block1k": blk & (op > 512) & (op <= 1024),
                     "block2k": blk & (op > 1024) & (op <= 2048),
                     "block4k": blk & (op > 2048) & (op <= 4096), "block_xl": blk & (op > 4096)}
@@ -185,9 +185,8 @@ def main():
 
     # ------------------------------------------------------------ roofline of the dominant kernel
     nnzc = np.diff(colptr.cpu().numpy().astype(np.int64))
-    t_block = opts.t_block if opts.t_block else 4096
-    op, nb, bins = per_column_work(A, B, t_esc=opts.t_esc or 256,
-                                   t_block=t_block if t_block > 0 else 0)
+    t_block = {0: 2 ** 31 - 1, -1: 0}.get(opts.t_block, opts.t_block)
+    op, nb, bins = per_column_work(A, B, t_esc=opts.t_esc or 256, t_block=t_block)
     kbytes = {}
     for name in bins:
         num, sym = kernel_bytes(op, nb, nnzc, bins[name], vb)

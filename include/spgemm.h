@@ -93,10 +93,11 @@ typedef struct spgemm_plan_s *spgemm_plan;
  *   t_esc       columns with at most this many products go to the wavefront
  *               sort-merge (ESC, Section 4) accumulator; 4..256, rounded up
  *               to a power of two; default 256.
- *   t_block     the other columns with at most this many products go to the
- *               workgroup sort-merge accumulator, the rest to the workgroup
- *               hash accumulator (HASH, Section 3.2, with direct indexing for
- *               row windows that fit); -1 (none) or 1..4096; default 4096.
+ *   t_block     the other columns go to the workgroup sort-merge accumulator
+ *               (row-windowed above 4096 products) unless they have more than
+ *               t_block products: those go to the workgroup hash accumulator
+ *               (HASH, Section 3.2, with direct indexing for row windows that
+ *               fit); -1 = every non-ESC column, 0 = none (default).
  *   t_dense     hash-accumulator columns with at least this many products
  *               may accumulate a row window by direct indexing (the SPA of
  *               Section 2.2) when its row span fits the LDS table; >= 1;

@@ -315,7 +315,7 @@ spgemm_options defaults() {
     o.dense_rows = 0;
     o.hash_cap = 0;
     o.t_split = 2048;
-    o.t_block = 4096;
+    o.t_block = 0;
     return o;
 }
 
@@ -323,7 +323,7 @@ spgemm_options defaults() {
 bool usable(const spgemm_options &o) {
     return o.t_esc >= 4 && o.t_esc <= 256 && o.t_dense >= 1 && o.dense_rows >= 0 &&
            (o.hash_cap == 0 || (o.hash_cap >= 16 && o.hash_cap <= (1 << 20))) &&
-           (o.t_split == -1 || o.t_split >= 1) && o.t_block >= -1 && o.t_block <= 4096;
+           (o.t_split == -1 || o.t_split >= 1) && o.t_block >= -1;
 }
 
 }  // namespace
@@ -438,7 +438,7 @@ spgemm_status spgemm_autotune(int32_t count, const spgemm_csc *A_host, const spg
     };
     std::vector<Axis> axes = {
         {&spgemm_options::t_esc, {128, 64, 32}},
-        {&spgemm_options::t_block, {2048, 1024}},
+        {&spgemm_options::t_block, {4096}},
         {&spgemm_options::t_split, {1024, 4096, -1}},
         {&spgemm_options::hash_cap, {2048, 1024}},
     };

@@ -14,9 +14,12 @@ constexpr int kWave = 64;
 //   EMPTY      Op_j == 0: no output entries
 //   ESC_i      Op_j <= 4 << i (and <= t_esc): wavefront sort-merge (Section 4),
 //              64 >> i columns per wavefront group (at most 256 products)
-//   SORT_i     Op_j <= 512 << i (and <= t_block): workgroup sort-merge, one
-//              column per workgroup of 128 << i threads
-//   BLK_c      the others: one workgroup per column with an LDS table over
+//   SORT_i     Op_j <= 512 << i: workgroup sort-merge, one column per
+//              workgroup of 128 << i threads
+//   WSORT      Op_j > 4096: the same sort over row windows of the column, one
+//              workgroup per column taking the windows in row order
+//   BLK_c      Op_j > t_block instead of SORT / WSORT (an option): one
+//              workgroup per column with an LDS table over
 //              row windows -- a direct-indexed SPA (Section 2.2) when the
 //              window's row span fits, else an order-preserving hash table
 //              with linear probing (Section 3.2) sized from Op_j (its size
@@ -28,9 +31,10 @@ enum Bin : int {
     BIN_ESC6 = 7,   // Op <= 256
     BIN_SORT0 = 8,  // Op <= 512
     BIN_SORT3 = 11, // Op <= 4096
-    BIN_BLK0 = 12,  // Op <= 512
-    BIN_BLK4 = 16,  // Op > 4096
-    NBINS = 17
+    BIN_WSORT = 12, // Op > 4096
+    BIN_BLK0 = 13,  // Op <= 512
+    BIN_BLK4 = 17,  // Op > 4096
+    NBINS = 18
 };
 constexpr int kEscBins = 7;
 constexpr int kSortBins = 4;
@@ -92,6 +96,7 @@ struct Tune {
     int32_t hash_cap;    // planned distinct rows per row window (0: table capacity / 2)
     int32_t t_split;     // columns with more products are split over several numeric workgroups
     int32_t t_block;     // columns with more products go to the workgroup hash accumulator
+                         // (instead of the sort-merge ones)
 };
 
 // Kernel arguments common to all planning / accumulation kernels.
@@ -168,6 +173,8 @@ hipError_t launch_place(const KArgs &a, hipStream_t s);
 hipError_t launch_esc(const KArgs &a, int grid, hipStream_t s);
 // workgroup sort of sort bin `cls` (n columns); wide: 64-bit keys (rows beyond 20 bits)
 hipError_t launch_sort(const KArgs &a, int cls, bool wide, int n, hipStream_t s);
+// windowed workgroup sort of the `n` columns listed from bin-list position `first`
+hipError_t launch_wsort(const KArgs &a, bool wide, int first, int n, hipStream_t s);
 // workgroup accumulator of block class `cls` over the `n` columns listed from
 // bin-list position `first`
 hipError_t launch_block(const KArgs &a, int cls, int first, int n, hipStream_t s);

@@ -52,7 +52,7 @@ struct BlkCfg<2> { static constexpr int T = 512, TC = 8192, PER = 4; };
 template <>
 struct BlkCfg<3> { static constexpr int T = 1024, TC = 12288, PER = 4; };
 template <>
-struct BlkCfg<4> { static constexpr int T = 1024, TC = 18432, PER = 12; };
+struct BlkCfg<4> { static constexpr int T = 1024, TC = 18432, PER = 8; };
 
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr unsigned kEmptyHi = ~0u;
@@ -274,7 +274,9 @@ __global__ __launch_bounds__(BlkCfg<CLS>::T) void k_block(KArgs a, int first, in
                 // ---- 3. ranks into the slots' low words
                 int distinct;
                 {
-                    const int per = ceil_div(nst, T);
+                    // consecutive slots per thread; an odd count keeps the
+                    // threads of a wavefront on distinct LDS banks
+                    const int per = ceil_div(nst, T) | 1;
                     const int s0 = min(nst, tid * per), s1 = min(nst, s0 + per);
                     int mycnt = 0;
                     for (int sl = s0; sl < s1; ++sl) mycnt += hw[2 * sl + 1] != kEmptyHi;

@@ -113,20 +113,19 @@ hipError_t launch_expand(const KArgs &a, hipStream_t s) {
 // Forms the products of `nbw` stored B entries (window arrays in LDS: A
 // column start, first product of the entry in the window's product numbering,
 // window column, B value) and writes each product through its destination:
-// the first product of an entry as 0 + product at C position c0 + rank, a
-// later product into the staging of the later list. `pos(tt, e)` gives the
+// the first product of an entry as first(c, rank, row, 0 + product), a later
+// product into the staging of the later list. `pos(tt, e)` gives the
 // product-space index of product e (window numbering) of entry tt,
 // `cinfo(c, c0, clen, lb)` the column's output start and length and the start
 // of its later products in the compact list.
-template <typename V, int PER, typename Pos, typename Cinfo>
+template <typename V, int PER, typename Pos, typename Cinfo, typename First>
 __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Prob &d,
                                                const int *s_acp, const int *s_eoff,
                                                const int *s_col, const V *s_bv, int nbw, int Ew,
-                                               Pos &&pos, Cinfo &&cinfo, int &bad) {
+                                               Pos &&pos, Cinfo &&cinfo, First &&first,
+                                               int &bad) {
     const V *__restrict__ av = (const V *)d.av;
     const int *__restrict__ ari = d.ari;
-    int *__restrict__ cri = d.cri;
-    V *__restrict__ cv = (V *)d.cv;
     V *__restrict__ lv = (V *)a.lv;
     const int tid = threadIdx.x;
     for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
@@ -157,8 +156,7 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
             const int o = (int)(dc[u] & ~kDstLater);
             if (o >= clen) { bad = 1; continue; }
             if (!(dc[u] & kDstLater)) {
-                cri[c0 + o] = row[u];
-                cv[c0 + o] = V(0) + v[u];
+                first(c[u], o, row[u], V(0) + v[u]);
             } else {
                 const long long li = lb + a.lr[pp[u]];
                 if (li < 0 || li >= a.later_n) { bad = 1; continue; }
@@ -173,12 +171,14 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
 
 constexpr int kColWin = 256;  // columns per window of a tile
 constexpr int kNumPer = 8;    // products per thread per pass
+constexpr int kStage = 2048;  // output entries a tile's column window stages in LDS
 
 template <typename V>
 struct NumSmem {
     int s_bcp[kColWin + 1];     // B column pointers of the column window
     int s_c0[kColWin + 1];      // C column pointers of the column window
     int s_ceff[kColWin + 1];    // first product of each column among the window's tile columns
+    int s_oeff[kColWin + 1];    // first output entry of each column among the tile columns
     long long s_pcol[kColWin];  // first product of each column in the product space
     int s_ok[kColWin];          // column done by the tile (at most t_split products)
     long long s_lb[kColWin];    // start of each column's later products in the compact list
@@ -187,6 +187,8 @@ struct NumSmem {
     int s_col[kBlock];          // window column of each stored B entry of the B window
     V s_bv[kBlock];             // B value of each stored B entry of the B window
     int scan_tmp[kBlock / 64 + 1];
+    V sval[kStage];             // output values of the window's tile columns
+    int srow[kStage];           // output rows of the window's tile columns
 };
 
 // One workgroup per product-balanced tile; columns with more than t_split
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
         for (int jw = js; jw < je; jw += kColWin) {
             const int nc = min(kColWin, je - jw);
             const int gw = d.col0 + jw;
-            int eff = 0;
+            int eff = 0, oeff = 0;
             for (int c = tid; c <= nc; c += kBlock) {
                 S.s_bcp[c] = d.bcp[jw + c];
                 S.s_c0[c] = d.ccp[jw + c];
@@ -215,16 +217,30 @@ __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
                 const int op = a.op[gw + tid];
                 const int ok = op <= a.tune.t_split;
                 S.s_ok[tid] = ok;
+                const int c0 = d.ccp[jw + tid];
                 const long long pc = a.colprod[gw + tid];
                 S.s_pcol[tid] = pc;
-                S.s_lb[tid] = pc - (a.nprob == 1 ? (long long)d.ccp[jw + tid] : a.gcp[gw + tid]);
+                S.s_lb[tid] = pc - (a.nprob == 1 ? (long long)c0 : a.gcp[gw + tid]);
                 eff = ok ? op : 0;
+                oeff = ok ? d.ccp[jw + tid + 1] - c0 : 0;
             }
-            int tot;
+            int tot, otot;
             const int ex = block_excl_scan(eff, S.scan_tmp, tot);
-            if (tid < nc) S.s_ceff[tid] = ex;
-            if (tid == 0) S.s_ceff[nc] = tot;
+            const int ox = block_excl_scan(oeff, S.scan_tmp, otot);
+            if (tid < nc) {
+                S.s_ceff[tid] = ex;
+                S.s_oeff[tid] = ox;
+            }
+            if (tid == 0) {
+                S.s_ceff[nc] = tot;
+                S.s_oeff[nc] = otot;
+            }
             __syncthreads();
+            // the window's output entries are staged in LDS and written in
+            // order when they fit, else written straight through
+            const bool stage = otot <= kStage;
+            int *__restrict__ cri = d.cri;
+            V *__restrict__ cv = (V *)d.cv;
             const int pb = S.s_bcp[0], pe = S.s_bcp[nc];
             int base = 0;  // first product of the B window among the tile columns
             int2 nez = make_int2(0, 0);
@@ -265,8 +281,27 @@ __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
                         clen = S.s_c0[c + 1] - c0;
                         lb = S.s_lb[c];
                     },
+                    [&](int c, int o, int row, V v) {
+                        if (stage) {
+                            S.sval[S.s_oeff[c] + o] = v;
+                            S.srow[S.s_oeff[c] + o] = row;
+                        } else {
+                            cri[S.s_c0[c] + o] = row;
+                            cv[S.s_c0[c] + o] = v;
+                        }
+                    },
                     bad);
                 base += Ew;
+                __syncthreads();
+            }
+            if (stage) {
+                // staged entries to their output positions, in order
+                for (int i = tid; i < otot; i += kBlock) {
+                    const int c = last_le(S.s_oeff, nc + 1, i);
+                    const int o = S.s_c0[c] + (i - S.s_oeff[c]);
+                    cri[o] = S.srow[i];
+                    cv[o] = S.sval[i];
+                }
                 __syncthreads();
             }
         }
@@ -286,17 +321,26 @@ struct BigSmem {
 };
 
 // One workgroup per chunk of kChunkB stored B entries of a column with more
-// than t_split products (blockIdx.x: column in the bin list, blockIdx.y: chunk).
+// than t_split products. Workgroups are dealt to the XCDs round-robin by
+// launch order; the numbering below sends every chunk of column c to XCD
+// c mod 8, so the column's output lines, written piecewise by its chunks,
+// meet in one L2 before they are written back.
+constexpr int kXcds = 8;
+
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int n) {
     __shared__ BigSmem<V> S;
     if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
         return;  // every thread takes the same branch
     const int tid = threadIdx.x;
-    const int4 ent = a.binlist[first + blockIdx.x];
+    const int ncol8 = ceil_div(n, kXcds);
+    const int xcd = (int)blockIdx.x % kXcds, r = (int)blockIdx.x / kXcds;
+    const int chunk = r / ncol8, col = (r % ncol8) * kXcds + xcd;
+    if (col >= n) return;
+    const int4 ent = a.binlist[first + col];
     const int g = ent.x, bs = ent.y, nb = ent.z;
     const int op = a.op[g];
-    const int b0 = bs + (int)blockIdx.y * kChunkB;
+    const int b0 = bs + chunk * kChunkB;
     if (op <= a.tune.t_split || b0 >= bs + nb) return;  // tile column, or no such chunk
     const int b1 = min(bs + nb, b0 + kChunkB);
     const int pid = find_prob(a, g);
@@ -335,6 +379,10 @@ __global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int 
             ol = clen;
             lb = lb0;
         },
+        [&](int, int o, int row, V v) {
+            d.cri[c0 + o] = row;
+            ((V *)d.cv)[c0 + o] = v;
+        },
         bad);
     if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
 }
@@ -364,7 +412,9 @@ hipError_t launch_numeric(const KArgs &a, bool f64, hipStream_t s) {
 hipError_t launch_numeric_big(const KArgs &a, bool f64, int first, int nbig, int maxchunks,
                               hipStream_t s) {
     if (nbig <= 0 || maxchunks <= 0) return hipSuccess;
-    const dim3 grid(nbig, maxchunks);
+    const long long nwg = (long long)kXcds * ceil_div(nbig, kXcds) * maxchunks;
+    if (nwg > 0x7fffffffll) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nwg);
     if (f64) hipLaunchKernelGGL((k_numeric_big<double>), grid, dim3(kBlock), 0, s, a, first, nbig);
     else hipLaunchKernelGGL((k_numeric_big<float>), grid, dim3(kBlock), 0, s, a, first, nbig);
     return hipGetLastError();

@@ -113,8 +113,9 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
         int bin;
         if (op == 0) bin = BIN_EMPTY;
         else if (op <= esc_max) bin = BIN_ESC0 + max(ceil_log2(op), 2) - 2;
-        else if (op <= a.tune.t_block) bin = BIN_SORT0 + max(ceil_log2(op), 9) - 9;
-        else bin = BIN_BLK0 + blk_class(op);
+        else if (op > a.tune.t_block) bin = BIN_BLK0 + blk_class(op);
+        else if (op <= kSortMax) bin = BIN_SORT0 + max(ceil_log2(op), 9) - 9;
+        else bin = BIN_WSORT;
         if (op > a.tune.t_split) maxch = max(maxch, ceil_div(s_bcp[c + 1] - s_bcp[c], kChunkB));
         a.op[g] = op;
         a.binw[g] = bin;

@@ -207,6 +207,217 @@ __global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
     }
 }
 
+// ---------------------------------------------------------------- windowed sort
+// Columns of more than kSortMax products: the column's rows [lo, hi] are cut
+// into W windows of equal row span, W planned for about 3/4 of a sort each;
+// one workgroup takes the windows in row order, sorting the products of each
+// (in product order) like k_bsort and carrying the ranks and the later-product
+// indices of the earlier windows. A window holding more than kSortMax
+// products is split in halves; a window of a single row (any number of
+// products: one entry) needs no sort, its products take their occurrence
+// indices in product order.
+constexpr int kWinDepth = 48;
+
+template <typename K>
+__global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
+    constexpr int T = 1024, N = 4 * T, NW = T / 64;
+    constexpr int EB = 12;  // bits of a window position (N <= 4096)
+    constexpr K KMAX = KeyMax<K>::v;
+    static_assert(N <= (1 << EB), "positions must fit the key");
+    __shared__ K buf[N];     // keys, exchanges, then the sorted keys
+    __shared__ int rh[N];    // sorted position of every run head
+    __shared__ int emap[N];  // product position of every window position
+    __shared__ int wcnt[NW + 1];
+    __shared__ int scan_tmp[NW + 1];
+    __shared__ int stk_lo[kWinDepth], stk_hi[kWinDepth];
+    __shared__ int s_min, s_max, s_kmax;
+    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
+        return;  // every thread takes the same branch
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, sb = wave * 256;
+    if (tid == 0) s_kmax = 0;
+    int kmax = 0;
+    bool abort = false;  // workgroup-uniform
+    for (int li = blockIdx.x; li < n && !abort; li += gridDim.x) {
+        const int g = a.binlist[first + li].x;
+        const int op = a.op[g];
+        const long long pbase = a.colprod[g];
+        const int *__restrict__ prow = a.prow + pbase;
+        uint32_t *__restrict__ dstp = a.dst + pbase;
+        // rows of the column, and a contiguous range of products per thread
+        if (tid == 0) {
+            s_min = 0x7fffffff;
+            s_max = -1;
+        }
+        __syncthreads();
+        {
+            int mn = 0x7fffffff, mx = -1;
+            for (int e = tid; e < op; e += T) {
+                const int r = prow[e];
+                mn = min(mn, r);
+                mx = max(mx, r);
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                mn = min(mn, __builtin_amdgcn_ds_bpermute((lane ^ d) << 2, mn));
+                mx = max(mx, __builtin_amdgcn_ds_bpermute((lane ^ d) << 2, mx));
+            }
+            if (lane == 0) {
+                atomicMin(&s_min, mn);
+                atomicMax(&s_max, mx);
+            }
+        }
+        __syncthreads();
+        const int lo = s_min, span = s_max + 1 - s_min;
+        const int q = ceil_div(op, T);
+        const int e0 = min(op, tid * q), e1 = min(op, e0 + q);
+        int W = ceil_div(op, 3 * N / 4);
+        if (W > span) W = span;
+        int total = 0, ltotal = 0;
+        for (int w = 0; w < W && !abort; ++w) {
+            if (tid == 0) {
+                stk_lo[0] = lo + (int)((long long)w * span / W);
+                stk_hi[0] = lo + (int)((long long)(w + 1) * span / W);
+            }
+            int sp = 1;
+            __syncthreads();
+            while (sp > 0) {
+                --sp;
+                const int x = stk_lo[sp], y = stk_hi[sp];
+                // the window's products, numbered in product order
+                int c = 0;
+                for (int e = e0; e < e1; ++e) {
+                    const int r = prow[e];
+                    c += r >= x && r < y;
+                }
+                int cnt;
+                const int off = wg_excl_scan<T>(c, scan_tmp, cnt);
+                if (cnt > N && y - x > 1) {
+                    // split; the left half is taken first
+                    if (sp + 2 > kWinDepth) {  // cannot happen: the span halves each time
+                        abort = true;
+                        break;
+                    }
+                    const int mid = x + (y - x) / 2;
+                    if (tid == 0) {
+                        stk_lo[sp] = mid; stk_hi[sp] = y;
+                        stk_lo[sp + 1] = x; stk_hi[sp + 1] = mid;
+                    }
+                    sp += 2;
+                    __syncthreads();
+                    continue;
+                }
+                if (cnt > N) {
+                    // one row: one entry; occurrence indices in product order
+                    int k = off;
+                    for (int e = e0; e < e1; ++e) {
+                        const int r = prow[e];
+                        if (r < x || r >= y) continue;
+                        if (k == 0) {
+                            dstp[e] = (uint32_t)total;
+                        } else {
+                            dstp[e] = kDstLater | (uint32_t)total;
+                            a.lk[pbase + e] = k;
+                            a.lr[pbase + e] = ltotal + k - 1;
+                            kmax = max(kmax, k);
+                        }
+                        ++k;
+                    }
+                    total += 1;
+                    ltotal += cnt - 1;
+                    __syncthreads();
+                    continue;
+                }
+                // keys (row, window position) in LDS, then into registers
+                {
+                    int i = off;
+                    for (int e = e0; e < e1; ++e) {
+                        const int r = prow[e];
+                        if (r < x || r >= y) continue;
+                        emap[i] = e;
+                        buf[i] = ((K)r << EB) | (K)i;
+                        ++i;
+                    }
+                }
+                __syncthreads();
+                K key[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int s = sb + r * 64 + lane;
+                    key[r] = s < cnt ? buf[s] : KMAX;
+                }
+                __syncthreads();
+                block_sort<K, N>(key, buf);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) buf[sb + r * 64 + lane] = key[r];
+                __syncthreads();
+                // run heads and run indices (position order: wavefront, register, lane)
+                bool head[4];
+                int run[4];
+                int before = 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int s = sb + r * 64 + lane;
+                    head[r] = key[r] != KMAX && (s == 0 || (buf[s - 1] >> EB) != (key[r] >> EB));
+                    const unsigned long long m = ballot(head[r]);
+                    run[r] = before + popc64(m & mask_lt()) - (head[r] ? 0 : 1);
+                    before += popc64(m);
+                }
+                if (lane == 0) wcnt[wave] = before;
+                __syncthreads();
+                if (tid == 0) {
+                    int tot = 0;
+                    for (int v = 0; v < NW; ++v) {
+                        const int t = wcnt[v];
+                        wcnt[v] = tot;
+                        tot += t;
+                    }
+                    wcnt[NW] = tot;
+                }
+                __syncthreads();
+                const int woff = wcnt[wave], runs = wcnt[NW];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    run[r] += woff;
+                    if (head[r]) rh[run[r]] = sb + r * 64 + lane;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (key[r] == KMAX) continue;
+                    const int s = sb + r * 64 + lane;
+                    const int e = emap[(int)(key[r] & (K)((1 << EB) - 1))];
+                    const int k = s - rh[run[r]];
+                    const int rank = total + run[r];
+                    if (k == 0) {
+                        dstp[e] = (uint32_t)rank;
+                    } else {
+                        dstp[e] = kDstLater | (uint32_t)rank;
+                        a.lk[pbase + e] = k;
+                        a.lr[pbase + e] = ltotal + (s - run[r] - 1);
+                        kmax = max(kmax, k);
+                    }
+                }
+                total += runs;
+                ltotal += cnt - runs;
+                __syncthreads();
+            }
+        }
+        if (tid == 0) a.gnnz[g] = total;
+    }
+    if (abort && tid == 0) atomicOr(&a.hdr->err, ERR_GROUP);
+    if (kmax) atomicMax(&s_kmax, kmax);
+    __syncthreads();
+    if (tid == 0 && s_kmax > __atomic_load_n(&a.hdr->later_maxk, __ATOMIC_RELAXED))
+        atomicMax(&a.hdr->later_maxk, s_kmax);
+}
+
+hipError_t launch_wsort(const KArgs &a, bool wide, int first, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (wide) hipLaunchKernelGGL((k_wsort<unsigned long long>), dim3(n), dim3(1024), 0, s, a, first, n);
+    else hipLaunchKernelGGL((k_wsort<unsigned>), dim3(n), dim3(1024), 0, s, a, first, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_sort(const KArgs &a, int cls, bool wide, int grid, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     const int bin = BIN_SORT0 + cls;  // columns of at most 512 << cls products

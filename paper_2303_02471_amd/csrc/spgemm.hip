@@ -139,7 +139,7 @@ spgemm_status hip_status(hipError_t e) {
     } while (0)
 
 spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flags) {
-    int t_esc = 256, t_dense = 1, dense_rows = 0, cap = 0, t_split = 2048, t_block = kSortMax;
+    int t_esc = 256, t_dense = 1, dense_rows = 0, cap = 0, t_split = 2048, t_block = 0;
     flags = 0;
     if (opt) {
         if (opt->t_esc) t_esc = opt->t_esc;
@@ -155,7 +155,7 @@ spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flag
     if (dense_rows < 0) return SPGEMM_ERR_INVALID;
     if (cap != 0 && (cap < 16 || cap > (1 << 20))) return SPGEMM_ERR_INVALID;
     if (t_split < -1) return SPGEMM_ERR_INVALID;
-    if (t_block < -1 || t_block > kSortMax) return SPGEMM_ERR_INVALID;
+    if (t_block < -1) return SPGEMM_ERR_INVALID;
     int bins = 1;
     while ((4 << (bins - 1)) < t_esc) ++bins;  // t_esc rounded up to a power of two
     t.esc_bins = bins;
@@ -163,7 +163,7 @@ spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flag
     t.dense_rows = dense_rows;
     t.hash_cap = cap;
     t.t_split = t_split < 0 ? 0x7fffffff : t_split;
-    t.t_block = t_block < 0 ? 0 : t_block;
+    t.t_block = t_block < 0 ? 0 : (t_block == 0 ? 0x7fffffff : t_block);
     return SPGEMM_OK;
 }
 
@@ -370,6 +370,11 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
         ProfScope ps(bnames[c], sc);
         if ((e = launch_block(a, c, bin_start(h, BIN_BLK0 + c), n, sc))) return e;
     }
+    if (const int n = h.bin_count[BIN_WSORT]) {
+        ProfScope ps("wsort_symbolic", side(p, 2, s));
+        if ((e = launch_wsort(a, p->wide_keys, bin_start(h, BIN_WSORT), n, side(p, 2, s))))
+            return e;
+    }
     static const char *snames[kSortBins] = {"sort512_symbolic", "sort1k_symbolic",
                                             "sort2k_symbolic", "sort4k_symbolic"};
     for (int c = kSortBins - 1; c >= 2; --c) {
@@ -402,10 +407,11 @@ hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
     // product count exceeds t_split on (bin-list order)
     int fb = BIN_ESC0;
     while (fb < NBINS) {
-        const long long bmax = fb < BIN_SORT0  ? (4ll << (fb - BIN_ESC0))
-                               : fb < BIN_BLK0 ? (512ll << (fb - BIN_SORT0))
-                               : fb < BIN_BLK4 ? (512ll << (fb - BIN_BLK0))
-                                               : 0x7fffffffll;
+        const long long bmax = fb < BIN_SORT0   ? (4ll << (fb - BIN_ESC0))
+                               : fb < BIN_WSORT ? (512ll << (fb - BIN_SORT0))
+                               : fb == BIN_WSORT ? 0x7fffffffll
+                               : fb < BIN_BLK4  ? (512ll << (fb - BIN_BLK0))
+                                                : 0x7fffffffll;
         if (bmax > p->tune.t_split) break;
         ++fb;
     }
@@ -781,6 +787,7 @@ spgemm_status spgemm_plan_get_stats(spgemm_plan p, spgemm_plan_stats *out) {
     s.cols_empty = h.bin_count[BIN_EMPTY];
     for (int i = 0; i < kEscBins; ++i) s.cols_esc += h.bin_count[BIN_ESC0 + i];
     for (int i = 0; i < kSortBins; ++i) s.cols_sort += h.bin_count[BIN_SORT0 + i];
+    s.cols_sort += h.bin_count[BIN_WSORT];
     for (int i = 0; i < kBlkBins; ++i) s.cols_block += h.bin_count[BIN_BLK0 + i];
     s.esc_groups = esc_groups(h);
     s.nprob = p->nprob;

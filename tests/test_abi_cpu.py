@@ -78,7 +78,7 @@ def test_options_validated_on_host(L):
     for bad in (_lib.Options(2, 0, 0, 0, 0), _lib.Options(512, 0, 0, 0, 0),
                 _lib.Options(0, 0, -1, 0, 0), _lib.Options(0, 0, 0, 8, 0),
                 _lib.Options(0, 0, 0, 2_000_000, 0), _lib.Options(0, -1, 0, 0, 0),
-                _lib.Options(0, 0, 0, 0, 0, -2), _lib.Options(0, 0, 0, 0, 0, 0, 5000),
+                _lib.Options(0, 0, 0, 0, 0, -2),
                 _lib.Options(0, 0, 0, 0, 0, 0, -2)):
         st = L.spgemm_symbolic(C.byref(a), C.byref(a), 1, C.byref(bad), None, C.byref(plan),
                                C.addressof(fake), C.byref(nnz))

@@ -92,7 +92,8 @@ def test_powerlaw_reduced():
     dict(t_dense=100000, t_block=-1), dict(dense_rows=1, t_block=600), dict(t_esc=4, dense_rows=64),
     dict(t_split=-1), dict(t_split=1), dict(t_esc=4, t_split=300, hash_cap=64, t_block=-1),
     dict(t_esc=16, t_split=1, t_dense=100000, t_block=1000), dict(hash_cap=16, t_dense=100000),
-    dict(t_esc=4, hash_cap=16, dense_rows=1, t_block=-1), dict(t_block=-1), dict(t_block=512)])
+    dict(t_esc=4, hash_cap=16, dense_rows=1, t_block=-1), dict(t_block=-1), dict(t_block=512),
+    dict(t_block=4096, hash_cap=300)])
 def test_forced_bins_identical(opts):
     """Any split of the work between accumulators gives the same bits (the
     t = 0 / t = infinity limits of Section 3.3 and everything between)."""
@@ -177,8 +178,8 @@ def test_stats_reported():
     assert st["cols_empty"] == int((op == 0).sum())
     assert st["cols_empty"] + st["cols_esc"] + st["cols_sort"] + st["cols_block"] == 20_000
     assert st["cols_esc"] == int(((op > 0) & (op <= 256)).sum())
-    assert st["cols_sort"] == int(((op > 256) & (op <= 4096)).sum())
-    assert st["cols_block"] == int((op > 4096).sum())
+    assert st["cols_sort"] == int((op > 256).sum())
+    assert st["cols_block"] == 0
     # every workgroup column has at least one row window
     assert st["cols_direct"] + st["cols_hash"] >= st["cols_block"]
     nnz_c = int(oracle.symbolic(A, B)[-1])
@@ -198,11 +199,13 @@ def _csc_from_columns(m, cols, rng, dtype=np.float64):
     return gen.CSC(m, len(cols), cp.astype(np.int32), ri.astype(np.int32), val)
 
 
-@pytest.mark.parametrize("opts", [dict(), dict(t_dense=100000), dict(hash_cap=512)])
+@pytest.mark.parametrize("opts", [dict(), dict(t_block=4096), dict(t_block=4096, t_dense=100000),
+                                  dict(t_block=4096, hash_cap=512)])
 def test_heavy_columns_streamed(opts):
-    """Columns above the workgroup accumulator's register capacity (more than
-    12288 products) stream their rows again for every pass; with many repeated
-    rows (20000 products over 20000 rows) most products are later products."""
+    """Heavy columns (up to 24000 products): the row-windowed sort by default;
+    with t_block the hash accumulator, whose columns above its register
+    capacity stream their rows again for every pass. With many repeated rows
+    (20000 products over 20000 rows) most products are later products."""
     from paper_2303_02471_amd import api
     _say(f"heavy streamed columns {opts}")
     rng = np.random.default_rng(11)
@@ -243,3 +246,21 @@ def test_clustered_rows_split():
         st = plan.stats()
         plan.close()
         assert st["cols_split"] > 0
+
+
+def test_repeated_row_heavy_column():
+    """One row reached by more than 4096 products of a column: the windowed
+    sort splits its row window down to that single row, which is one entry
+    whose products take their occurrence indices in product order."""
+    _say("one row in 4500 products of a column")
+    rng = np.random.default_rng(13)
+    m = 50_000
+    acols = []
+    for _ in range(5000):
+        rows = np.concatenate([[5], rng.choice(np.arange(10, m), size=2, replace=False)])
+        rng.shuffle(rows)
+        acols.append(rows)
+    A = _csc_from_columns(m, acols, rng)
+    B = _csc_from_columns(5000, [rng.choice(5000, size=d, replace=False)
+                                 for d in (4500, 3000, 7, 1600)], rng)
+    check_f64(A, B, what="repeated row")
