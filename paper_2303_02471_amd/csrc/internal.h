@@ -40,7 +40,7 @@ constexpr int kEscBins = 7;
 constexpr int kSortBins = 4;
 constexpr int kBlkBins = 5;
 constexpr int kSortMax = 4096;        // products per workgroup sort
-constexpr int kProdTile = 1024;       // products per product-balanced tile
+constexpr int kProdTile = 2048;       // products per product-balanced tile
 constexpr int kEscMaxProducts = 256;  // products per wavefront group
 constexpr int kChunkB = 256;          // stored B entries per chunk of a split column
 

@@ -9,11 +9,12 @@
 // the rows of the A column each entry selects, in storage order -- to the
 // product space. The symbolic accumulators stream these rows.
 //
-// Numeric: the symbolic phase left, per product, a destination: the rank of
-// its output row inside its column, or for a product that is not the first of
-// its output entry a place in the list of such "later" products with its
-// occurrence index k. The numeric kernels form every product A(i,k) * B(k,j)
-// from coalesced reads of the selected A columns (rows and values) and write
+// Numeric: the symbolic phase left, per product, its row (the expansion) and
+// a destination: the rank of its output row inside its column, or for a
+// product that is not the first of its output entry a place in the list of
+// such "later" products with its occurrence index k. The numeric kernels form
+// every product A(i,k) * B(k,j) from the values of the selected A columns,
+// read both arrays in product order and write
 // the first product of each entry as 0 + product straight to its output
 // position; later products are staged, and layer kernels add those of
 // occurrence index 1, 2, ... in that order, so every output entry is summed in
@@ -125,7 +126,6 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
                                                Pos &&pos, Cinfo &&cinfo, First &&first,
                                                int &bad) {
     const V *__restrict__ av = (const V *)d.av;
-    const int *__restrict__ ari = d.ari;
     V *__restrict__ lv = (V *)a.lv;
     const int tid = threadIdx.x;
     for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
@@ -143,7 +143,7 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
                 c[u] = s_col[tt];
                 pp[u] = pos(tt, e);
                 v[u] = av[q] * s_bv[tt];
-                row[u] = ari[q];
+                row[u] = a.prow[pp[u]];  // the expansion's row, read in product order
                 dc[u] = a.dst[pp[u]];
             }
         }
@@ -171,14 +171,12 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
 
 constexpr int kColWin = 256;  // columns per window of a tile
 constexpr int kNumPer = 8;    // products per thread per pass
-constexpr int kStage = 2048;  // output entries a tile's column window stages in LDS
 
 template <typename V>
 struct NumSmem {
     int s_bcp[kColWin + 1];     // B column pointers of the column window
     int s_c0[kColWin + 1];      // C column pointers of the column window
     int s_ceff[kColWin + 1];    // first product of each column among the window's tile columns
-    int s_oeff[kColWin + 1];    // first output entry of each column among the tile columns
     long long s_pcol[kColWin];  // first product of each column in the product space
     int s_ok[kColWin];          // column done by the tile (at most t_split products)
     long long s_lb[kColWin];    // start of each column's later products in the compact list
@@ -187,8 +185,6 @@ struct NumSmem {
     int s_col[kBlock];          // window column of each stored B entry of the B window
     V s_bv[kBlock];             // B value of each stored B entry of the B window
     int scan_tmp[kBlock / 64 + 1];
-    V sval[kStage];             // output values of the window's tile columns
-    int srow[kStage];           // output rows of the window's tile columns
 };
 
 // One workgroup per product-balanced tile; columns with more than t_split
@@ -208,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
         for (int jw = js; jw < je; jw += kColWin) {
             const int nc = min(kColWin, je - jw);
             const int gw = d.col0 + jw;
-            int eff = 0, oeff = 0;
+            int eff = 0;
             for (int c = tid; c <= nc; c += kBlock) {
                 S.s_bcp[c] = d.bcp[jw + c];
                 S.s_c0[c] = d.ccp[jw + c];
@@ -222,23 +218,12 @@ __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
                 S.s_pcol[tid] = pc;
                 S.s_lb[tid] = pc - (a.nprob == 1 ? (long long)c0 : a.gcp[gw + tid]);
                 eff = ok ? op : 0;
-                oeff = ok ? d.ccp[jw + tid + 1] - c0 : 0;
             }
-            int tot, otot;
+            int tot;
             const int ex = block_excl_scan(eff, S.scan_tmp, tot);
-            const int ox = block_excl_scan(oeff, S.scan_tmp, otot);
-            if (tid < nc) {
-                S.s_ceff[tid] = ex;
-                S.s_oeff[tid] = ox;
-            }
-            if (tid == 0) {
-                S.s_ceff[nc] = tot;
-                S.s_oeff[nc] = otot;
-            }
+            if (tid < nc) S.s_ceff[tid] = ex;
+            if (tid == 0) S.s_ceff[nc] = tot;
             __syncthreads();
-            // the window's output entries are staged in LDS and written in
-            // order when they fit, else written straight through
-            const bool stage = otot <= kStage;
             int *__restrict__ cri = d.cri;
             V *__restrict__ cv = (V *)d.cv;
             const int pb = S.s_bcp[0], pe = S.s_bcp[nc];
@@ -282,26 +267,11 @@ __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
                         lb = S.s_lb[c];
                     },
                     [&](int c, int o, int row, V v) {
-                        if (stage) {
-                            S.sval[S.s_oeff[c] + o] = v;
-                            S.srow[S.s_oeff[c] + o] = row;
-                        } else {
-                            cri[S.s_c0[c] + o] = row;
-                            cv[S.s_c0[c] + o] = v;
-                        }
+                        cri[S.s_c0[c] + o] = row;
+                        cv[S.s_c0[c] + o] = v;
                     },
                     bad);
                 base += Ew;
-                __syncthreads();
-            }
-            if (stage) {
-                // staged entries to their output positions, in order
-                for (int i = tid; i < otot; i += kBlock) {
-                    const int c = last_le(S.s_oeff, nc + 1, i);
-                    const int o = S.s_c0[c] + (i - S.s_oeff[c]);
-                    cri[o] = S.srow[i];
-                    cv[o] = S.sval[i];
-                }
                 __syncthreads();
             }
         }
@@ -326,6 +296,7 @@ struct BigSmem {
 // c mod 8, so the column's output lines, written piecewise by its chunks,
 // meet in one L2 before they are written back.
 constexpr int kXcds = 8;
+static_assert(kChunkB % kBlock == 0, "a chunk is a whole number of B windows");
 
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int n) {
@@ -348,13 +319,6 @@ __global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int 
     const int j = g - d.col0;
     const int2 *__restrict__ Ep = a.E + d.ebase;
     // this chunk's first product: the products of the column's earlier entries
-    const int t = b0 + tid;
-    int2 ez = make_int2(0, 0);
-    V b = V(0);
-    if (t < b1) {
-        ez = Ep[t];
-        b = ((const V *)d.bv)[t];
-    }
     long long pre = 0;
     for (int x = bs + tid; x < b0; x += kBlock) pre += Ep[x].y;
     if (tid == 0) S.s_pre = 0;
@@ -362,28 +326,49 @@ __global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int 
     if (pre) atomicAdd((unsigned long long *)&S.s_pre, (unsigned long long)pre);
     const int c0 = d.ccp[j], clen = d.ccp[j + 1] - c0;
     const long long lb0 = a.colprod[g] - (a.nprob == 1 ? (long long)c0 : a.gcp[g]);
-    int Ew;
-    const int ex = block_excl_scan(t < b1 ? ez.y : 0, S.scan_tmp, Ew);
-    S.s_acp[tid] = ez.x;
-    S.s_eoff[tid] = ex;
-    S.s_col[tid] = 0;
-    S.s_bv[tid] = b;
+    const V *__restrict__ bv = (const V *)d.bv;
     __syncthreads();
-    const long long pbase = a.colprod[g] + S.s_pre;
+    long long pbase = a.colprod[g] + S.s_pre;
     int bad = 0;
-    numeric_window<V, kNumPer>(
-        a, pid, d, S.s_acp, S.s_eoff, S.s_col, S.s_bv, b1 - b0, Ew,
-        [&](int, int e) { return pbase + e; },
-        [&](int, int &o0, int &ol, long long &lb) {
-            o0 = c0;
-            ol = clen;
-            lb = lb0;
-        },
-        [&](int, int o, int row, V v) {
-            d.cri[c0 + o] = row;
-            ((V *)d.cv)[c0 + o] = v;
-        },
-        bad);
+    // the chunk's entries in windows of kBlock, the next window's loads in flight
+    int2 nez = make_int2(0, 0);
+    V nbv = V(0);
+    if (b0 + tid < b1) {
+        nez = Ep[b0 + tid];
+        nbv = bv[b0 + tid];
+    }
+    for (int bw = b0; bw < b1; bw += kBlock) {
+        const int t = bw + tid;
+        const int2 ez = nez;
+        const V b = nbv;
+        if (t + kBlock < b1) {
+            nez = Ep[t + kBlock];
+            nbv = bv[t + kBlock];
+        }
+        int Ew;
+        const int ex = block_excl_scan(t < b1 ? ez.y : 0, S.scan_tmp, Ew);
+        S.s_acp[tid] = ez.x;
+        S.s_eoff[tid] = ex;
+        S.s_col[tid] = 0;
+        S.s_bv[tid] = b;
+        __syncthreads();
+        const long long pb = pbase;
+        numeric_window<V, kNumPer>(
+            a, pid, d, S.s_acp, S.s_eoff, S.s_col, S.s_bv, min(kBlock, b1 - bw), Ew,
+            [&](int, int e) { return pb + e; },
+            [&](int, int &o0, int &ol, long long &lb) {
+                o0 = c0;
+                ol = clen;
+                lb = lb0;
+            },
+            [&](int, int o, int row, V v) {
+                d.cri[c0 + o] = row;
+                ((V *)d.cv)[c0 + o] = v;
+            },
+            bad);
+        pbase += Ew;
+        __syncthreads();
+    }
     if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
 }
 
