@@ -211,6 +211,9 @@ typedef struct {
 /* on != 0 starts recording (and clears earlier records); on == 0 stops. */
 spgemm_status spgemm_profile_enable(int32_t on);
 
+/* Restricts recording to the launch group `name` (NULL or "" = every group),
+ * so that a timed loop carries the events of one kernel only. Host only. */
+spgemm_status spgemm_profile_select(const char *name);
 /* Copies up to `max` records into out_host and their number into n_host
  * (host pointers). Waits for the recorded events. */
 spgemm_status spgemm_profile_read(spgemm_kernel_time *out_host, int32_t max, int32_t *n_host);

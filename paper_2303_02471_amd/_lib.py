@@ -25,7 +25,7 @@ STATUS = {
 EXPORTS = (
     "spgemm_symbolic", "spgemm_numeric", "spgemm_backward", "spgemm_batched",
     "spgemm_plan_get_stats", "spgemm_plan_destroy", "spgemm_status_string", "spgemm_version",
-    "spgemm_profile_enable", "spgemm_profile_read",
+    "spgemm_profile_enable", "spgemm_profile_read", "spgemm_profile_select",
     "spgemm_autotune", "spgemm_tune_key", "spgemm_tune_cache_load", "spgemm_tune_cache_store",
 )
 
@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
                            "`python -m paper_2303_02471_amd.build` (hipcc, gfx950)")
     L = C.CDLL(LIB_PATH)
     vp, i32, i64p = C.c_void_p, C.c_int32, C.POINTER(C.c_int64)
+    L.spgemm_profile_select.argtypes = [C.c_char_p]
     L.spgemm_symbolic.argtypes = [C.POINTER(Csc), C.POINTER(Csc), C.c_int, C.POINTER(Options), vp,
                                   C.POINTER(vp), vp, i64p]
     L.spgemm_numeric.argtypes = [vp, vp, vp, vp, vp, vp]

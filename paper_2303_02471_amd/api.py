@@ -27,6 +27,12 @@ def profile_enable(on: bool = True) -> None:
     _lib.check(_lib.lib().spgemm_profile_enable(1 if on else 0), "profile_enable")
 
 
+def profile_select(name: Optional[str] = None) -> None:
+    """Record only the launch group `name` (None: every group)."""
+    _lib.check(_lib.lib().spgemm_profile_select(name.encode() if name else None),
+               "profile_select")
+
+
 def profile_read() -> dict:
     """{kernel name: (launches, total ms)} recorded since profile_enable(True)."""
     buf = (_lib.KernelTime * 64)()

@@ -170,7 +170,8 @@ __device__ __forceinline__ Prob get_prob(const KArgs &a, int pid) {
 // Each returns hipSuccess or the launch error.
 hipError_t launch_classify(const KArgs &a, hipStream_t s);
 hipError_t launch_place(const KArgs &a, hipStream_t s);
-hipError_t launch_esc(const KArgs &a, int grid, hipStream_t s);
+// wavefront groups of ESC sub-bin `sub`; wide: 64-bit keys (rows of 2^24 - 1 and more)
+hipError_t launch_esc(const KArgs &a, bool wide, int sub, int groups, hipStream_t s);
 // workgroup sort of sort bin `cls` (n columns); wide: 64-bit keys (rows beyond 20 bits)
 hipError_t launch_sort(const KArgs &a, int cls, bool wide, int n, hipStream_t s);
 // windowed workgroup sort of the `n` columns listed from bin-list position `first`

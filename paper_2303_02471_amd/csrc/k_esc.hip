@@ -1,31 +1,39 @@
 // Wavefront sort-merge accumulator for the lightest columns: expand, sort,
 // compress (ESC, Section 4), one 64-lane wavefront per group of columns.
 //
-// A group holds up to 64 columns whose products and stored B entries each add
-// up to at most 256. The wavefront
-//   1. reads the rows of the group's products from the product space (each
-//      column's products in the order the sequential SPA of Algorithm 1 meets
-//      them); e is the position in the group;
-//   2. sorts the keys (column, row, e) with a register bitonic network whose
-//      lane exchanges use DPP, ds_swizzle and ds_bpermute;
-//   3. compresses: every (column, row) run is one output entry; its rank
-//      inside the column is its output position (rows come out ascending),
-//      and the position of a key inside its run is the occurrence index k of
-//      that product among the products Algorithm 1 adds into the entry.
-// It counts the runs per column and records the destination of every
-// product: the rank of its row, marked for all but the first product of a run,
-// whose occurrence index k and index among the column's later products are
-// stored at the product's position.
+// Sub-bin i holds the columns of at most S = 4 << i products; a group is
+// 64 >> i of them and every column owns an aligned segment of S of the
+// wavefront's 256 key positions (position s = 64 r + lane for register r).
+// The wavefront
+//   1. reads the rows of each column's products from the product space (the
+//      order the sequential SPA of Algorithm 1 meets them) into its segment as
+//      keys (row, e), e the product's position in the column; the rest of the
+//      segment is padding that sorts last;
+//   2. sorts every segment with the first log2(S) stages of a bitonic network
+//      (the last stage ascending everywhere), lane exchanges through DPP,
+//      ds_swizzle and ds_bpermute, register exchanges for distances of 64 and
+//      more -- a column of at most 4 products takes 3 stages, not the 36 of a
+//      full 256-key sort;
+//   3. compresses: every run of equal rows is one output entry; its index
+//      among the column's runs is its rank (rows come out ascending), and the
+//      position of a key inside its run is the occurrence index k of that
+//      product among the products Algorithm 1 adds into the entry.
+// It writes every column's count and every product's destination: the rank,
+// marked for all but the first product of a run, whose k and index among the
+// column's later products are stored at the product's position.
+//
+// Keys are 32-bit when every row index is below 2^24 - 1, else 64-bit.
 #include "devutil.h"
 
 namespace spg {
 
+template <typename K>
 struct EscSmem {
-    int goff[65];    // first product of each column inside the group
-    long long cbase[64];  // first product of each column in the product space
-    int cnt[65];     // first run index of each column
-    unsigned long long sk[kEscMaxProducts];  // sorted keys
-    int rh[kEscMaxProducts];                 // sorted position of every run head
+    long long cbase[64];  // first product of each column of the group
+    int op[64];           // products of each column
+    int nnz[64];          // entries of each column
+    K sk[kEscMaxProducts];     // sorted keys
+    int rh[kEscMaxProducts];   // position of each run head, by segment start + run
 };
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -34,33 +42,42 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// compare-exchange across lanes at distance J (< 64) for every register row
-template <int R, int J>
-__device__ __forceinline__ void bitonic_lane_step(unsigned long long (&key)[4], int k, int lane) {
+template <int J>
+__device__ __forceinline__ unsigned xchg(unsigned v) {
+    return (unsigned)shfl_xor_c<J>((int)v);
+}
+template <int J>
+__device__ __forceinline__ unsigned long long xchg(unsigned long long v) {
+    return shfl_xor_c64<J>(v);
+}
+
+// compare-exchange across lanes at distance J (< 64), every register row;
+// position s keeps the smaller key when (ascending) == (s is the lower one)
+template <typename K, int J, int S>
+__device__ __forceinline__ void esc_lane_step(K (&key)[4], int k, int lane) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < 4; ++r) {
         const int s = r * 64 + lane;
-        unsigned long long o = shfl_xor_c64<J>(key[r]);
-        const bool asc = (s & k) == 0;
-        const bool lower = (lane & J) == 0;
-        const unsigned long long mn = key[r] < o ? key[r] : o;
-        const unsigned long long mx = key[r] < o ? o : key[r];
-        key[r] = (asc == lower) ? mn : mx;
+        const K o = xchg<J>(key[r]);
+        const bool asc = k == S || (s & k) == 0;
+        const bool take_min = asc == ((lane & J) == 0);
+        const K mn = key[r] < o ? key[r] : o;
+        const K mx = key[r] < o ? o : key[r];
+        key[r] = take_min ? mn : mx;
     }
 }
 
-// compare-exchange between register rows at distance J >= 64
-template <int R>
-__device__ __forceinline__ void bitonic_reg_step(unsigned long long (&key)[4], int k, int j,
-                                                 int lane) {
+// compare-exchange between register rows at distance j >= 64
+template <typename K, int S>
+__device__ __forceinline__ void esc_reg_step(K (&key)[4], int k, int j, int lane) {
     const int jr = j >> 6;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < 4; ++r) {
         const int rp = r ^ jr;
-        if (rp > r && rp < R) {
+        if (rp > r) {
             const int s = r * 64 + lane;
-            const bool asc = (s & k) == 0;
-            unsigned long long x = key[r], y = key[rp];
+            const bool asc = k == S || (s & k) == 0;
+            const K x = key[r], y = key[rp];
             const bool sw = asc ? (x > y) : (x < y);
             key[r] = sw ? y : x;
             key[rp] = sw ? x : y;
@@ -68,175 +85,165 @@ __device__ __forceinline__ void bitonic_reg_step(unsigned long long (&key)[4], i
     }
 }
 
-// Ascending sort of 64*R keys held as key[r] at position r*64 + lane.
-template <int R>
-__device__ __forceinline__ void wave_bitonic_sort(unsigned long long (&key)[4]) {
-    const int lane = lane_id();
+// every aligned segment of S = 1 << LS positions sorted ascending
+template <typename K, int LS>
+__device__ __forceinline__ void seg_sort(K (&key)[4], int lane) {
+    constexpr int S = 1 << LS;
 #pragma unroll
-    for (int k = 2; k <= 64 * R; k <<= 1) {
+    for (int k = 2; k <= S; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
             if (j >= 64) {
-                bitonic_reg_step<R>(key, k, j, lane);
+                esc_reg_step<K, S>(key, k, j, lane);
             } else {
                 switch (j) {
-                    case 32: bitonic_lane_step<R, 32>(key, k, lane); break;
-                    case 16: bitonic_lane_step<R, 16>(key, k, lane); break;
-                    case 8: bitonic_lane_step<R, 8>(key, k, lane); break;
-                    case 4: bitonic_lane_step<R, 4>(key, k, lane); break;
-                    case 2: bitonic_lane_step<R, 2>(key, k, lane); break;
-                    default: bitonic_lane_step<R, 1>(key, k, lane); break;
+                    case 32: esc_lane_step<K, 32, S>(key, k, lane); break;
+                    case 16: esc_lane_step<K, 16, S>(key, k, lane); break;
+                    case 8: esc_lane_step<K, 8, S>(key, k, lane); break;
+                    case 4: esc_lane_step<K, 4, S>(key, k, lane); break;
+                    case 2: esc_lane_step<K, 2, S>(key, k, lane); break;
+                    default: esc_lane_step<K, 1, S>(key, k, lane); break;
                 }
             }
         }
     }
 }
 
-constexpr unsigned long long kNoKey = ~0ull;
-
-__global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
-    __shared__ EscSmem smem[kBlock / 64];
-    if (a.hdr->err) return;
-    const int lane = lane_id();
-    EscSmem &S = smem[threadIdx.x >> 6];
-
-    // group numbering over the sort-merge sub-bins
-    int bstart[kEscBins], bcnt[kEscBins], gstart[kEscBins + 1];
-    {
-        int run = 0;
-        for (int b = 0; b < BIN_ESC0; ++b) run += a.hdr->bin_count[b];
-        int gr = 0;
-#pragma unroll
-        for (int i = 0; i < kEscBins; ++i) {
-            bstart[i] = run;
-            bcnt[i] = a.hdr->bin_count[BIN_ESC0 + i];
-            run += bcnt[i];
-            gstart[i] = gr;
-            gr += ceil_div(bcnt[i], 64 >> i);
-        }
-        gstart[kEscBins] = gr;
+template <typename K, int LS>
+__device__ __forceinline__ void esc_group(const KArgs &a, EscSmem<K> &S, int first, int ncols,
+                                          int lane, int &kmax) {
+    constexpr int SEG = 1 << LS;
+    constexpr K KMAX = (K)~(K)0;
+    // ---- the group's columns, one per lane
+    int g = 0;
+    if (lane < ncols) {
+        g = a.binlist[first + lane].x;
+        const int op = a.op[g];
+        S.op[lane] = op > SEG ? -1 : op;  // more than planned: cannot happen for unchanged inputs
+        S.cbase[lane] = a.colprod[g];
     }
-    const int ngroups = gstart[kEscBins];
-    const int wstride = gridDim.x * (kBlock / 64);
-    for (int gi = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); gi < ngroups; gi += wstride) {
-        int sb = 0;
+    wave_sync_lds();
+    // ---- keys (row, e) in each column's segment
+    K key[4];
+    bool bad = false;
 #pragma unroll
-        for (int i = 1; i < kEscBins; ++i) sb += gi >= gstart[i];
-        int G = 64, first = 0, cntb = 0, gs = 0;
-#pragma unroll
-        for (int i = 0; i < kEscBins; ++i)
-            if (i == sb) { G = 64 >> i; first = bstart[i]; cntb = bcnt[i]; gs = gstart[i]; }
-        const int lg = gi - gs;
-        const int ncols = min(G, cntb - lg * G);
-        first += lg * G;
-
-        // ---- the group's columns, one per lane
-        int g = 0, op = 0;
-        if (lane < ncols) {
-            g = a.binlist[first + lane].x;
-            op = a.op[g];
-            S.cbase[lane] = a.colprod[g];
-        }
-        const int incl = wave_incl_scan(op);
-        const int E = wave_bcast(incl, 63);
-        S.goff[lane] = incl - op;
-        S.cnt[lane] = 0;
-        if (E > kEscMaxProducts) {  // cannot happen for unchanged inputs
-            if (lane == 0) atomicOr(&a.hdr->err, ERR_GROUP);
-            continue;
-        }
-        wave_sync_lds();
-
-        // ---- keys (column, row, e) of the group's products
-        unsigned long long key[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int e = lane + 64 * r;
-            key[r] = kNoKey;
-            if (e < E) {
-                const int cc = last_le(S.goff, ncols, e);
-                const int row = a.prow[S.cbase[cc] + (e - S.goff[cc])];
-                key[r] = ((unsigned long long)cc << 40) | ((unsigned long long)row << 8) |
-                         (unsigned long long)e;
-            }
-        }
-        const int R = E <= 64 ? 1 : (E <= 128 ? 2 : 4);
-        if (R == 1) wave_bitonic_sort<1>(key);
-        else if (R == 2) wave_bitonic_sort<2>(key);
-        else wave_bitonic_sort<4>(key);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (r < R) S.sk[r * 64 + lane] = key[r];
-        wave_sync_lds();
-
-        // ---- compress: run heads, run index of every sorted key
-        bool head[4];
-        int run[4];
-        int before = 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int s = r * 64 + lane;
-            head[r] = false;
-            if (r < R && key[r] != kNoKey) {
-                const unsigned long long prev = s > 0 ? S.sk[s - 1] : kNoKey;
-                head[r] = (prev >> 8) != (key[r] >> 8);
-            }
-            const unsigned long long m = ballot(head[r]);
-            run[r] = before + popc64(m & mask_lt()) + (head[r] ? 0 : -1);
-            before += popc64(m);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (!head[r]) continue;
-            const int s = r * 64 + lane;
-            const int cc = (int)(key[r] >> 40);
-            S.rh[run[r]] = s;
-            const unsigned long long prev = s > 0 ? S.sk[s - 1] : kNoKey;
-            if ((prev >> 40) != (unsigned long long)cc) S.cnt[cc] = run[r];
-        }
-        if (lane == 0) S.cnt[ncols] = before;
-        wave_sync_lds();
-        if (lane < ncols) a.gnnz[g] = S.cnt[lane + 1] - S.cnt[lane];
-        // the largest occurrence index of the group (a device atomic only when
-        // it raises the value already there)
-        const int nlater = E - before;
-        if (nlater > 0) {
-            int kmax = 0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (r < R && key[r] != kNoKey) kmax = max(kmax, r * 64 + lane - S.rh[run[r]]);
-#pragma unroll
-            for (int dd = 32; dd >= 1; dd >>= 1)
-                kmax = max(kmax, __builtin_amdgcn_ds_bpermute((lane ^ dd) << 2, kmax));
-            if (lane == 0 && kmax > __atomic_load_n(&a.hdr->later_maxk, __ATOMIC_RELAXED))
-                atomicMax(&a.hdr->later_maxk, kmax);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (r >= R || key[r] == kNoKey) continue;
-            const int s = r * 64 + lane;
-            const int cc = (int)(key[r] >> 40);
-            const int e = (int)(key[r] & 255u);
-            const int rank = run[r] - S.cnt[cc];
-            const int k = s - S.rh[run[r]];
-            const long long pe = S.cbase[cc] + (e - S.goff[cc]);
-            if (k == 0) {
-                a.dst[pe] = (uint32_t)rank;
-            } else {
-                // index among the column's later products: later keys before
-                // this one in sorted order, minus those of the earlier columns
-                // of the group (their products minus their entries)
-                a.dst[pe] = kDstLater | (uint32_t)rank;
-                a.lk[pe] = k;
-                a.lr[pe] = (s - run[r] - 1) - (S.goff[cc] - S.cnt[cc]);
-            }
+    for (int r = 0; r < 4; ++r) {
+        const int s = r * 64 + lane, cc = s >> LS, i = s & (SEG - 1);
+        key[r] = KMAX;
+        if (cc < ncols) {
+            const int op = S.op[cc];
+            bad |= op < 0;
+            if (i < op) key[r] = ((K)(unsigned)a.prow[S.cbase[cc] + i] << 8) | (K)i;
         }
     }
+    if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
+    seg_sort<K, LS>(key, lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S.sk[r * 64 + lane] = key[r];
+    wave_sync_lds();
+    // ---- runs: heads, run index inside the column
+    bool head[4];
+    unsigned long long hm[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int s = r * 64 + lane;
+        head[r] = key[r] != KMAX && ((s & (SEG - 1)) == 0 || (S.sk[s - 1] >> 8) != (key[r] >> 8));
+        hm[r] = ballot(head[r]);
+    }
+    const unsigned long long le = mask_lt() | (1ull << lane);
+    int run[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int c;
+        if (SEG <= 64) {
+            // the segment lies inside register row r
+            const int ls = lane & ~(SEG - 1);
+            const unsigned long long seg = SEG == 64 ? ~0ull : (((1ull << SEG) - 1ull) << ls);
+            c = popc64(hm[r] & le & seg);
+        } else {
+            // the segment starts at lane 0 of row r0 and spans SEG / 64 rows
+            constexpr int RS = SEG / 64;
+            const int r0 = r & ~(RS - 1);
+            c = popc64(hm[r] & le);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q >= r0 && q < r) c += popc64(hm[q]);
+        }
+        run[r] = c - 1;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int s = r * 64 + lane, ss = s & ~(SEG - 1);
+        if (head[r]) S.rh[ss + run[r]] = s;
+        // the last key of a column holds its entry count
+        const int cc = s >> LS;
+        if (key[r] != KMAX && (s - ss) == S.op[cc] - 1) S.nnz[cc] = run[r] + 1;
+    }
+    wave_sync_lds();
+    if (lane < ncols) a.gnnz[g] = S.op[lane] > 0 ? S.nnz[lane] : 0;
+    // ---- destinations
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (key[r] == KMAX) continue;
+        const int s = r * 64 + lane, ss = s & ~(SEG - 1), cc = s >> LS;
+        const int e = (int)(key[r] & (K)255);
+        const int k = s - S.rh[ss + run[r]];
+        const long long pe = S.cbase[cc] + e;
+        if (k == 0) {
+            a.dst[pe] = (uint32_t)run[r];
+        } else {
+            // later keys before this one inside the column
+            a.dst[pe] = kDstLater | (uint32_t)run[r];
+            a.lk[pe] = k;
+            a.lr[pe] = (s - ss) - run[r] - 1;
+            kmax = max(kmax, k);
+        }
+    }
+    wave_sync_lds();  // the LDS of this group is read before the next group writes it
 }
 
-hipError_t launch_esc(const KArgs &a, int grid, hipStream_t s) {
-    if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_esc, dim3(grid), dim3(kBlock), 0, s, a);
+// one launch per sub-bin: sub-bin LS - 2 holds columns of at most 1 << LS
+// products, 64 >> (LS - 2) of them per wavefront group
+template <typename K, int LS>
+__global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
+    __shared__ EscSmem<K> smem[kBlock / 64];
+    if (a.hdr->err) return;
+    const int lane = lane_id();
+    EscSmem<K> &S = smem[threadIdx.x >> 6];
+    constexpr int sb = LS - 2, G = 64 >> sb;
+    int start = 0;
+    for (int b = 0; b < BIN_ESC0 + sb; ++b) start += a.hdr->bin_count[b];
+    const int cnt = a.hdr->bin_count[BIN_ESC0 + sb];
+    const int ngroups = ceil_div(cnt, G);
+    const int wstride = gridDim.x * (kBlock / 64);
+    int kmax = 0;
+    for (int gi = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); gi < ngroups; gi += wstride)
+        esc_group<K, LS>(a, S, start + gi * G, min(G, cnt - gi * G), lane, kmax);
+    // the largest occurrence index (a device atomic only when it raises the
+    // value already there)
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+        kmax = max(kmax, __builtin_amdgcn_ds_bpermute((lane ^ d) << 2, kmax));
+    if (lane == 0 && kmax > __atomic_load_n(&a.hdr->later_maxk, __ATOMIC_RELAXED))
+        atomicMax(&a.hdr->later_maxk, kmax);
+}
+
+hipError_t launch_esc(const KArgs &a, bool wide, int sub, int groups, hipStream_t s) {
+    if (groups <= 0) return hipSuccess;
+    const dim3 grid(ceil_div(groups, kBlock / 64));
+#define SPG_ESC(K)                                                                       \
+    switch (sub) {                                                                       \
+        case 0: hipLaunchKernelGGL((k_esc<K, 2>), grid, dim3(kBlock), 0, s, a); break;   \
+        case 1: hipLaunchKernelGGL((k_esc<K, 3>), grid, dim3(kBlock), 0, s, a); break;   \
+        case 2: hipLaunchKernelGGL((k_esc<K, 4>), grid, dim3(kBlock), 0, s, a); break;   \
+        case 3: hipLaunchKernelGGL((k_esc<K, 5>), grid, dim3(kBlock), 0, s, a); break;   \
+        case 4: hipLaunchKernelGGL((k_esc<K, 6>), grid, dim3(kBlock), 0, s, a); break;   \
+        case 5: hipLaunchKernelGGL((k_esc<K, 7>), grid, dim3(kBlock), 0, s, a); break;   \
+        default: hipLaunchKernelGGL((k_esc<K, 8>), grid, dim3(kBlock), 0, s, a); break;  \
+    }
+    if (wide) SPG_ESC(unsigned long long)
+    else SPG_ESC(unsigned)
+#undef SPG_ESC
     return hipGetLastError();
 }
 

@@ -86,6 +86,7 @@ struct spgemm_plan_s {
     int *bt_err = nullptr;
 
     bool wide_keys = false;  // some problem has 2^20 rows or more: 64-bit sort keys
+    bool wide_esc = false;   // some problem has 2^24 - 1 rows or more: 64-bit ESC keys
 
     hipStream_t last_stream = nullptr;
 };
@@ -101,6 +102,7 @@ struct ProfRec {
 };
 struct Profiler {
     bool on = false;
+    char only[32] = {0};  // record only this launch group when set
     std::vector<ProfRec> recs;
     size_t used = 0;
 } g_prof;
@@ -110,6 +112,7 @@ struct ProfScope {
     hipStream_t s;
     ProfScope(const char *name, hipStream_t st) : s(st) {
         if (!g_prof.on) return;
+        if (g_prof.only[0] && std::strncmp(g_prof.only, name, sizeof(g_prof.only)) != 0) return;
         if (g_prof.used == g_prof.recs.size()) {
             ProfRec nr{name, nullptr, nullptr};
             if (hipEventCreate(&nr.a) != hipSuccess || hipEventCreate(&nr.b) != hipSuccess) return;
@@ -385,7 +388,9 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
     }
     {
         ProfScope ps("esc_symbolic", s);
-        if ((e = launch_esc(a, ceil_div(esc_groups(h), kBlock / 64), s))) return e;
+        for (int i = kEscBins - 1; i >= 0; --i)
+            if ((e = launch_esc(a, p->wide_esc, i, ceil_div(h.bin_count[BIN_ESC0 + i], 64 >> i), s)))
+                return e;
     }
     for (int c = 0; c < 2; ++c) {
         const int n = h.bin_count[BIN_SORT0 + c];
@@ -620,7 +625,11 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
     p->probs = std::move(probs);
     // 32-bit sort keys hold rows below 2^20
     p->wide_keys = false;
-    for (const Prob &q : p->probs) p->wide_keys |= q.m > (1 << 20);
+    p->wide_esc = false;
+    for (const Prob &q : p->probs) {
+        p->wide_keys |= q.m > (1 << 20);
+        p->wide_esc |= q.m >= (1 << 24) - 1;
+    }
     p->ncols = (int)ncols;
     p->total_nnzb = nnzb_total;
     p->ntiles = (int)tiles.size();
@@ -812,6 +821,12 @@ spgemm_status spgemm_plan_get_stats(spgemm_plan p, spgemm_plan_stats *out) {
 spgemm_status spgemm_profile_enable(int32_t on) {
     g_prof.on = on != 0;
     if (g_prof.on) g_prof.used = 0;
+    return SPGEMM_OK;
+}
+
+spgemm_status spgemm_profile_select(const char *name) {
+    std::memset(g_prof.only, 0, sizeof(g_prof.only));
+    if (name) std::strncpy(g_prof.only, name, sizeof(g_prof.only) - 1);
     return SPGEMM_OK;
 }
 
