@@ -76,7 +76,6 @@ struct Prob {
 // Device header written by the planning kernels.
 struct Hdr {
     int32_t bin_count[NBINS];
-    int32_t bin_cursor[NBINS];
     int32_t err;
     int32_t later_maxk;                // largest occurrence index k of any product
     int32_t big_chunks;                // most kChunkB-entry chunks of a column above t_split
@@ -108,6 +107,12 @@ struct KArgs {
     int32_t ncols;          // total columns over all problems
     int32_t ntiles;
     const int4 *tiles;      // (pid, j0, j1, 0) when nprob > 1
+    // per classification tile: the tile's column count of every bin (then the
+    // tile's first position inside the bin), its products and the most
+    // chunks of one of its columns above t_split
+    int32_t *th;            // [ntiles * NBINS]
+    long long *ttot;        // [ntiles]
+    int32_t *tmax;          // [ntiles]
     Tune tune;
     Hdr *hdr;
     int32_t *op;            // [ncols]
@@ -169,6 +174,9 @@ __device__ __forceinline__ Prob get_prob(const KArgs &a, int pid) {
 // ---------------------------------------------------------------- launchers
 // Each returns hipSuccess or the launch error.
 hipError_t launch_classify(const KArgs &a, hipStream_t s);
+// bin counts, product total and largest chunk count from the tile tallies;
+// per-tile positions inside every bin
+hipError_t launch_tally(const KArgs &a, hipStream_t s);
 hipError_t launch_place(const KArgs &a, hipStream_t s);
 // wavefront groups of ESC sub-bin `sub`; wide: 64-bit keys (rows of 2^24 - 1 and more)
 hipError_t launch_esc(const KArgs &a, bool wide, int sub, int groups, hipStream_t s);

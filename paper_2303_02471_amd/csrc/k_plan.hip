@@ -127,17 +127,67 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     atomicAdd(&s_tot, tot);
     if (maxch) atomicMax(&s_maxch, maxch);
     __syncthreads();
-    if (tid < NBINS && s_hist[tid]) atomicAdd(&a.hdr->bin_count[tid], s_hist[tid]);
+    // the tile's tallies (no device atomics: k_tally combines the tiles)
+    if (tid < NBINS) a.th[blockIdx.x * NBINS + tid] = s_hist[tid];
     if (tid == 0) {
-        atomicAdd(&a.hdr->total_op, s_tot);
-        if (s_maxch) atomicMax(&a.hdr->big_chunks, s_maxch);
+        a.ttot[blockIdx.x] = (long long)s_tot;
+        a.tmax[blockIdx.x] = s_maxch;
         if (s_err) atomicOr(&a.hdr->err, s_err);
     }
 }
 
+// ---------------------------------------------------------------- tally
+// Workgroup b < NBINS: exclusive scan of bin b's per-tile counts (in place:
+// each tile's first position inside the bin) and the bin's total. Workgroup
+// NBINS: the product total and the largest chunk count.
+__global__ __launch_bounds__(1024) void k_tally(KArgs a) {
+    constexpr int T = 1024;
+    __shared__ int tmp[T / 64 + 1];
+    __shared__ unsigned long long s_tot;
+    __shared__ int s_max;
+    const int tid = threadIdx.x, b = blockIdx.x, nt = a.ntiles;
+    if (b < NBINS) {
+        int carry = 0;
+        for (int t0 = 0; t0 < nt; t0 += T) {
+            const int t = t0 + tid;
+            const int v = t < nt ? a.th[t * NBINS + b] : 0;
+            int total;
+            const int ex = wg_excl_scan<T>(v, tmp, total);
+            if (t < nt) a.th[t * NBINS + b] = carry + ex;
+            carry += total;
+        }
+        if (tid == 0) a.hdr->bin_count[b] = carry;
+    } else {
+        if (tid == 0) {
+            s_tot = 0;
+            s_max = 0;
+        }
+        __syncthreads();
+        unsigned long long tot = 0;
+        int mx = 0;
+        for (int t = tid; t < nt; t += T) {
+            tot += (unsigned long long)a.ttot[t];
+            mx = max(mx, a.tmax[t]);
+        }
+        atomicAdd(&s_tot, tot);
+        atomicMax(&s_max, mx);
+        __syncthreads();
+        if (tid == 0) {
+            a.hdr->total_op = s_tot;
+            a.hdr->big_chunks = s_max;
+        }
+    }
+}
+
+hipError_t launch_tally(const KArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tally, dim3(NBINS + 1), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- place
-// Same tiling. Each tile reserves a contiguous range in every bin list with
-// one global atomic per bin, then writes its columns there.
+// Same tiling. Each tile writes its columns to its range of every bin list
+// (the tally's per-tile positions), in any order inside the range.
 __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
     __shared__ int s_start[NBINS];
     __shared__ int s_cnt[NBINS];
@@ -164,7 +214,10 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
             run += a.hdr->bin_count[b];
         }
     }
-    if (tid < NBINS) s_cnt[tid] = 0;
+    if (tid < NBINS) {
+        s_cnt[tid] = 0;
+        s_base[tid] = a.th[blockIdx.x * NBINS + tid];
+    }
     __syncthreads();
 
     constexpr int PER = kTile / kBlock;
@@ -179,8 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
         }
     }
     __syncthreads();
-    if (tid < NBINS && s_cnt[tid])
-        s_base[tid] = s_start[tid] + atomicAdd(&a.hdr->bin_cursor[tid], s_cnt[tid]);
+    if (tid < NBINS) s_base[tid] += s_start[tid];
     __syncthreads();
     const int32_t *bcp = a.nprob == 1 ? a.single.bcp : a.table[pid].bcp;
 #pragma unroll

@@ -61,6 +61,8 @@ struct spgemm_plan_s {
     long long *gcp = nullptr, *bsum = nullptr, *totals = nullptr;
     Prob *table = nullptr;
     int4 *tiles = nullptr;
+    int32_t *th = nullptr, *tmax = nullptr;
+    long long *ttot = nullptr;
     int nbsum = 0;
 
     // pinned host mirror of the header and totals
@@ -128,6 +130,7 @@ struct ProfScope {
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+constexpr size_t kHdrBytes = (sizeof(Hdr) + 63) / 64 * 64;  // header, then the totals
 
 spgemm_status hip_status(hipError_t e) {
     if (e == hipSuccess) return SPGEMM_OK;
@@ -210,17 +213,20 @@ spgemm_status ensure_workspace(spgemm_plan p) {
         off = align_up(off + bytes, 256);
         return o;
     };
-    const size_t o_hdr = take(sizeof(Hdr));
+    // the header and the per-problem totals are adjacent: one copy reads both
+    const size_t o_hdr = take(kHdrBytes + 8 * (size_t)std::max(p->nprob, 1));
     const size_t o_op = take(4 * n), o_binw = take(4 * n), o_binlist = take(16 * n),
                  o_gnnz = take(4 * n);
     const size_t o_E = take(8 * (size_t)std::max(p->total_nnzb, 1ll));
     const size_t o_colprod = take(8 * (n + 1));
     const size_t o_gcp = take(8 * (n + 1));
     const size_t o_bsum = take(8 * (size_t)p->nbsum);
-    const size_t o_tot = take(8 * (size_t)std::max(p->nprob, 1));
     const size_t o_tab = take(sizeof(Prob) * (size_t)std::max(p->nprob, 1));
     const size_t o_c0 = take(4 * ((size_t)p->nprob + 1));
     const size_t o_tiles = take(sizeof(int4) * (size_t)std::max(p->ntiles, 1));
+    const size_t o_th = take(4 * (size_t)NBINS * std::max(p->ntiles, 1));
+    const size_t o_ttot = take(8 * (size_t)std::max(p->ntiles, 1));
+    const size_t o_tmax = take(4 * (size_t)std::max(p->ntiles, 1));
     const size_t need = off;
     if (need > p->ws_bytes) {
         if (p->ws) {
@@ -243,12 +249,15 @@ spgemm_status ensure_workspace(spgemm_plan p) {
     p->colprod = (long long *)(b + o_colprod);
     p->gcp = (long long *)(b + o_gcp);
     p->bsum = (long long *)(b + o_bsum);
-    p->totals = (long long *)(b + o_tot);
+    p->totals = (long long *)(b + o_hdr + kHdrBytes);
     p->table = (Prob *)(b + o_tab);
     p->col0s = (int32_t *)(b + o_c0);
     p->tiles = (int4 *)(b + o_tiles);
+    p->th = (int32_t *)(b + o_th);
+    p->ttot = (long long *)(b + o_ttot);
+    p->tmax = (int32_t *)(b + o_tmax);
 
-    const size_t pin = sizeof(Hdr) + 8 * (size_t)std::max(p->nprob, 1);
+    const size_t pin = kHdrBytes + 8 * (size_t)std::max(p->nprob, 1);
     if (pin > p->pinned_bytes) {
         if (p->pinned) (void)hipHostFree(p->pinned);
         p->pinned = nullptr;
@@ -268,6 +277,9 @@ KArgs make_args(spgemm_plan p) {
     a.ncols = p->ncols;
     a.ntiles = p->ntiles;
     a.tiles = p->tiles;
+    a.th = p->th;
+    a.ttot = p->ttot;
+    a.tmax = p->tmax;
     a.tune = p->tune;
     a.hdr = p->hdr;
     a.op = p->op;
@@ -459,6 +471,7 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
         SPG_TRY(hipMemsetAsync(p->hdr, 0, sizeof(Hdr), s));
         const KArgs a = make_args(p);
         { ProfScope ps("classify", s); SPG_TRY(launch_classify(a, s)); }
+        { ProfScope ps("tally", s); SPG_TRY(launch_tally(a, s)); }
         { ProfScope ps("place", s); SPG_TRY(launch_place(a, s)); }
         // the bin sizes fix the grid of every accumulator launch: read them once
         SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, sizeof(Hdr), hipMemcpyDeviceToHost, s));
@@ -497,15 +510,13 @@ spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4>
             ProfScope ps("scan", s);
             SPG_TRY(launch_scan(a, p->gcp, p->bsum, p->nblk, p->totals, s));
         }
-        SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, sizeof(Hdr), hipMemcpyDeviceToHost, s));
-        if (p->ncols > 0)
-            SPG_TRY(hipMemcpyAsync((char *)p->pinned + sizeof(Hdr), p->totals,
-                                   8 * (size_t)p->nprob, hipMemcpyDeviceToHost, s));
+        SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, kHdrBytes + 8 * (size_t)p->nprob,
+                               hipMemcpyDeviceToHost, s));
         SPG_TRY(hipStreamSynchronize(s));
         std::memcpy(&p->hdr_host, p->pinned, sizeof(Hdr));
         p->totals_host.assign(p->nprob, 0);
         if (p->ncols > 0)
-            std::memcpy(p->totals_host.data(), (char *)p->pinned + sizeof(Hdr), 8 * (size_t)p->nprob);
+            std::memcpy(p->totals_host.data(), (char *)p->pinned + kHdrBytes, 8 * (size_t)p->nprob);
         err = p->hdr_host.err;
         if (err & (ERR_CSC | ERR_GROUP)) return SPGEMM_ERR_CSC;
         if (err & (ERR_OPOVF | ERR_NNZOVF)) return SPGEMM_ERR_INDEX_OVERFLOW;
