@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-runs", type=int, default=4)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--t-esc", type=int, default=0, help="library option (0 = default)")
     ap.add_argument("--hash-cap", type=int, default=0, help="library option (0 = default)")
     ap.add_argument("--no-autotune", action="store_true",
