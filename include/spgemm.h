@@ -39,8 +39,9 @@
  * order like distinct products.
  *
  * Synchronisation: spgemm_symbolic and the size-query form of spgemm_batched
- * block the host until the output sizes are known. Every other call is
- * stream-ordered and returns immediately.
+ * block the host until the output sizes are known (one read-back at the end
+ * when the plan has run before with the same product count, two otherwise).
+ * Every other call is stream-ordered and returns immediately.
  */
 #ifndef SPGEMM_H
 #define SPGEMM_H
@@ -84,6 +85,10 @@ typedef struct spgemm_plan_s *spgemm_plan;
 #define SPGEMM_ONE_STREAM 2u /* run every accumulator kind on the caller's stream instead of
                                  overlapping them on internal side streams (same results;
                                  per-kernel timings without overlap) */
+#define SPGEMM_NO_PLANNED_LAUNCH 4u /* always read the bin sizes back before launching the
+                                       accumulators (by default a plan that has run before
+                                       launches the whole symbolic phase from its previous
+                                       sizes and redoes it only if the device finds others) */
 
 /*
  * Tuning options. Results never depend on them: they only choose which

@@ -56,7 +56,9 @@ enum ErrBits : int {
     ERR_CSC = 1,        // malformed input seen by a kernel
     ERR_OPOVF = 2,      // a column's product count exceeds INT32_MAX
     ERR_NNZOVF = 8,     // nnz(C) of a problem exceeds INT32_MAX
-    ERR_GROUP = 16      // a work item exceeded its planned bounds (inputs changed)
+    ERR_GROUP = 16,     // a work item exceeded its planned bounds (inputs changed)
+    ERR_RETRY = 32      // a launch planned from an earlier call met other sizes: the
+                        // product-space kernels did nothing, the host redoes the phase
 };
 
 // One problem of a (possibly single-problem) batch. All pointers are device
@@ -114,6 +116,12 @@ struct KArgs {
     long long *ttot;        // [ntiles]
     int32_t *tmax;          // [ntiles]
     Tune tune;
+    // A symbolic launch planned before the sizes are read back (from the
+    // previous call on the plan) covers the bins in spec_mask with product
+    // space for spec_total products; spec_total < 0 when the launch follows
+    // the read-back.
+    long long spec_total;
+    unsigned spec_mask;
     Hdr *hdr;
     int32_t *op;            // [ncols]
     int32_t *binw;          // [ncols] bin of every global column, window flags
@@ -182,11 +190,11 @@ hipError_t launch_place(const KArgs &a, hipStream_t s);
 hipError_t launch_esc(const KArgs &a, bool wide, int sub, int groups, hipStream_t s);
 // workgroup sort of sort bin `cls` (n columns); wide: 64-bit keys (rows beyond 20 bits)
 hipError_t launch_sort(const KArgs &a, int cls, bool wide, int n, hipStream_t s);
-// windowed workgroup sort of the `n` columns listed from bin-list position `first`
-hipError_t launch_wsort(const KArgs &a, bool wide, int first, int n, hipStream_t s);
-// workgroup accumulator of block class `cls` over the `n` columns listed from
-// bin-list position `first`
-hipError_t launch_block(const KArgs &a, int cls, int first, int n, hipStream_t s);
+// windowed workgroup sort (columns from the device header; any grid covers them)
+hipError_t launch_wsort(const KArgs &a, bool wide, int grid, hipStream_t s);
+// workgroup hash accumulator of block class `cls` (columns and their bin-list
+// positions from the device header; any grid covers them)
+hipError_t launch_block(const KArgs &a, int cls, int grid, hipStream_t s);
 hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk,
                        long long *totals, hipStream_t s);
 // first product of every global column (colprod) and first column of every

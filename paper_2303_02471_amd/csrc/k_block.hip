@@ -71,7 +71,7 @@ struct BlkSmem {
 __device__ __forceinline__ int blk_pad(int h, int cap) { return min(min(256, h / 4 + 16), cap - h); }
 
 template <int CLS>
-__global__ __launch_bounds__(BlkCfg<CLS>::T) void k_block(KArgs a, int first, int n) {
+__global__ __launch_bounds__(BlkCfg<CLS>::T) void k_block(KArgs a) {
     constexpr int T = BlkCfg<CLS>::T, TC = BlkCfg<CLS>::TC, PER = BlkCfg<CLS>::PER;
     constexpr int CH = T * PER;
     constexpr int PB = T <= 256 ? 8 : (T <= 512 ? 9 : 10);  // bits of a position in a chunk
@@ -82,6 +82,9 @@ __global__ __launch_bounds__(BlkCfg<CLS>::T) void k_block(KArgs a, int first, in
         return;  // every thread takes the same branch
     const int tid = threadIdx.x;
     unsigned *hw = (unsigned *)S.tab;  // hw[2s]: low word (e, then rank); hw[2s + 1]: row
+    int first = 0;
+    for (int b = 0; b < BIN_BLK0 + CLS; ++b) first += a.hdr->bin_count[b];
+    const int n = a.hdr->bin_count[BIN_BLK0 + CLS];
     int err = 0, kmax = 0;
     bool abort = false;  // workgroup-uniform: a window could not be split further
     if (tid == 0) S.s_kmax = 0;
@@ -411,10 +414,9 @@ __global__ __launch_bounds__(BlkCfg<CLS>::T) void k_block(KArgs a, int first, in
         atomicMax(&a.hdr->later_maxk, S.s_kmax);
 }
 
-hipError_t launch_block(const KArgs &a, int cls, int first, int n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-#define SPG_LAUNCH(C) \
-    hipLaunchKernelGGL((k_block<C>), dim3(n), dim3(BlkCfg<C>::T), 0, s, a, first, n)
+hipError_t launch_block(const KArgs &a, int cls, int grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+#define SPG_LAUNCH(C) hipLaunchKernelGGL((k_block<C>), dim3(grid), dim3(BlkCfg<C>::T), 0, s, a)
     switch (cls) {
         case 0: SPG_LAUNCH(0); break;
         case 1: SPG_LAUNCH(1); break;

@@ -156,7 +156,12 @@ __global__ __launch_bounds__(1024) void k_tally(KArgs a) {
             if (t < nt) a.th[t * NBINS + b] = carry + ex;
             carry += total;
         }
-        if (tid == 0) a.hdr->bin_count[b] = carry;
+        if (tid == 0) {
+            a.hdr->bin_count[b] = carry;
+            // a planned launch that does not cover a non-empty bin is redone
+            if (a.spec_total >= 0 && carry > 0 && !((a.spec_mask >> b) & 1u))
+                atomicOr(&a.hdr->err, ERR_RETRY);
+        }
     } else {
         if (tid == 0) {
             s_tot = 0;
@@ -175,6 +180,9 @@ __global__ __launch_bounds__(1024) void k_tally(KArgs a) {
         if (tid == 0) {
             a.hdr->total_op = s_tot;
             a.hdr->big_chunks = s_max;
+            // a planned launch sized for another product count is redone
+            if (a.spec_total >= 0 && s_tot != (unsigned long long)a.spec_total)
+                atomicOr(&a.hdr->err, ERR_RETRY);
         }
     }
 }
@@ -388,6 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_finish(KArgs a, const long long
 // product are empty.
 __global__ __launch_bounds__(kBlock) void k_prod_down(KArgs a, const long long *__restrict__ bsum) {
     __shared__ long long s[kScanBlock];
+    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
+        return;  // every thread takes the same branch
     const int n = a.ncols;
     ScanOut o;
     block_scan_down(a.op, n, bsum, s, o);

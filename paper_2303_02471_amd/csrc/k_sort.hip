@@ -217,9 +217,10 @@ __global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
 // products: one entry) needs no sort, its products take their occurrence
 // indices in product order.
 constexpr int kWinDepth = 48;
+constexpr int kWinRows = 12288;  // rows of a column staged in LDS (larger columns re-read)
 
 template <typename K>
-__global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
+__global__ __launch_bounds__(1024) void k_wsort(KArgs a) {
     constexpr int T = 1024, N = 4 * T, NW = T / 64;
     constexpr int EB = 12;  // bits of a window position (N <= 4096)
     constexpr K KMAX = KeyMax<K>::v;
@@ -227,6 +228,7 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
     __shared__ K buf[N];     // keys, exchanges, then the sorted keys
     __shared__ int rh[N];    // sorted position of every run head
     __shared__ int emap[N];  // product position of every window position
+    __shared__ int srow[kWinRows];  // the column's rows, when they fit
     __shared__ int wcnt[NW + 1];
     __shared__ int scan_tmp[NW + 1];
     __shared__ int stk_lo[kWinDepth], stk_hi[kWinDepth];
@@ -234,6 +236,9 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
     if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
         return;  // every thread takes the same branch
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, sb = wave * 256;
+    int first = 0;
+    for (int b = 0; b < BIN_WSORT; ++b) first += a.hdr->bin_count[b];
+    const int n = a.hdr->bin_count[BIN_WSORT];
     if (tid == 0) s_kmax = 0;
     int kmax = 0;
     bool abort = false;  // workgroup-uniform
@@ -243,19 +248,30 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
         const long long pbase = a.colprod[g];
         const int *__restrict__ prow = a.prow + pbase;
         uint32_t *__restrict__ dstp = a.dst + pbase;
-        // rows of the column, and a contiguous range of products per thread
+        // the column's rows, staged in LDS when they fit (coalesced loads, four
+        // in flight per thread); every window pass then reads them there
+        const bool staged = op <= kWinRows;
         if (tid == 0) {
             s_min = 0x7fffffff;
             s_max = -1;
         }
+        int mn = 0x7fffffff, mx = -1;
+        for (int e = tid; e < op; e += 4 * T) {
+            int r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) r[u] = e + u * T < op ? prow[e + u * T] : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (r[u] < 0) continue;
+                mn = min(mn, r[u]);
+                mx = max(mx, r[u]);
+                if (staged) srow[e + u * T] = r[u];
+            }
+        }
+        // (separate paths keep the LDS reads as LDS instructions)
+        auto row_at = [&](int e) { return staged ? srow[e] : prow[e]; };
         __syncthreads();
         {
-            int mn = 0x7fffffff, mx = -1;
-            for (int e = tid; e < op; e += T) {
-                const int r = prow[e];
-                mn = min(mn, r);
-                mx = max(mx, r);
-            }
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) {
                 mn = min(mn, __builtin_amdgcn_ds_bpermute((lane ^ d) << 2, mn));
@@ -270,7 +286,8 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
         const int lo = s_min, span = s_max + 1 - s_min;
         const int q = ceil_div(op, T);
         const int e0 = min(op, tid * q), e1 = min(op, e0 + q);
-        int W = ceil_div(op, 3 * N / 4);
+        // windows planned for about 0.9 of a sort (a window above N splits)
+        int W = ceil_div(op, 9 * N / 10);
         if (W > span) W = span;
         int total = 0, ltotal = 0;
         for (int w = 0; w < W && !abort; ++w) {
@@ -286,7 +303,7 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
                 // the window's products, numbered in product order
                 int c = 0;
                 for (int e = e0; e < e1; ++e) {
-                    const int r = prow[e];
+                    const int r = row_at(e);
                     c += r >= x && r < y;
                 }
                 int cnt;
@@ -310,7 +327,7 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
                     // one row: one entry; occurrence indices in product order
                     int k = off;
                     for (int e = e0; e < e1; ++e) {
-                        const int r = prow[e];
+                        const int r = row_at(e);
                         if (r < x || r >= y) continue;
                         if (k == 0) {
                             dstp[e] = (uint32_t)total;
@@ -331,7 +348,7 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
                 {
                     int i = off;
                     for (int e = e0; e < e1; ++e) {
-                        const int r = prow[e];
+                        const int r = row_at(e);
                         if (r < x || r >= y) continue;
                         emap[i] = e;
                         buf[i] = ((K)r << EB) | (K)i;
@@ -411,10 +428,10 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a, int first, int n) {
         atomicMax(&a.hdr->later_maxk, s_kmax);
 }
 
-hipError_t launch_wsort(const KArgs &a, bool wide, int first, int n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    if (wide) hipLaunchKernelGGL((k_wsort<unsigned long long>), dim3(n), dim3(1024), 0, s, a, first, n);
-    else hipLaunchKernelGGL((k_wsort<unsigned>), dim3(n), dim3(1024), 0, s, a, first, n);
+hipError_t launch_wsort(const KArgs &a, bool wide, int grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    if (wide) hipLaunchKernelGGL((k_wsort<unsigned long long>), dim3(grid), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL((k_wsort<unsigned>), dim3(grid), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 

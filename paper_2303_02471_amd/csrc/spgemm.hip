@@ -52,6 +52,8 @@ struct spgemm_plan_s {
     uint32_t *dst = nullptr;
     int32_t *lk = nullptr, *lr = nullptr, *tilestart = nullptr;
     int nptiles = 0;
+    long long prod_total = 0;  // products the product-space arrays are carved for
+    bool spec_ready = false;   // a planned symbolic launch may be tried
     // staging of the later products for the numeric phase (sized by their count)
     void *stage = nullptr;
     size_t stage_bytes = 0;
@@ -383,11 +385,11 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
         if (!n) continue;
         hipStream_t sc = side(p, c == kBlkBins - 1 ? 2 : 0, s);
         ProfScope ps(bnames[c], sc);
-        if ((e = launch_block(a, c, bin_start(h, BIN_BLK0 + c), n, sc))) return e;
+        if ((e = launch_block(a, c, n, sc))) return e;
     }
     if (const int n = h.bin_count[BIN_WSORT]) {
         ProfScope ps("wsort_symbolic", side(p, 2, s));
-        if ((e = launch_wsort(a, p->wide_keys, bin_start(h, BIN_WSORT), n, side(p, 2, s))))
+        if ((e = launch_wsort(a, p->wide_keys, n, side(p, 2, s))))
             return e;
     }
     static const char *snames[kSortBins] = {"sort512_symbolic", "sort1k_symbolic",
@@ -452,106 +454,153 @@ hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
     return hipSuccess;
 }
 
-// Symbolic launch sequence; returns after the totals are on the host.
-spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4> &tiles_host) {
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        spgemm_status st = ensure_workspace(p);
-        if (st) return st;
-        if (p->nprob > 1) {
-            std::vector<int32_t> c0(p->nprob + 1);
-            for (int i = 0; i < p->nprob; ++i) c0[i] = p->probs[i].col0;
-            c0[p->nprob] = p->ncols;
-            SPG_TRY(hipMemcpyAsync(p->table, p->probs.data(), sizeof(Prob) * p->nprob,
-                                   hipMemcpyHostToDevice, s));
-            SPG_TRY(hipMemcpyAsync(p->col0s, c0.data(), 4 * c0.size(), hipMemcpyHostToDevice, s));
-            SPG_TRY(hipMemcpyAsync(p->tiles, tiles_host.data(), sizeof(int4) * tiles_host.size(),
-                                   hipMemcpyHostToDevice, s));
-            p->table_dev_copy = p->probs;
+// Product-space arrays for `total` products (the allocation only grows).
+spgemm_status ensure_products(spgemm_plan p, unsigned long long total) {
+    const size_t P = (size_t)std::max<unsigned long long>(total, 1);
+    const size_t q1 = align_up(4 * P, 256);
+    p->nptiles = (int)(total / kProdTile) + 1;
+    const size_t pneed = 4 * q1 + 4 * ((size_t)p->nptiles + 1);
+    if (pneed > p->prod_bytes) {
+        if (p->prod) {
+            if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
+            (void)hipFree(p->prod);
         }
-        SPG_TRY(hipMemsetAsync(p->hdr, 0, sizeof(Hdr), s));
-        const KArgs a = make_args(p);
+        p->prod = nullptr;
+        p->prod_bytes = 0;
+        if (hipMalloc(&p->prod, pneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
+        p->prod_bytes = pneed;
+    }
+    p->prow = (int32_t *)p->prod;
+    p->dst = (uint32_t *)((char *)p->prod + q1);
+    p->lk = (int32_t *)((char *)p->prod + 2 * q1);
+    p->lr = (int32_t *)((char *)p->prod + 3 * q1);
+    p->tilestart = (int32_t *)((char *)p->prod + 4 * q1);
+    p->prod_total = (long long)total;
+    return SPGEMM_OK;
+}
+
+// One pass of the symbolic launch sequence; returns after the totals are on
+// the host. A planned pass (spec) launches everything from the sizes of the
+// plan's previous call with no read-back in between; when the device finds
+// other sizes it does no product-space work and *retry is set.
+spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4> &tiles_host,
+                            bool spec, bool *retry) {
+    *retry = false;
+    spgemm_status st = ensure_workspace(p);
+    if (st) return st;
+    if (p->nprob > 1) {
+        std::vector<int32_t> c0(p->nprob + 1);
+        for (int i = 0; i < p->nprob; ++i) c0[i] = p->probs[i].col0;
+        c0[p->nprob] = p->ncols;
+        SPG_TRY(hipMemcpyAsync(p->table, p->probs.data(), sizeof(Prob) * p->nprob,
+                               hipMemcpyHostToDevice, s));
+        SPG_TRY(hipMemcpyAsync(p->col0s, c0.data(), 4 * c0.size(), hipMemcpyHostToDevice, s));
+        SPG_TRY(hipMemcpyAsync(p->tiles, tiles_host.data(), sizeof(int4) * tiles_host.size(),
+                               hipMemcpyHostToDevice, s));
+        // the pageable sources may change after return: wait for the copies
+        SPG_TRY(hipStreamSynchronize(s));
+        p->table_dev_copy = p->probs;
+    }
+    SPG_TRY(hipMemsetAsync(p->hdr, 0, sizeof(Hdr), s));
+    // launches are planned from hdr_host: the previous call's sizes (spec) or
+    // this call's, read back after the placement
+    unsigned mask = 0;
+    for (int b = 0; b < NBINS; ++b) mask |= (p->hdr_host.bin_count[b] > 0 ? 1u : 0u) << b;
+    auto args = [&]() {
+        KArgs a = make_args(p);
+        a.spec_total = spec ? p->prod_total : -1;
+        a.spec_mask = spec ? mask : 0u;
+        return a;
+    };
+    {
+        const KArgs a = args();
         { ProfScope ps("classify", s); SPG_TRY(launch_classify(a, s)); }
         { ProfScope ps("tally", s); SPG_TRY(launch_tally(a, s)); }
         { ProfScope ps("place", s); SPG_TRY(launch_place(a, s)); }
-        // the bin sizes fix the grid of every accumulator launch: read them once
+    }
+    if (!spec) {
+        // the bin sizes fix the grids and the product count the allocation
         SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, sizeof(Hdr), hipMemcpyDeviceToHost, s));
         SPG_TRY(hipStreamSynchronize(s));
         std::memcpy(&p->hdr_host, p->pinned, sizeof(Hdr));
-        int err = p->hdr_host.err;
+        const int err = p->hdr_host.err;
         if (err & ERR_CSC) return SPGEMM_ERR_CSC;
         if (err & ERR_OPOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
-        // per-product arrays
-        const Hdr &hh = p->hdr_host;
-        const size_t P = (size_t)std::max<unsigned long long>(hh.total_op, 1);
-        const size_t q1 = align_up(4 * P, 256);
-        p->nptiles = (int)(hh.total_op / kProdTile) + 1;
-        const size_t pneed = 4 * q1 + 4 * ((size_t)p->nptiles + 1);
-        if (pneed > p->prod_bytes) {
-            if (p->prod) (void)hipFree(p->prod);
-            p->prod = nullptr;
-            p->prod_bytes = 0;
-            if (hipMalloc(&p->prod, pneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
-            p->prod_bytes = pneed;
+        if ((st = ensure_products(p, p->hdr_host.total_op))) return st;
+    }
+    if (p->ncols > 0) {
+        const KArgs al = args();
+        {
+            // first product of every column (exclusive scan of Op_j), tiles
+            ProfScope ps("product_offsets", s);
+            SPG_TRY(launch_prod_offsets(al, p->bsum, p->nbsum, s));
         }
-        p->prow = (int32_t *)p->prod;
-        p->dst = (uint32_t *)((char *)p->prod + q1);
-        p->lk = (int32_t *)((char *)p->prod + 2 * q1);
-        p->lr = (int32_t *)((char *)p->prod + 3 * q1);
-        p->tilestart = (int32_t *)((char *)p->prod + 4 * q1);
-        if (p->ncols > 0) {
-            const KArgs al = make_args(p);
-            {
-                // first product of every column (exclusive scan of Op_j), tiles
-                ProfScope ps("product_offsets", s);
-                SPG_TRY(launch_prod_offsets(al, p->bsum, p->nbsum, s));
-            }
-            { ProfScope ps("expand", s); SPG_TRY(launch_expand(al, s)); }
-            SPG_TRY(launch_symbolic_accumulators(p, al, s));
-            ProfScope ps("scan", s);
-            SPG_TRY(launch_scan(a, p->gcp, p->bsum, p->nblk, p->totals, s));
-        }
-        SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, kHdrBytes + 8 * (size_t)p->nprob,
-                               hipMemcpyDeviceToHost, s));
-        SPG_TRY(hipStreamSynchronize(s));
-        std::memcpy(&p->hdr_host, p->pinned, sizeof(Hdr));
-        p->totals_host.assign(p->nprob, 0);
-        if (p->ncols > 0)
-            std::memcpy(p->totals_host.data(), (char *)p->pinned + kHdrBytes, 8 * (size_t)p->nprob);
-        err = p->hdr_host.err;
-        if (err & (ERR_CSC | ERR_GROUP)) return SPGEMM_ERR_CSC;
-        if (err & (ERR_OPOVF | ERR_NNZOVF)) return SPGEMM_ERR_INDEX_OVERFLOW;
-        // staging of the later products: every product beyond the first of
-        // its entry
-        long long nnz_all = 0;
-        for (long long t : p->totals_host) nnz_all += t;
-        p->later_total = (long long)p->hdr_host.total_op - nnz_all;
-        if (p->later_total < 0) return SPGEMM_ERR_CSC;  // cannot happen
-        const size_t NL = (size_t)std::max<long long>(p->later_total, 1);
-        const size_t vsz = p->dt == SPGEMM_F64 ? 8 : 4;
-        const size_t o_pid = align_up(4 * NL, 256), o_k = o_pid + align_up(4 * NL, 256);
-        const size_t o_v = o_k + align_up(4 * NL, 256);
-        const size_t sneed = o_v + vsz * NL;
-        if (sneed > p->stage_bytes) {
-            if (p->stage) (void)hipFree(p->stage);
-            p->stage = nullptr;
-            p->stage_bytes = 0;
-            if (hipMalloc(&p->stage, sneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
-            p->stage_bytes = sneed;
-        }
-        p->lo = (int32_t *)p->stage;
-        p->lpid = (int32_t *)((char *)p->stage + o_pid);
-        p->lkc = (int32_t *)((char *)p->stage + o_k);
-        p->lv = (char *)p->stage + o_v;
-        if (p->ncols == 0) {
-            // no columns at all: every problem's column pointer is {0}
-            for (int i = 0; i < p->nprob; ++i)
-                SPG_TRY(hipMemsetAsync(p->probs[i].ccp, 0, sizeof(int32_t), s));
-            SPG_TRY(hipStreamSynchronize(s));
-        }
-        p->symbolic_ok = true;
+        { ProfScope ps("expand", s); SPG_TRY(launch_expand(al, s)); }
+        SPG_TRY(launch_symbolic_accumulators(p, al, s));
+        ProfScope ps("scan", s);
+        SPG_TRY(launch_scan(al, p->gcp, p->bsum, p->nblk, p->totals, s));
+    }
+    SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, kHdrBytes + 8 * (size_t)p->nprob,
+                           hipMemcpyDeviceToHost, s));
+    SPG_TRY(hipStreamSynchronize(s));
+    std::memcpy(&p->hdr_host, p->pinned, sizeof(Hdr));
+    int err = p->hdr_host.err;
+    if (err & ERR_CSC) return SPGEMM_ERR_CSC;
+    if (err & ERR_OPOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
+    if (spec && (err & ERR_RETRY)) {
+        *retry = true;
         return SPGEMM_OK;
     }
-    return SPGEMM_ERR_NO_MEMORY;
+    p->totals_host.assign(p->nprob, 0);
+    if (p->ncols > 0)
+        std::memcpy(p->totals_host.data(), (char *)p->pinned + kHdrBytes, 8 * (size_t)p->nprob);
+    if (err & (ERR_GROUP | ERR_RETRY)) return SPGEMM_ERR_CSC;
+    if (err & ERR_NNZOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
+    // staging of the later products: every product beyond the first of its entry
+    long long nnz_all = 0;
+    for (long long t : p->totals_host) nnz_all += t;
+    p->later_total = (long long)p->hdr_host.total_op - nnz_all;
+    if (p->later_total < 0) return SPGEMM_ERR_CSC;  // cannot happen
+    const size_t NL = (size_t)std::max<long long>(p->later_total, 1);
+    const size_t vsz = p->dt == SPGEMM_F64 ? 8 : 4;
+    const size_t o_pid = align_up(4 * NL, 256), o_k = o_pid + align_up(4 * NL, 256);
+    const size_t o_v = o_k + align_up(4 * NL, 256);
+    const size_t sneed = o_v + vsz * NL;
+    if (sneed > p->stage_bytes) {
+        if (p->stage) (void)hipFree(p->stage);
+        p->stage = nullptr;
+        p->stage_bytes = 0;
+        if (hipMalloc(&p->stage, sneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
+        p->stage_bytes = sneed;
+    }
+    p->lo = (int32_t *)p->stage;
+    p->lpid = (int32_t *)((char *)p->stage + o_pid);
+    p->lkc = (int32_t *)((char *)p->stage + o_k);
+    p->lv = (char *)p->stage + o_v;
+    if (p->ncols == 0) {
+        // no columns at all: every problem's column pointer is {0}
+        for (int i = 0; i < p->nprob; ++i)
+            SPG_TRY(hipMemsetAsync(p->probs[i].ccp, 0, sizeof(int32_t), s));
+        SPG_TRY(hipStreamSynchronize(s));
+    }
+    p->symbolic_ok = true;
+    p->spec_ready = p->ncols > 0;
+    return SPGEMM_OK;
+}
+
+// Symbolic phase: a planned pass when the plan has run before, the pass with
+// the mid read-back when it has not or when the sizes changed.
+spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4> &tiles_host) {
+    bool retry = false;
+    if (p->spec_ready && !(p->flags & SPGEMM_NO_PLANNED_LAUNCH)) {
+        const spgemm_status st = symbolic_pass(p, s, tiles_host, true, &retry);
+        if (st || !retry) {
+            if (st) p->spec_ready = false;
+            return st;
+        }
+    }
+    p->spec_ready = false;
+    return symbolic_pass(p, s, tiles_host, false, &retry);
 }
 
 spgemm_status run_numeric(spgemm_plan p, hipStream_t s) {

@@ -264,3 +264,34 @@ def test_repeated_row_heavy_column():
     B = _csc_from_columns(5000, [rng.choice(5000, size=d, replace=False)
                                  for d in (4500, 3000, 7, 1600)], rng)
     check_f64(A, B, what="repeated row")
+
+
+def test_planned_launch_and_retry():
+    """A plan that has run before launches its symbolic phase from the previous
+    sizes; when the device finds other sizes (another product count, or the
+    same count spread over other bins) the phase is redone. Results always
+    equal the oracle's."""
+    import torch
+    from paper_2303_02471_amd import api
+    _say("planned symbolic launches, reuse and retry")
+    rng = np.random.default_rng(17)
+    A = gen.uniform_z(1000, 10, seed=7)
+    # two columns of 100 products; then 190 + 10 products (same total, other
+    # bins); then another product count; then the first pair again
+    B1 = _csc_from_columns(1000, [rng.choice(1000, 10, replace=False) for _ in range(2)], rng)
+    B2 = _csc_from_columns(1000, [rng.choice(1000, 19, replace=False),
+                                  rng.choice(1000, 1, replace=False)], rng)
+    B3 = gen.uniform_z(1000, 6, seed=8, nrows=1000)
+    At = api.CscTensor.from_host(A)
+    plan = None
+    for B in (B1, B1, B2, B3, B1, B1):
+        Bt = api.CscTensor.from_host(B)
+        plan, colptr, nnz = api.symbolic(At, Bt, torch.float64, None, plan=plan)
+        ri = torch.empty(nnz, dtype=torch.int32, device="cuda")
+        v = torch.empty(nnz, dtype=torch.float64, device="cuda")
+        api.numeric(plan, At.val, Bt.val, ri, v)
+        torch.cuda.synchronize()
+        ocp, ori, ov = oracle.spgemm(A, B)
+        assert_same_structure(colptr.cpu().numpy(), ri.cpu().numpy(), ocp, ori, "planned")
+        assert_values_exact(v.cpu().numpy(), ov, "planned")
+    plan.close()
