@@ -58,6 +58,15 @@ def parse():
                     help="library option: no overlap of accumulator kinds (per-kernel timings)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (default: a temporary one); profiled runs "
+                         "pass the timed run's file to reuse its options")
+    ap.add_argument("--record-traffic", nargs=4,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="no GPU: turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output of this "
+                         "benchmark and of --copy-calibration into profiles/traffic.json")
+    ap.add_argument("--traffic-kernel", default="numeric",
+                    help="launch group whose traffic --record-traffic records")
     return ap.parse_args()
 
 
@@ -73,6 +82,65 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
+
+
+# launch group -> kernel symbol (FP64 runs)
+KERNEL_SYMBOL = {"numeric": "k_numeric<double>", "numeric_big": "k_numeric_big<double>",
+                 "expand": "k_expand", "wsort_symbolic": "k_wsort<unsigned int>"}
+
+
+def _src_digest():
+    """Digest of the library sources: traffic counters taken on other sources
+    are stale."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2303_02471_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        rows += list(csv.DictReader(open(f)))
+    return rows
+
+
+def _per_dispatch(rows, counter, symbol):
+    v = [float(r["Counter_Value"]) for r in rows
+         if r["Counter_Name"] == counter and symbol in r["Kernel_Name"]]
+    return sum(v) / len(v) if v else None, len(v)
+
+
+def record_traffic(args):
+    """HBM-side bytes per launch of one kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the same
+    counter reads for a plain 1 GiB device copy."""
+    fdir, wdir, cfdir, cwdir = args.record_traffic
+    sym = KERNEL_SYMBOL[args.traffic_kernel]
+    fetch, nf = _per_dispatch(_pmc_rows(fdir), "FETCH_SIZE", sym)
+    write, nw = _per_dispatch(_pmc_rows(wdir), "WRITE_SIZE", sym)
+    cfetch, _ = _per_dispatch(_pmc_rows(cfdir), "FETCH_SIZE", "copyBuffer")
+    cwrite, _ = _per_dispatch(_pmc_rows(cwdir), "WRITE_SIZE", "copyBuffer")
+    gib_kib = float(1 << 20)
+    fs, ws = gib_kib / cfetch, gib_kib / cwrite
+    out = {"kernel_key": args.traffic_kernel, "kernel_symbol": sym,
+           "workload": f"powerlaw_n{args.n}",
+           "fetch_kib_per_dispatch": round(fetch, 1), "write_kib_per_dispatch": round(write, 1),
+           "dispatches": [nf, nw],
+           "copy_calibration": {"copy_bytes": 1 << 30, "fetch_kib": cfetch, "write_kib": cwrite,
+                                "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
+           "hbm_bytes_per_launch": int(round((fetch * fs + write * ws) * 1024)),
+           "source_digest": _src_digest()}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def csc_bytes(n, nnz, vb):
@@ -116,6 +184,9 @@ def kernel_bytes(op, nb, nnzc, sel, vb):
 
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(args)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -148,7 +219,7 @@ def main():
         # the options never change results)
         with tempfile.TemporaryDirectory() as td:
             opts, trep = api.autotune([(At, Bt)], torch.float64,
-                                      cache_path=os.path.join(td, "tune.json"))
+                                      cache_path=args.tune_cache or os.path.join(td, "tune.json"))
         if args.one_stream:
             opts.flags |= 2
         tuning = {"t_esc": opts.t_esc, "t_block": opts.t_block, "t_split": opts.t_split,
@@ -235,7 +306,8 @@ def main():
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         tj = json.load(open(tfile))
-        if tj.get("kernel_key") == dom and tj.get("workload") == f"powerlaw_n{args.n}":
+        if tj.get("kernel_key") == dom and tj.get("workload") == f"powerlaw_n{args.n}" and \
+                tj.get("source_digest") == _src_digest():
             traffic = tj.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
