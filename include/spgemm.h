@@ -174,9 +174,15 @@ spgemm_status spgemm_numeric(spgemm_plan plan, const void *A_val, const void *B_
  * respect to the stored values of A and B, sparsity patterns fixed:
  *   dA(i,k) = sum_j G(i,j) B(k,j)  over stored B(k,j), j ascending   (G B^T on A's pattern)
  *   dB(k,j) = sum_i A(i,k) G(i,j)  over stored A(i,k), A's order     (A^T G on B's pattern)
- * C_rowidx is the array spgemm_numeric filled. dA_val or dB_val may be NULL
- * to skip that gradient. Single-problem plans only. The first call builds and
- * caches a row view of B's pattern inside the plan (may allocate).
+ * G_val [nnz(C)] is in the entry order spgemm_numeric gave C; C_rowidx is
+ * the row array it filled (C's positions come from the plan, so only its
+ * presence is checked). A_val, B_val, G_val device arrays of the plan's dtype;
+ * dA_val [A.nnz], dB_val [B.nnz] device outputs, either may be NULL to skip
+ * that gradient. Every term is added in the stated order without FMA, so the
+ * result equals the sequential sums bit for bit. Single-problem plans only.
+ * The first call builds and caches a view of the two patterns inside the plan
+ * (per stored entry: its first product and C column start; a row view of B)
+ * and may allocate; later calls on the plan are stream-ordered and do not.
  */
 spgemm_status spgemm_backward(spgemm_plan plan, const void *A_val, const void *B_val,
                               const int32_t *C_rowidx, const void *G_val,

@@ -212,13 +212,47 @@ hipError_t launch_numeric_big(const KArgs &a, bool f64, int first, int nbig, int
                               hipStream_t s);
 // adds the staged later products of occurrence index k (n of them listed)
 hipError_t launch_layer(const KArgs &a, bool f64, int k, long long n, hipStream_t s);
-hipError_t launch_btranspose(const Prob &p, int32_t *rowptr, int32_t *fill, int32_t *colj,
-                             int32_t *pos, long long *scratch, int nscratch, hipStream_t s);
-hipError_t launch_backward(const Prob &p, bool f64, const void *av, const void *bv,
-                           const int32_t *cri, const void *gv, void *da, void *db,
-                           const int32_t *rowptr, const int32_t *colj, const int32_t *pos,
-                           int *err, hipStream_t s);
+// Backward view, built once per single-problem plan: per stored B entry its
+// first product (pofs) and its column's first C entry (cb); per stored A entry
+// (column, offset in the column); a row view of B (rowptr over B's rows,
+// entries by ascending column) holding (B entry, cb) and the first product.
+struct BwView {
+    const int2 *E;            // the plan's (A column start, length) per stored B entry
+    const uint32_t *dst;      // the plan's product destinations
+    long long nnzc;           // stored entries of C
+    const long long *pofs;    // [nnz(B)]
+    const int32_t *cb;        // [nnz(B)]
+    const int2 *aview;        // [nnz(A)]
+    const int32_t *rowptr;    // [rows of B + 1]
+    const int2 *rv;           // [nnz(B)]
+    const long long *rvp;     // [nnz(B)]
+};
+// writable arrays of the view and its construction temporaries
+struct BwBuild {
+    long long *pofs;
+    int32_t *cb;
+    int2 *aview;
+    int32_t *rowptr;
+    int2 *rv;
+    long long *rvp;
+    int32_t *fill, *colj, *pos, *bcol, *len;
+    long long *scratch;  // scan partials of the row counts (nscratch)
+    int nscratch;
+    long long *scratch2;  // scan partials of the product counts (nscratch2)
+    int nscratch2;
+};
+hipError_t launch_bw_view(const Prob &p, const int2 *E, const BwBuild &b, BwView &w,
+                          hipStream_t s);
+// dA (if da) and dB (if db) of one problem through the view; err collects
+// ERR_CSC for a destination outside C (an inconsistent plan)
+hipError_t launch_backward(const Prob &p, const BwView &w, bool f64, const void *av,
+                           const void *bv, const void *gv, void *da, void *db, int *err,
+                           hipStream_t s);
+// exclusive scans of n int32 values (bsum: nbsum partials, in place allowed
+// for the int32 output)
 hipError_t launch_scan_i32(const int32_t *in, int n, long long *bsum, int nbsum, int32_t *out,
+                           hipStream_t s);
+hipError_t launch_scan_i64(const int32_t *in, int n, long long *bsum, int nbsum, long long *out,
                            hipStream_t s);
 
 constexpr int kScanBlock = 1024;  // elements per scan block

@@ -5,9 +5,16 @@
 //   dA(i,k) = sum over stored B(k,j), j ascending,          of G(i,j) B(k,j)
 // One thread owns one output entry and adds its terms sequentially in the
 // stated order (no fused multiply-add), so the result is reproducible and
-// matches a plain sequential loop bit for bit. G(i,j) is found by binary
-// search of row i in the ascending rows of C's column j. dA walks B by rows
-// through a row view of B's pattern (built once per plan).
+// matches a plain sequential loop bit for bit.
+//
+// Every term is one product of the forward pass: stored B entry t of column j
+// times the u-th entry of A's column bri[t]. The symbolic phase recorded that
+// product's rank among the entries of C's column j (dst, flag bit aside), so
+// G(i,j) sits at ccp[j] + rank: no search of C's rows. A view built once per
+// plan holds, per stored B entry, its first product (pofs) and its column's
+// first C entry (cb); per stored A entry, its column and offset in it; and a
+// row view of B (entries of each row by ascending column) with the same two
+// values per entry, so the dA loop reads them without an indirection.
 #include "devutil.h"
 
 namespace spg {
@@ -23,76 +30,122 @@ __device__ __forceinline__ int column_of(const int32_t *cp, int n, int t) {
     return lo;
 }
 
-// position of row i in cri[c0, c1) (ascending), or -1
-__device__ __forceinline__ int find_row(const int32_t *cri, int c0, int c1, int i) {
-    int lo = c0, hi = c1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (cri[mid] < i) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < c1 && cri[lo] == i) ? lo : -1;
+constexpr int kBwUnroll = 4;  // terms whose loads are issued together
+
+template <typename V>
+__device__ __forceinline__ V g_at(const V *__restrict__ gv, long long nnzc, int cb, uint32_t d,
+                                  int &bad) {
+    const long long gp = (long long)cb + (long long)(d & ~kDstLater);
+    if (gp >= nnzc) { bad = 1; return V(0); }
+    return gv[gp];
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_grad_b(Prob p, const V *__restrict__ av,
-                                                   const int32_t *__restrict__ cri,
+__global__ __launch_bounds__(kBlock) void k_grad_b(BwView w, int nnzb, const V *__restrict__ av,
                                                    const V *__restrict__ gv, V *__restrict__ db,
                                                    int *err) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= p.nnzb) return;
-    const int j = column_of(p.bcp, p.n, t);
-    const int k = p.bri[t];
-    const int c0 = p.ccp[j], c1 = p.ccp[j + 1];
+    if (t >= nnzb) return;
+    const int2 e = w.E[t];  // A column start and length of the entry's row of B
+    const long long base = w.pofs[t];
+    const int cb = w.cb[t];
+    const V *__restrict__ ap = av + e.x;
+    const uint32_t *__restrict__ dp = w.dst + base;
     V acc = V(0);
-    for (int q = p.acp[k]; q < p.acp[k + 1]; ++q) {
-        const int at = find_row(cri, c0, c1, p.ari[q]);
-        if (at < 0) { atomicOr(err, ERR_CSC); break; }
-        acc = acc + av[q] * gv[at];
+    int bad = 0, u = 0;
+    for (; u + kBwUnroll <= e.y; u += kBwUnroll) {
+        V a[kBwUnroll], g[kBwUnroll];
+        uint32_t d[kBwUnroll];
+#pragma unroll
+        for (int v = 0; v < kBwUnroll; ++v) {
+            a[v] = ap[u + v];
+            d[v] = dp[u + v];
+        }
+#pragma unroll
+        for (int v = 0; v < kBwUnroll; ++v) g[v] = g_at(gv, w.nnzc, cb, d[v], bad);
+#pragma unroll
+        for (int v = 0; v < kBwUnroll; ++v) acc = acc + a[v] * g[v];
     }
+    for (; u < e.y; ++u) acc = acc + ap[u] * g_at(gv, w.nnzc, cb, dp[u], bad);
     db[t] = acc;
+    if (bad) atomicOr(err, ERR_CSC);
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_grad_a(Prob p, const V *__restrict__ bv,
-                                                   const int32_t *__restrict__ cri,
+__global__ __launch_bounds__(kBlock) void k_grad_a(BwView w, int nnza, const V *__restrict__ bv,
                                                    const V *__restrict__ gv, V *__restrict__ da,
-                                                   const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ colj,
-                                                   const int32_t *__restrict__ pos, int *err) {
+                                                   int *err) {
     const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= p.nnza) return;
-    const int k = column_of(p.acp, p.k, q);
-    const int i = p.ari[q];
+    if (q >= nnza) return;
+    const int2 ku = w.aview[q];  // column of A (= row of B) and offset in that column
+    const int r0 = w.rowptr[ku.x], r1 = w.rowptr[ku.x + 1];
     V acc = V(0);
-    for (int r = rowptr[k]; r < rowptr[k + 1]; ++r) {
-        const int j = colj[r];
-        const int at = find_row(cri, p.ccp[j], p.ccp[j + 1], i);
-        if (at < 0) { atomicOr(err, ERR_CSC); break; }
-        acc = acc + gv[at] * bv[pos[r]];
+    int bad = 0, r = r0;
+    for (; r + kBwUnroll <= r1; r += kBwUnroll) {
+        int2 tc[kBwUnroll];
+        long long pf[kBwUnroll];
+#pragma unroll
+        for (int v = 0; v < kBwUnroll; ++v) {
+            tc[v] = w.rv[r + v];
+            pf[v] = w.rvp[r + v];
+        }
+        uint32_t d[kBwUnroll];
+        V b[kBwUnroll], g[kBwUnroll];
+#pragma unroll
+        for (int v = 0; v < kBwUnroll; ++v) {
+            d[v] = w.dst[pf[v] + ku.y];
+            b[v] = bv[tc[v].x];
+        }
+#pragma unroll
+        for (int v = 0; v < kBwUnroll; ++v) g[v] = g_at(gv, w.nnzc, tc[v].y, d[v], bad);
+#pragma unroll
+        for (int v = 0; v < kBwUnroll; ++v) acc = acc + g[v] * b[v];
+    }
+    for (; r < r1; ++r) {
+        const int2 tc = w.rv[r];
+        const uint32_t d = w.dst[w.rvp[r] + ku.y];
+        acc = acc + g_at(gv, w.nnzc, tc.y, d, bad) * bv[tc.x];
     }
     da[q] = acc;
+    if (bad) atomicOr(err, ERR_CSC);
 }
 
-// ---------------------------------------------------------------- row view of B
-__global__ __launch_bounds__(kBlock) void k_bt_count(Prob p, int32_t *cnt) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t < p.nnzb) atomicAdd(&cnt[p.bri[t]], 1);
-}
-
-__global__ __launch_bounds__(kBlock) void k_bt_fill(Prob p, const int32_t *rowptr, int32_t *fill,
-                                                    int32_t *colj, int32_t *pos) {
+// ---------------------------------------------------------------- view construction
+// per stored B entry: its column, its column's first C entry, the length of
+// the A column it selects, and the count of its row
+__global__ __launch_bounds__(kBlock) void k_bv_bent(Prob p, const int2 *__restrict__ E,
+                                                    int32_t *bcol, int32_t *cb, int32_t *len,
+                                                    int32_t *cnt) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= p.nnzb) return;
     const int j = column_of(p.bcp, p.n, t);
+    bcol[t] = j;
+    cb[t] = p.ccp[j];
+    len[t] = E[t].y;
+    atomicAdd(&cnt[p.bri[t]], 1);
+}
+
+// per stored A entry: its column and its offset in the column
+__global__ __launch_bounds__(kBlock) void k_bv_aent(Prob p, int2 *aview) {
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= p.nnza) return;
+    const int k = column_of(p.acp, p.k, q);
+    aview[q] = make_int2(k, q - p.acp[k]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bv_fill(Prob p, const int32_t *rowptr,
+                                                    const int32_t *bcol, int32_t *fill,
+                                                    int32_t *colj, int32_t *pos) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= p.nnzb) return;
     const int k = p.bri[t];
     const int slot = rowptr[k] + atomicAdd(&fill[k], 1);
-    colj[slot] = j;
+    colj[slot] = bcol[t];
     pos[slot] = t;
 }
 
 // each row's entries by ascending column (Shell sort with Ciura's gaps)
-__global__ __launch_bounds__(kBlock) void k_bt_sort(int nrows, const int32_t *rowptr,
+__global__ __launch_bounds__(kBlock) void k_bv_sort(int nrows, const int32_t *rowptr,
                                                     int32_t *colj, int32_t *pos) {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= nrows) return;
@@ -115,49 +168,76 @@ __global__ __launch_bounds__(kBlock) void k_bt_sort(int nrows, const int32_t *ro
     }
 }
 
+// the row view's per-entry values: (B entry, C column start) and first product
+__global__ __launch_bounds__(kBlock) void k_bv_pack(int nnzb, const int32_t *pos,
+                                                    const int32_t *cb, const long long *pofs,
+                                                    int2 *rv, long long *rvp) {
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nnzb) return;
+    const int t = pos[r];
+    rv[r] = make_int2(t, cb[t]);
+    rvp[r] = pofs[t];
+}
+
 // ---------------------------------------------------------------- launchers
-hipError_t launch_btranspose(const Prob &p, int32_t *rowptr, int32_t *fill, int32_t *colj,
-                             int32_t *pos, long long *scratch, int nscratch, hipStream_t s) {
+hipError_t launch_bw_view(const Prob &p, const int2 *E, const BwBuild &b, BwView &w,
+                          hipStream_t s) {
     const int nrows = p.k;  // rows of B
-    hipError_t e = hipMemsetAsync(rowptr, 0, sizeof(int32_t) * (size_t)(nrows + 1), s);
+    hipError_t e = hipMemsetAsync(b.rowptr, 0, sizeof(int32_t) * (size_t)(nrows + 1), s);
     if (e != hipSuccess) return e;
-    e = hipMemsetAsync(fill, 0, sizeof(int32_t) * (size_t)(nrows > 0 ? nrows : 1), s);
+    e = hipMemsetAsync(b.fill, 0, sizeof(int32_t) * (size_t)(nrows > 0 ? nrows : 1), s);
     if (e != hipSuccess) return e;
     const int gb = ceil_div(p.nnzb, kBlock);
-    if (gb > 0) hipLaunchKernelGGL(k_bt_count, dim3(gb), dim3(kBlock), 0, s, p, rowptr);
-    e = launch_scan_i32(rowptr, nrows + 1, scratch, nscratch, rowptr, s);
+    if (gb > 0)
+        hipLaunchKernelGGL(k_bv_bent, dim3(gb), dim3(kBlock), 0, s, p, E, b.bcol, b.cb, b.len,
+                           b.rowptr);
+    if (p.nnza > 0)
+        hipLaunchKernelGGL(k_bv_aent, dim3(ceil_div(p.nnza, kBlock)), dim3(kBlock), 0, s, p,
+                           b.aview);
+    e = launch_scan_i32(b.rowptr, nrows + 1, b.scratch, b.nscratch, b.rowptr, s);
     if (e != hipSuccess) return e;
-    if (gb > 0) hipLaunchKernelGGL(k_bt_fill, dim3(gb), dim3(kBlock), 0, s, p,
-                                   (const int32_t *)rowptr, fill, colj, pos);
+    e = launch_scan_i64(b.len, p.nnzb, b.scratch2, b.nscratch2, b.pofs, s);
+    if (e != hipSuccess) return e;
+    if (gb > 0)
+        hipLaunchKernelGGL(k_bv_fill, dim3(gb), dim3(kBlock), 0, s, p, (const int32_t *)b.rowptr,
+                           (const int32_t *)b.bcol, b.fill, b.colj, b.pos);
     if (nrows > 0)
-        hipLaunchKernelGGL(k_bt_sort, dim3(ceil_div(nrows, kBlock)), dim3(kBlock), 0, s, nrows,
-                           (const int32_t *)rowptr, colj, pos);
+        hipLaunchKernelGGL(k_bv_sort, dim3(ceil_div(nrows, kBlock)), dim3(kBlock), 0, s, nrows,
+                           (const int32_t *)b.rowptr, b.colj, b.pos);
+    if (gb > 0)
+        hipLaunchKernelGGL(k_bv_pack, dim3(gb), dim3(kBlock), 0, s, p.nnzb,
+                           (const int32_t *)b.pos, (const int32_t *)b.cb,
+                           (const long long *)b.pofs, b.rv, b.rvp);
+    w.E = E;
+    w.pofs = b.pofs;
+    w.cb = b.cb;
+    w.aview = b.aview;
+    w.rowptr = b.rowptr;
+    w.rv = b.rv;
+    w.rvp = b.rvp;
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const Prob &p, bool f64, const void *av, const void *bv,
-                           const int32_t *cri, const void *gv, void *da, void *db,
-                           const int32_t *rowptr, const int32_t *colj, const int32_t *pos,
-                           int *err, hipStream_t s) {
+hipError_t launch_backward(const Prob &p, const BwView &w, bool f64, const void *av,
+                           const void *bv, const void *gv, void *da, void *db, int *err,
+                           hipStream_t s) {
     if (db && p.nnzb > 0) {
         const int gb = ceil_div(p.nnzb, kBlock);
         if (f64)
-            hipLaunchKernelGGL(k_grad_b<double>, dim3(gb), dim3(kBlock), 0, s, p,
-                               (const double *)av, cri, (const double *)gv, (double *)db, err);
+            hipLaunchKernelGGL(k_grad_b<double>, dim3(gb), dim3(kBlock), 0, s, w, p.nnzb,
+                               (const double *)av, (const double *)gv, (double *)db, err);
         else
-            hipLaunchKernelGGL(k_grad_b<float>, dim3(gb), dim3(kBlock), 0, s, p,
-                               (const float *)av, cri, (const float *)gv, (float *)db, err);
+            hipLaunchKernelGGL(k_grad_b<float>, dim3(gb), dim3(kBlock), 0, s, w, p.nnzb,
+                               (const float *)av, (const float *)gv, (float *)db, err);
     }
     if (da && p.nnza > 0) {
         const int ga = ceil_div(p.nnza, kBlock);
         if (f64)
-            hipLaunchKernelGGL(k_grad_a<double>, dim3(ga), dim3(kBlock), 0, s, p,
-                               (const double *)bv, cri, (const double *)gv, (double *)da, rowptr,
-                               colj, pos, err);
+            hipLaunchKernelGGL(k_grad_a<double>, dim3(ga), dim3(kBlock), 0, s, w, p.nnza,
+                               (const double *)bv, (const double *)gv, (double *)da, err);
         else
-            hipLaunchKernelGGL(k_grad_a<float>, dim3(ga), dim3(kBlock), 0, s, p,
-                               (const float *)bv, cri, (const float *)gv, (float *)da, rowptr,
-                               colj, pos, err);
+            hipLaunchKernelGGL(k_grad_a<float>, dim3(ga), dim3(kBlock), 0, s, w, p.nnza,
+                               (const float *)bv, (const float *)gv, (float *)da, err);
     }
     return hipGetLastError();
 }

@@ -431,6 +431,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_down_i32(const int32_t *in, int
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_scan_down_i64(const int32_t *in, int n,
+                                                          const long long *__restrict__ bsum,
+                                                          long long *out) {
+    __shared__ long long s[kScanBlock];
+    ScanOut o;
+    block_scan_down(in, n, bsum, s, o);
+#pragma unroll
+    for (int u = 0; u < ScanOut::PER; ++u) {
+        const int i = blockIdx.x * kScanBlock + threadIdx.x * ScanOut::PER + u;
+        if (i < n) out[i] = o.pre[u];
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_scan_i32(const int32_t *in, int n, long long *bsum, int nbsum, int32_t *out,
                            hipStream_t s) {
@@ -439,6 +452,17 @@ hipError_t launch_scan_i32(const int32_t *in, int n, long long *bsum, int nbsum,
     if (nblk > nbsum) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kBlock), 0, s, in, n, bsum);
     hipLaunchKernelGGL(k_scan_down_i32, dim3(nblk), dim3(kBlock), 0, s, in, n,
+                       (const long long *)bsum, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_i64(const int32_t *in, int n, long long *bsum, int nbsum, long long *out,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nblk = ceil_div(n, kScanBlock);
+    if (nblk > nbsum) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kBlock), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_down_i64, dim3(nblk), dim3(kBlock), 0, s, in, n,
                        (const long long *)bsum, out);
     return hipGetLastError();
 }

@@ -801,15 +801,25 @@ spgemm_status spgemm_backward(spgemm_plan p, const void *A_val, const void *B_va
     q.av = A_val;
     q.bv = B_val;
     const bool f64 = p->dt == SPGEMM_F64;
-    // row view of B (rowptr, fill, colj, pos), scan scratch and an error word
-    const size_t k = (size_t)q.k, nb = (size_t)std::max(q.nnzb, 1);
+    // the backward view (per B entry, per A entry, row view of B), its
+    // construction temporaries, scan partials and an error word
+    const size_t k = (size_t)q.k, nb = (size_t)std::max(q.nnzb, 1),
+                 na = (size_t)std::max(q.nnza, 1);
     const int nbs = ceil_div((int)k + 1, kScanBlock) + 2;
-    const size_t o_fill = align_up(4 * (k + 1), 256);
-    const size_t o_colj = o_fill + align_up(4 * std::max<size_t>(k, 1), 256);
-    const size_t o_pos = o_colj + align_up(4 * nb, 256);
-    const size_t o_scr = o_pos + align_up(4 * nb, 256);
-    const size_t o_err = o_scr + align_up(8 * (size_t)nbs, 256);
-    const size_t need = o_err + 256;
+    const int nbs2 = ceil_div((int)nb, kScanBlock) + 2;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes, 256);
+        return o;
+    };
+    const size_t o_pofs = carve(8 * nb), o_cb = carve(4 * nb), o_aview = carve(8 * na),
+                 o_rowptr = carve(4 * (k + 1)), o_rv = carve(8 * nb), o_rvp = carve(8 * nb),
+                 o_fill = carve(4 * std::max<size_t>(k, 1)), o_colj = carve(4 * nb),
+                 o_pos = carve(4 * nb), o_bcol = carve(4 * nb), o_len = carve(4 * nb),
+                 o_scr = carve(8 * (size_t)nbs), o_scr2 = carve(8 * (size_t)nbs2),
+                 o_err = carve(sizeof(int));
+    const size_t need = off;
     if (need > p->bt_bytes) {
         if (p->bt) {
             (void)hipStreamSynchronize(p->last_stream);
@@ -822,23 +832,42 @@ spgemm_status spgemm_backward(spgemm_plan p, const void *A_val, const void *B_va
         p->bt_bytes = need;
     }
     char *b = (char *)p->bt;
-    int32_t *rowptr = (int32_t *)b;
-    int32_t *fill = (int32_t *)(b + o_fill);
-    int32_t *colj = (int32_t *)(b + o_colj);
-    int32_t *pos = (int32_t *)(b + o_pos);
-    long long *scr = (long long *)(b + o_scr);
+    BwBuild bb{};
+    bb.pofs = (long long *)(b + o_pofs);
+    bb.cb = (int32_t *)(b + o_cb);
+    bb.aview = (int2 *)(b + o_aview);
+    bb.rowptr = (int32_t *)(b + o_rowptr);
+    bb.rv = (int2 *)(b + o_rv);
+    bb.rvp = (long long *)(b + o_rvp);
+    bb.fill = (int32_t *)(b + o_fill);
+    bb.colj = (int32_t *)(b + o_colj);
+    bb.pos = (int32_t *)(b + o_pos);
+    bb.bcol = (int32_t *)(b + o_bcol);
+    bb.len = (int32_t *)(b + o_len);
+    bb.scratch = (long long *)(b + o_scr);
+    bb.nscratch = nbs;
+    bb.scratch2 = (long long *)(b + o_scr2);
+    bb.nscratch2 = nbs2;
     p->bt_err = (int *)(b + o_err);
     SPG_TRY(hipMemsetAsync(p->bt_err, 0, sizeof(int), s));
-    if (dA_val && !p->bt_ready) {
-        ProfScope ps("b_rowview", s);
-        SPG_TRY(launch_btranspose(q, rowptr, fill, colj, pos, scr, nbs, s));
+    BwView w{};
+    w.E = p->E;
+    w.dst = p->dst;
+    w.nnzc = p->totals_host[0];
+    w.pofs = bb.pofs;
+    w.cb = bb.cb;
+    w.aview = bb.aview;
+    w.rowptr = bb.rowptr;
+    w.rv = bb.rv;
+    w.rvp = bb.rvp;
+    if (!p->bt_ready) {
+        ProfScope ps("bw_view", s);
+        SPG_TRY(launch_bw_view(q, p->E, bb, w, s));
         p->bt_ready = true;
     }
-    int *err = p->bt_err;
     {
         ProfScope ps("gradients", s);
-        SPG_TRY(launch_backward(q, f64, A_val, B_val, C_rowidx, G_val, dA_val, dB_val, rowptr,
-                                colj, pos, err, s));
+        SPG_TRY(launch_backward(q, w, f64, A_val, B_val, G_val, dA_val, dB_val, p->bt_err, s));
     }
     p->last_stream = s;
     return SPGEMM_OK;
