@@ -7,6 +7,14 @@
 // that order, and sorts them with a bitonic network: exchanges at distance
 // below 64 move through DPP / ds_swizzle / ds_bpermute, distances 64..128
 // between the four registers a lane holds, and larger distances through LDS.
+// Before the network, the workgroup tries a bucket sort, which does far less
+// work when the rows are spread out: the span [lo, hi] of the column's rows is
+// cut into one bucket per thread by a monotone map, keys are counted and
+// scattered to their buckets in LDS, and every thread sorts its own bucket by
+// insertion. Buckets are in row order and every key is unique, so the result
+// is the same ascending order the network gives. If any bucket would exceed
+// kBucketCap keys (clustered or repeated rows), the column takes the network.
+//
 // Every run of equal rows is one output entry; its rank is the run index and
 // the position of a key inside its run is the occurrence index k of that
 // product. Every product gets the rank as its destination, marked for all but
@@ -114,15 +122,47 @@ __device__ __forceinline__ void block_sort(K (&key)[4], K *buf) {
     }
 }
 
+constexpr int kBucketCap = 24;  // most keys a bucket of the bucket sort takes
+
+// smallest and largest of lo / hi over the workgroup (red: 2 * NW ints);
+// ends with a barrier
+template <int NW>
+__device__ __forceinline__ void wg_minmax(int &lo, int &hi, int *red) {
+    lo = min(lo, shfl_xor_c<32>(lo));
+    hi = max(hi, shfl_xor_c<32>(hi));
+    lo = min(lo, shfl_xor_c<16>(lo));
+    hi = max(hi, shfl_xor_c<16>(hi));
+    lo = min(lo, shfl_xor_c<8>(lo));
+    hi = max(hi, shfl_xor_c<8>(hi));
+    lo = min(lo, shfl_xor_c<4>(lo));
+    hi = max(hi, shfl_xor_c<4>(hi));
+    lo = min(lo, shfl_xor_c<2>(lo));
+    hi = max(hi, shfl_xor_c<2>(hi));
+    lo = min(lo, shfl_xor_c<1>(lo));
+    hi = max(hi, shfl_xor_c<1>(hi));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w] = lo;
+        red[NW + w] = hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        lo = min(lo, red[i]);
+        hi = max(hi, red[NW + i]);
+    }
+}
+
 template <typename K, int T>
-__global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
+__global__ __launch_bounds__(T, 8) void k_bsort(KArgs a, int bin) {
     constexpr int N = 4 * T, NW = T / 64;
     constexpr int EB = 12;  // bits of the product position (N <= 4096)
     constexpr K KMAX = KeyMax<K>::v;
     static_assert(N <= (1 << EB), "positions must fit the key");
     __shared__ K buf[N];     // exchanges, then the sorted keys
-    __shared__ int rh[N];    // sorted position of every run head
+    __shared__ int rh[N];    // bucket counts and starts, then the sorted position of every run head
     __shared__ int wcnt[NW + 1];
+    __shared__ int red[2 * NW];
     __shared__ int s_kmax;
     if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
         return;  // every thread takes the same branch
@@ -138,16 +178,75 @@ __global__ __launch_bounds__(T) void k_bsort(KArgs a, int bin) {
             if (tid == 0) atomicOr(&a.hdr->err, ERR_GROUP);
             continue;
         }
-        K key[4];
+        int row[4];
+        int lo = 0x7fffffff, hi = -1;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int s = sb + r * 64 + lane;
-            key[r] = s < op ? (((K)a.prow[pbase + s] << EB) | (K)s) : KMAX;
+            row[r] = s < op ? a.prow[pbase + s] : -1;
+            if (row[r] >= 0) {
+                lo = min(lo, row[r]);
+                hi = max(hi, row[r]);
+            }
         }
-        block_sort<K, N>(key, buf);
+        rh[tid] = 0;
+        wg_minmax<NW>(lo, hi, red);  // its barrier also orders the zeroing
+        // bucket of a row: monotone in the row, so buckets are in row order
+        const float scale = (float)T / (float)(hi - lo + 1);
+        int bk[4], slot[4];
+        bool ovf = false;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) buf[sb + r * 64 + lane] = key[r];
-        __syncthreads();
+        for (int r = 0; r < 4; ++r) {
+            bk[r] = 0;
+            slot[r] = 0;
+            if (row[r] >= 0) {
+                bk[r] = min((int)((float)(row[r] - lo) * scale), T - 1);
+                slot[r] = atomicAdd(&rh[bk[r]], 1);
+                ovf |= slot[r] >= kBucketCap;
+            }
+        }
+        K key[4];
+        if (!__syncthreads_or(ovf)) {
+            const int cnt = rh[tid];
+            int tot;
+            const int st = wg_excl_scan<T>(cnt, wcnt, tot);
+            rh[tid] = st;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int s = sb + r * 64 + lane;
+                if (row[r] >= 0) buf[rh[bk[r]] + slot[r]] = ((K)row[r] << EB) | (K)s;
+            }
+            __syncthreads();
+            // insertion sort of this thread's bucket (keys are unique)
+            for (int i = st + 1; i < st + cnt; ++i) {
+                const K x = buf[i];
+                int j = i - 1;
+                K y = buf[j];
+                while (y > x) {
+                    buf[j + 1] = y;
+                    if (--j < st) break;
+                    y = buf[j];
+                }
+                buf[j + 1] = x;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int s = sb + r * 64 + lane;
+                key[r] = s < op ? buf[s] : KMAX;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int s = sb + r * 64 + lane;
+                key[r] = row[r] >= 0 ? (((K)row[r] << EB) | (K)s) : KMAX;
+            }
+            block_sort<K, N>(key, buf);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) buf[sb + r * 64 + lane] = key[r];
+            __syncthreads();
+        }
 
         // run heads and run indices (position order: wavefront, register, lane)
         bool head[4];
