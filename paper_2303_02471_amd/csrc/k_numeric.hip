@@ -170,7 +170,8 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
 }
 
 constexpr int kColWin = 256;  // columns per window of a tile
-constexpr int kNumPer = 8;    // products per thread per pass
+constexpr int kNumPer = 4;     // products per thread per pass, product-balanced tiles
+constexpr int kNumPerBig = 8;  // products per thread per pass, chunks of large columns
 
 template <typename V>
 struct NumSmem {
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int 
         S.s_bv[tid] = b;
         __syncthreads();
         const long long pb = pbase;
-        numeric_window<V, kNumPer>(
+        numeric_window<V, kNumPerBig>(
             a, pid, d, S.s_acp, S.s_eoff, S.s_col, S.s_bv, min(kBlock, b1 - bw), Ew,
             [&](int, int e) { return pb + e; },
             [&](int, int &o0, int &ol, long long &lb) {

@@ -328,6 +328,7 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a) {
     __shared__ int rh[N];    // sorted position of every run head
     __shared__ int emap[N];  // product position of every window position
     __shared__ int srow[kWinRows];  // the column's rows, when they fit
+    __shared__ int bfill[T];        // bucket fill counters of the bucket sort
     __shared__ int wcnt[NW + 1];
     __shared__ int scan_tmp[NW + 1];
     __shared__ int stk_lo[kWinDepth], stk_hi[kWinDepth];
@@ -399,12 +400,23 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a) {
             while (sp > 0) {
                 --sp;
                 const int x = stk_lo[sp], y = stk_hi[sp];
-                // the window's products, numbered in product order
+                // the window's products, numbered in product order, and their
+                // bucket counts (one bucket per thread over the window's rows)
+                const float scale = (float)T / (float)(y - x);
+                rh[tid] = 0;
+                bfill[tid] = 0;
+                __syncthreads();
                 int c = 0;
+                bool ovf = false;
                 for (int e = e0; e < e1; ++e) {
                     const int r = row_at(e);
-                    c += r >= x && r < y;
+                    if (r >= x && r < y) {
+                        ++c;
+                        const int b = min((int)((float)(r - x) * scale), T - 1);
+                        ovf |= atomicAdd(&rh[b], 1) >= kBucketCap;
+                    }
                 }
+                ovf = __syncthreads_or(ovf);
                 int cnt;
                 const int off = wg_excl_scan<T>(c, scan_tmp, cnt);
                 if (cnt > N && y - x > 1) {
@@ -443,8 +455,43 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a) {
                     __syncthreads();
                     continue;
                 }
-                // keys (row, window position) in LDS, then into registers
-                {
+                // keys (row, window position): scattered to their buckets and
+                // sorted there, or (a bucket too full) sorted by the network
+                K key[4];
+                if (!ovf) {
+                    const int bc = rh[tid];
+                    int bt;
+                    const int bst = wg_excl_scan<T>(bc, scan_tmp, bt);
+                    rh[tid] = bst;
+                    __syncthreads();
+                    int i = off;
+                    for (int e = e0; e < e1; ++e) {
+                        const int r = row_at(e);
+                        if (r < x || r >= y) continue;
+                        emap[i] = e;
+                        const int b = min((int)((float)(r - x) * scale), T - 1);
+                        buf[rh[b] + atomicAdd(&bfill[b], 1)] = ((K)r << EB) | (K)i;
+                        ++i;
+                    }
+                    __syncthreads();
+                    for (int u = bst + 1; u < bst + bc; ++u) {
+                        const K v = buf[u];
+                        int j = u - 1;
+                        K y2 = buf[j];
+                        while (y2 > v) {
+                            buf[j + 1] = y2;
+                            if (--j < bst) break;
+                            y2 = buf[j];
+                        }
+                        buf[j + 1] = v;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int s = sb + r * 64 + lane;
+                        key[r] = s < cnt ? buf[s] : KMAX;
+                    }
+                } else {
                     int i = off;
                     for (int e = e0; e < e1; ++e) {
                         const int r = row_at(e);
@@ -453,19 +500,18 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a) {
                         buf[i] = ((K)r << EB) | (K)i;
                         ++i;
                     }
-                }
-                __syncthreads();
-                K key[4];
+                    __syncthreads();
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int s = sb + r * 64 + lane;
-                    key[r] = s < cnt ? buf[s] : KMAX;
-                }
-                __syncthreads();
-                block_sort<K, N>(key, buf);
+                    for (int r = 0; r < 4; ++r) {
+                        const int s = sb + r * 64 + lane;
+                        key[r] = s < cnt ? buf[s] : KMAX;
+                    }
+                    __syncthreads();
+                    block_sort<K, N>(key, buf);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) buf[sb + r * 64 + lane] = key[r];
-                __syncthreads();
+                    for (int r = 0; r < 4; ++r) buf[sb + r * 64 + lane] = key[r];
+                    __syncthreads();
+                }
                 // run heads and run indices (position order: wavefront, register, lane)
                 bool head[4];
                 int run[4];

@@ -401,10 +401,14 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
         if ((e = launch_sort(a, c, p->wide_keys, n, side(p, 1, s)))) return e;
     }
     {
+        // stream of each ESC sub-bin (-1: the caller's), largest sub-bin first
+        static const int esc_stream[kEscBins] = {-1, -1, -1, -1, -1, -1, -1};
         ProfScope ps("esc_symbolic", s);
-        for (int i = kEscBins - 1; i >= 0; --i)
-            if ((e = launch_esc(a, p->wide_esc, i, ceil_div(h.bin_count[BIN_ESC0 + i], 64 >> i), s)))
+        for (int i = kEscBins - 1; i >= 0; --i) {
+            hipStream_t si = esc_stream[i] < 0 ? s : side(p, esc_stream[i], s);
+            if ((e = launch_esc(a, p->wide_esc, i, ceil_div(h.bin_count[BIN_ESC0 + i], 64 >> i), si)))
                 return e;
+        }
     }
     for (int c = 0; c < 2; ++c) {
         const int n = h.bin_count[BIN_SORT0 + c];
