@@ -85,8 +85,8 @@ def copy_calibration():
 
 
 # launch group -> kernel symbol (FP64 runs)
-KERNEL_SYMBOL = {"numeric": "k_numeric<double>", "numeric_big": "k_numeric_big<double>",
-                 "expand": "k_expand", "wsort_symbolic": "k_wsort<unsigned int>"}
+KERNEL_SYMBOL = {"numeric": "k_numeric<double>", "expand": "k_expand",
+                 "wsort_symbolic": "k_wsort<unsigned int>"}
 
 
 def _src_digest():
@@ -280,12 +280,8 @@ def main():
         num, sym = kernel_bytes(op, nb, nnzc, bins[name], vb)
         kbytes[f"{name}_numeric"] = num
         kbytes[f"{name}_symbolic"] = sym
-    # the tiles do the columns of at most t_split products, the chunked
-    # kernel the others
-    t_split = opts.t_split if opts.t_split else 2048
-    small = (op > 0) & (op <= t_split) if t_split > 0 else (op > 0)
-    kbytes["numeric"] = kernel_bytes(op, nb, nnzc, small, vb)[0]
-    kbytes["numeric_big"] = kernel_bytes(op, nb, nnzc, (op > 0) & ~small, vb)[0]
+    # one numeric launch does every column (tiles and chunks of large ones)
+    kbytes["numeric"] = kernel_bytes(op, nb, nnzc, op > 0, vb)[0]
     # expansion: (A column start, length) per stored B entry, A row read and
     # product row written per product
     kbytes["expand"] = 8 * B.nnz + 8 * int(op.sum())

@@ -202,14 +202,13 @@ hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk
 hipError_t launch_prod_offsets(const KArgs &a, long long *bsum, int nbsum, hipStream_t s);
 // row of every product (prow), one workgroup per product-balanced tile
 hipError_t launch_expand(const KArgs &a, hipStream_t s);
-// numeric phase: the columns of at most t_split products by product-balanced
-// tiles (one workgroup per tile), the larger ones (listed from bin-list
-// position `first`, `nbig` of them, with at most `maxchunks` chunks of
-// kChunkB stored B entries) by one workgroup per chunk; first products are
-// written to their output entries, later products staged
-hipError_t launch_numeric(const KArgs &a, bool f64, hipStream_t s);
-hipError_t launch_numeric_big(const KArgs &a, bool f64, int first, int nbig, int maxchunks,
-                              hipStream_t s);
+// numeric phase, one launch: the columns of at most t_split products by
+// product-balanced tiles (one workgroup per tile), the larger ones (listed
+// from bin-list position `first`, `nbig` of them, with at most `maxchunks`
+// chunks of kChunkB stored B entries) by one workgroup per chunk; first
+// products are written to their output entries, later products staged
+hipError_t launch_numeric(const KArgs &a, bool f64, int first, int nbig, int maxchunks,
+                          hipStream_t s);
 // adds the staged later products of occurrence index k (n of them listed)
 hipError_t launch_layer(const KArgs &a, bool f64, int k, long long n, hipStream_t s);
 // Backward view, built once per single-problem plan: per stored B entry its

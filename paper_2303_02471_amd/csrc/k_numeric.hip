@@ -171,7 +171,7 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
 
 constexpr int kColWin = 256;  // columns per window of a tile
 constexpr int kNumPer = 4;     // products per thread per pass, product-balanced tiles
-constexpr int kNumPerBig = 8;  // products per thread per pass, chunks of large columns
+constexpr int kNumPerBig = 6;  // products per thread per pass, chunks of large columns
 
 template <typename V>
 struct NumSmem {
@@ -189,14 +189,11 @@ struct NumSmem {
 };
 
 // One workgroup per product-balanced tile; columns with more than t_split
-// products are left to k_numeric_big (their products count zero here).
+// products are left to the chunk workgroups (their products count zero here).
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_numeric(KArgs a) {
-    __shared__ NumSmem<V> S;
-    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
-        return;  // every thread takes the same branch
+__device__ __forceinline__ void numeric_tile(const KArgs &a, NumSmem<V> &S, int tile) {
     const int tid = threadIdx.x;
-    const int g0 = a.tilestart[blockIdx.x], g1 = a.tilestart[blockIdx.x + 1];
+    const int g0 = a.tilestart[tile], g1 = a.tilestart[tile + 1];
     if (g0 >= g1) return;
     int bad = 0;
     for_each_segment(a, g0, g1, [&](int pid, const Prob &d, int js, int je) {
@@ -300,13 +297,11 @@ constexpr int kXcds = 8;
 static_assert(kChunkB % kBlock == 0, "a chunk is a whole number of B windows");
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int n) {
-    __shared__ BigSmem<V> S;
-    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
-        return;  // every thread takes the same branch
+__device__ __forceinline__ void numeric_chunk(const KArgs &a, BigSmem<V> &S, int first, int n,
+                                              int wg) {
     const int tid = threadIdx.x;
     const int ncol8 = ceil_div(n, kXcds);
-    const int xcd = (int)blockIdx.x % kXcds, r = (int)blockIdx.x / kXcds;
+    const int xcd = wg % kXcds, r = wg / kXcds;
     const int chunk = r / ncol8, col = (r % ncol8) * kXcds + xcd;
     if (col >= n) return;
     const int4 ent = a.binlist[first + col];
@@ -373,6 +368,26 @@ __global__ __launch_bounds__(kBlock) void k_numeric_big(KArgs a, int first, int 
     if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
 }
 
+template <typename V>
+union NumericSmem {
+    NumSmem<V> tile;
+    BigSmem<V> chunk;
+};
+
+// The numeric launch: workgroups [0, nchunkwg) take the chunks of the
+// columns above t_split (listed from bin-list position `first`, `nbig` of
+// them; nchunkwg is a multiple of 8 so the XCD numbering holds), the rest one
+// product-balanced tile each. One launch lets the two kinds share the chip
+// without a fork and join of streams.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_numeric(KArgs a, int first, int nbig, int nchunkwg) {
+    __shared__ NumericSmem<V> S;
+    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
+        return;  // every thread takes the same branch
+    if ((int)blockIdx.x < nchunkwg) numeric_chunk<V>(a, S.chunk, first, nbig, (int)blockIdx.x);
+    else numeric_tile<V>(a, S.tile, (int)blockIdx.x - nchunkwg);
+}
+
 // later products of occurrence index k, added to their (already written)
 // output entries; every entry has at most one product of each index
 template <typename V>
@@ -388,21 +403,18 @@ __global__ __launch_bounds__(kBlock) void k_layer(KArgs a, int k, long long n) {
     }
 }
 
-hipError_t launch_numeric(const KArgs &a, bool f64, hipStream_t s) {
-    if (a.nptiles <= 0) return hipSuccess;
-    if (f64) hipLaunchKernelGGL((k_numeric<double>), dim3(a.nptiles), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_numeric<float>), dim3(a.nptiles), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_numeric_big(const KArgs &a, bool f64, int first, int nbig, int maxchunks,
-                              hipStream_t s) {
-    if (nbig <= 0 || maxchunks <= 0) return hipSuccess;
-    const long long nwg = (long long)kXcds * ceil_div(nbig, kXcds) * maxchunks;
+hipError_t launch_numeric(const KArgs &a, bool f64, int first, int nbig, int maxchunks,
+                          hipStream_t s) {
+    const long long nchunk =
+        (nbig > 0 && maxchunks > 0) ? (long long)kXcds * ceil_div(nbig, kXcds) * maxchunks : 0;
+    const long long nwg = nchunk + (a.nptiles > 0 ? a.nptiles : 0);
+    if (nwg <= 0) return hipSuccess;
     if (nwg > 0x7fffffffll) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nwg);
-    if (f64) hipLaunchKernelGGL((k_numeric_big<double>), grid, dim3(kBlock), 0, s, a, first, nbig);
-    else hipLaunchKernelGGL((k_numeric_big<float>), grid, dim3(kBlock), 0, s, a, first, nbig);
+    if (f64)
+        hipLaunchKernelGGL((k_numeric<double>), grid, dim3(kBlock), 0, s, a, first, nbig, (int)nchunk);
+    else
+        hipLaunchKernelGGL((k_numeric<float>), grid, dim3(kBlock), 0, s, a, first, nbig, (int)nchunk);
     return hipGetLastError();
 }
 

@@ -342,19 +342,23 @@ hipStream_t side(spgemm_plan p, int i, hipStream_t s) {
     return (p->flags & SPGEMM_ONE_STREAM) ? s : p->side[i];
 }
 
-hipError_t fork(spgemm_plan p, hipStream_t s) {
-    if (p->flags & SPGEMM_ONE_STREAM) return hipSuccess;
+// the side streams in `used` (bit i: side stream i) wait for the caller's
+// stream, and later the caller's stream for them
+hipError_t fork(spgemm_plan p, hipStream_t s, unsigned used) {
+    if ((p->flags & SPGEMM_ONE_STREAM) || !used) return hipSuccess;
     hipError_t e;
     if ((e = hipEventRecord(p->fork_ev, s))) return e;
     for (int i = 0; i < spgemm_plan_s::kSide; ++i)
-        if ((e = hipStreamWaitEvent(p->side[i], p->fork_ev, 0))) return e;
+        if ((used >> i) & 1u)
+            if ((e = hipStreamWaitEvent(p->side[i], p->fork_ev, 0))) return e;
     return hipSuccess;
 }
 
-hipError_t join(spgemm_plan p, hipStream_t s) {
-    if (p->flags & SPGEMM_ONE_STREAM) return hipSuccess;
+hipError_t join(spgemm_plan p, hipStream_t s, unsigned used) {
+    if ((p->flags & SPGEMM_ONE_STREAM) || !used) return hipSuccess;
     hipError_t e;
     for (int i = 0; i < spgemm_plan_s::kSide; ++i) {
+        if (!((used >> i) & 1u)) continue;
         if ((e = hipEventRecord(p->join_ev[i], p->side[i]))) return e;
         if ((e = hipStreamWaitEvent(s, p->join_ev[i], 0))) return e;
     }
@@ -376,7 +380,17 @@ int bin_start(const Hdr &h, int b) {
 hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream_t s) {
     const Hdr &h = p->hdr_host;
     hipError_t e;
-    if ((e = fork(p, s))) return e;
+    // stream of each ESC sub-bin (-1: the caller's), largest sub-bin first
+    static const int esc_stream[kEscBins] = {-1, -1, -1, -1, -1, -1, -1};
+    unsigned used = 0;
+    for (int c = 0; c < kBlkBins; ++c)
+        if (h.bin_count[BIN_BLK0 + c]) used |= c == kBlkBins - 1 ? 4u : 1u;
+    if (h.bin_count[BIN_WSORT]) used |= 4u;
+    for (int c = 2; c < kSortBins; ++c)
+        if (h.bin_count[BIN_SORT0 + c]) used |= 2u;
+    for (int i = 0; i < kEscBins; ++i)
+        if (h.bin_count[BIN_ESC0 + i] && esc_stream[i] >= 0) used |= 1u << esc_stream[i];
+    if ((e = fork(p, s, used))) return e;
     static const char *bnames[kBlkBins] = {"block512_symbolic", "block1k_symbolic",
                                            "block2k_symbolic", "block4k_symbolic",
                                            "block_xl_symbolic"};
@@ -401,8 +415,6 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
         if ((e = launch_sort(a, c, p->wide_keys, n, side(p, 1, s)))) return e;
     }
     {
-        // stream of each ESC sub-bin (-1: the caller's), largest sub-bin first
-        static const int esc_stream[kEscBins] = {-1, -1, -1, -1, -1, -1, -1};
         ProfScope ps("esc_symbolic", s);
         for (int i = kEscBins - 1; i >= 0; --i) {
             hipStream_t si = esc_stream[i] < 0 ? s : side(p, esc_stream[i], s);
@@ -416,12 +428,11 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
         ProfScope ps(snames[c], s);
         if ((e = launch_sort(a, c, p->wide_keys, n, s))) return e;
     }
-    return join(p, s);
+    return join(p, s, used);
 }
 
-// Numeric: one launch over the tiles and one over the chunks of the columns
-// above t_split (concurrently), then one small launch per occurrence index of
-// the later products.
+// Numeric: one launch over the tiles and the chunks of the columns above
+// t_split, then one small launch per occurrence index of the later products.
 hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
     const bool f64 = p->dt == SPGEMM_F64;
     const Hdr &h = p->hdr_host;
@@ -441,16 +452,10 @@ hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
     const int first = bin_start(h, fb);
     int n = 0;
     for (int b = fb; b < NBINS; ++b) n += h.bin_count[b];
-    if ((e = fork(p, s))) return e;
-    if (n > 0 && h.big_chunks > 0) {
-        ProfScope ps("numeric_big", side(p, 0, s));
-        if ((e = launch_numeric_big(a, f64, first, n, h.big_chunks, side(p, 0, s)))) return e;
-    }
     {
         ProfScope ps("numeric", s);
-        if ((e = launch_numeric(a, f64, s))) return e;
+        if ((e = launch_numeric(a, f64, first, n, h.big_chunks, s))) return e;
     }
-    if ((e = join(p, s))) return e;
     if (p->later_total == 0) return hipSuccess;
     ProfScope ps("later_layers", s);
     for (int k = 1; k <= h.later_maxk; ++k)
