@@ -316,7 +316,6 @@ __global__ __launch_bounds__(T, 8) void k_bsort(KArgs a, int bin) {
 // products: one entry) needs no sort, its products take their occurrence
 // indices in product order.
 constexpr int kWinDepth = 48;
-constexpr int kWinRows = 12288;  // rows of a column staged in LDS (larger columns re-read)
 
 template <typename K>
 __global__ __launch_bounds__(1024) void k_wsort(KArgs a) {
@@ -327,7 +326,6 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a) {
     __shared__ K buf[N];     // keys, exchanges, then the sorted keys
     __shared__ int rh[N];    // sorted position of every run head
     __shared__ int emap[N];  // product position of every window position
-    __shared__ int srow[kWinRows];  // the column's rows, when they fit
     __shared__ int bfill[T];        // bucket fill counters of the bucket sort
     __shared__ int wcnt[NW + 1];
     __shared__ int scan_tmp[NW + 1];
@@ -348,9 +346,8 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a) {
         const long long pbase = a.colprod[g];
         const int *__restrict__ prow = a.prow + pbase;
         uint32_t *__restrict__ dstp = a.dst + pbase;
-        // the column's rows, staged in LDS when they fit (coalesced loads, four
-        // in flight per thread); every window pass then reads them there
-        const bool staged = op <= kWinRows;
+        // row span of the column (the window passes re-read the rows, which
+        // stay in L2)
         if (tid == 0) {
             s_min = 0x7fffffff;
             s_max = -1;
@@ -365,11 +362,9 @@ __global__ __launch_bounds__(1024) void k_wsort(KArgs a) {
                 if (r[u] < 0) continue;
                 mn = min(mn, r[u]);
                 mx = max(mx, r[u]);
-                if (staged) srow[e + u * T] = r[u];
             }
         }
-        // (separate paths keep the LDS reads as LDS instructions)
-        auto row_at = [&](int e) { return staged ? srow[e] : prow[e]; };
+        auto row_at = [&](int e) { return prow[e]; };
         __syncthreads();
         {
 #pragma unroll
