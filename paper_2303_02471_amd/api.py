@@ -112,8 +112,13 @@ def _code(dtype: torch.dtype) -> int:
     raise TypeError(f"unsupported value type {dtype}")
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream(stream) -> Optional[int]:
     if stream is None:
+        if _raw_stream is not None:  # the current stream's handle without a Stream object
+            return _raw_stream(torch.cuda.current_device()) or None
         stream = torch.cuda.current_stream()
     return stream.cuda_stream or None
 

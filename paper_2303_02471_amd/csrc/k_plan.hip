@@ -401,6 +401,13 @@ __global__ __launch_bounds__(kBlock) void k_prod_down(KArgs a, const long long *
     const int n = a.ncols;
     ScanOut o;
     block_scan_down(a.op, n, bsum, s, o);
+    // a launch planned from an earlier call's sizes may run before the tally
+    // has compared them: products beyond the product space carved for that
+    // call stop the expansion here
+    if (a.spec_total >= 0 && o.block_end > a.spec_total) {
+        if (threadIdx.x == 0) atomicOr(&a.hdr->err, ERR_RETRY);
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < ScanOut::PER; ++u) {
         const int g = blockIdx.x * kScanBlock + threadIdx.x * ScanOut::PER + u;

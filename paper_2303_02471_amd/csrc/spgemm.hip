@@ -521,11 +521,18 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         a.spec_mask = spec ? mask : 0u;
         return a;
     };
+    // A planned launch runs the tally and the placement (needed only by the
+    // accumulators) on a side stream while the product offsets and the
+    // expansion run on the caller's; the offsets kernel stops the expansion if
+    // the products outgrow the planned product space.
+    const bool overlap = spec && p->ncols > 0 && !(p->flags & SPGEMM_ONE_STREAM);
     {
         const KArgs a = args();
         { ProfScope ps("classify", s); SPG_TRY(launch_classify(a, s)); }
-        { ProfScope ps("tally", s); SPG_TRY(launch_tally(a, s)); }
-        { ProfScope ps("place", s); SPG_TRY(launch_place(a, s)); }
+        if (overlap) SPG_TRY(fork(p, s, 1u));
+        hipStream_t sp = overlap ? p->side[0] : s;
+        { ProfScope ps("tally", sp); SPG_TRY(launch_tally(a, sp)); }
+        { ProfScope ps("place", sp); SPG_TRY(launch_place(a, sp)); }
     }
     if (!spec) {
         // the bin sizes fix the grids and the product count the allocation
@@ -545,6 +552,7 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
             SPG_TRY(launch_prod_offsets(al, p->bsum, p->nbsum, s));
         }
         { ProfScope ps("expand", s); SPG_TRY(launch_expand(al, s)); }
+        if (overlap) SPG_TRY(join(p, s, 1u));
         SPG_TRY(launch_symbolic_accumulators(p, al, s));
         ProfScope ps("scan", s);
         SPG_TRY(launch_scan(al, p->gcp, p->bsum, p->nblk, p->totals, s));
