@@ -41,11 +41,8 @@ __device__ __forceinline__ V g_at(const V *__restrict__ gv, long long nnzc, int 
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_grad_b(BwView w, int nnzb, const V *__restrict__ av,
-                                                   const V *__restrict__ gv, V *__restrict__ db,
-                                                   int *err) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= nnzb) return;
+__device__ __forceinline__ void grad_b(const BwView &w, int t, const V *__restrict__ av,
+                                       const V *__restrict__ gv, V *__restrict__ db, int *err) {
     const int2 e = w.E[t];  // A column start and length of the entry's row of B
     const long long base = w.pofs[t];
     const int cb = w.cb[t];
@@ -72,11 +69,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_b(BwView w, int nnzb, const V *
 }
 
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_grad_a(BwView w, int nnza, const V *__restrict__ bv,
-                                                   const V *__restrict__ gv, V *__restrict__ da,
-                                                   int *err) {
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= nnza) return;
+__device__ __forceinline__ void grad_a(const BwView &w, int q, const V *__restrict__ bv,
+                                       const V *__restrict__ gv, V *__restrict__ da, int *err) {
     const int2 ku = w.aview[q];  // column of A (= row of B) and offset in that column
     const int r0 = w.rowptr[ku.x], r1 = w.rowptr[ku.x + 1];
     V acc = V(0);
@@ -108,6 +102,23 @@ __global__ __launch_bounds__(kBlock) void k_grad_a(BwView w, int nnza, const V *
     }
     da[q] = acc;
     if (bad) atomicOr(err, ERR_CSC);
+}
+
+// Both gradients in one launch: workgroups [0, nbw) take dB (one thread per
+// stored B entry), the rest dA (one thread per stored A entry).
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_grad(BwView w, int nnza, int nnzb, int nbw,
+                                                 const V *__restrict__ av,
+                                                 const V *__restrict__ bv,
+                                                 const V *__restrict__ gv, V *__restrict__ da,
+                                                 V *__restrict__ db, int *err) {
+    if ((int)blockIdx.x < nbw) {
+        const int t = blockIdx.x * kBlock + threadIdx.x;
+        if (t < nnzb) grad_b<V>(w, t, av, gv, db, err);
+    } else {
+        const int q = (blockIdx.x - nbw) * kBlock + threadIdx.x;
+        if (q < nnza) grad_a<V>(w, q, bv, gv, da, err);
+    }
 }
 
 // ---------------------------------------------------------------- view construction
@@ -221,24 +232,17 @@ hipError_t launch_bw_view(const Prob &p, const int2 *E, const BwBuild &b, BwView
 hipError_t launch_backward(const Prob &p, const BwView &w, bool f64, const void *av,
                            const void *bv, const void *gv, void *da, void *db, int *err,
                            hipStream_t s) {
-    if (db && p.nnzb > 0) {
-        const int gb = ceil_div(p.nnzb, kBlock);
-        if (f64)
-            hipLaunchKernelGGL(k_grad_b<double>, dim3(gb), dim3(kBlock), 0, s, w, p.nnzb,
-                               (const double *)av, (const double *)gv, (double *)db, err);
-        else
-            hipLaunchKernelGGL(k_grad_b<float>, dim3(gb), dim3(kBlock), 0, s, w, p.nnzb,
-                               (const float *)av, (const float *)gv, (float *)db, err);
-    }
-    if (da && p.nnza > 0) {
-        const int ga = ceil_div(p.nnza, kBlock);
-        if (f64)
-            hipLaunchKernelGGL(k_grad_a<double>, dim3(ga), dim3(kBlock), 0, s, w, p.nnza,
-                               (const double *)bv, (const double *)gv, (double *)da, err);
-        else
-            hipLaunchKernelGGL(k_grad_a<float>, dim3(ga), dim3(kBlock), 0, s, w, p.nnza,
-                               (const float *)bv, (const float *)gv, (float *)da, err);
-    }
+    const int nbw = (db && p.nnzb > 0) ? ceil_div(p.nnzb, kBlock) : 0;
+    const int naw = (da && p.nnza > 0) ? ceil_div(p.nnza, kBlock) : 0;
+    if (nbw + naw == 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(k_grad<double>, dim3(nbw + naw), dim3(kBlock), 0, s, w, p.nnza, p.nnzb,
+                           nbw, (const double *)av, (const double *)bv, (const double *)gv,
+                           (double *)da, (double *)db, err);
+    else
+        hipLaunchKernelGGL(k_grad<float>, dim3(nbw + naw), dim3(kBlock), 0, s, w, p.nnza, p.nnzb,
+                           nbw, (const float *)av, (const float *)bv, (const float *)gv,
+                           (float *)da, (float *)db, err);
     return hipGetLastError();
 }
 
