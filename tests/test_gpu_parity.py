@@ -295,3 +295,35 @@ def test_planned_launch_and_retry():
         assert_same_structure(colptr.cpu().numpy(), ri.cpu().numpy(), ocp, ori, "planned")
         assert_values_exact(v.cpu().numpy(), ov, "planned")
     plan.close()
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(t_esc=8), dict(t_block=300), dict(t_split=300)])
+def test_wide_rows(opts):
+    """More than 2^24 - 1 rows: the sort bins and the wavefront sort-merge use
+    64-bit keys. Columns reach every accumulator (up to about 11,000 products),
+    rows spread over the whole range with some at its top and one row shared
+    by many A columns (later products)."""
+    from paper_2303_02471_amd import api
+    _say(f"wide rows m=2^24+1000 {opts}")
+    rng = np.random.default_rng(19)
+    m = (1 << 24) + 1000
+    acols = []
+    for kk in range(3000):
+        ln = int(rng.choice([1, 2, 3, 5, 8, 40]))
+        rows = rng.choice(m - 1, size=ln, replace=False)
+        if kk % 3 == 0:
+            rows[0] = m - 1 - int(rng.integers(0, 64))  # near the top of the range
+        if kk % 10 == 0:
+            rows = np.concatenate([rows[rows != m - 1], [m - 1]])  # one shared row
+        rng.shuffle(rows)
+        acols.append(np.unique(rows) if kk % 7 == 0 else rows)
+    A = _csc_from_columns(m, acols, rng)
+    degs = [1, 2, 4, 8, 16, 32, 64, 120, 400, 900, 1500, 3000]
+    B = _csc_from_columns(3000, [rng.choice(3000, size=d, replace=False) for d in degs * 2], rng)
+    ocp, ori, ov = oracle.spgemm(A, B)
+    (cp, ri, v), plan, _ = gpu_product(A, B, api.options(**opts), return_plan=True)
+    assert_same_structure(cp, ri, ocp, ori, f"wide {opts}")
+    assert_values_exact(v, ov, f"wide {opts}")
+    st = plan.stats()
+    plan.close()
+    assert st["later_max"] >= 1
