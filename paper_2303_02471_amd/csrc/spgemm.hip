@@ -380,14 +380,16 @@ int bin_start(const Hdr &h, int b) {
 hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream_t s) {
     const Hdr &h = p->hdr_host;
     hipError_t e;
-    // stream of each ESC sub-bin (-1: the caller's), largest sub-bin first
+    // stream of each ESC sub-bin and sort class (-1: the caller's, after the
+    // ESC sub-bins; sorts on side streams start first, largest class first)
     static const int esc_stream[kEscBins] = {-1, -1, -1, -1, -1, -1, -1};
+    static const int sort_stream[kSortBins] = {-1, -1, 1, 1};
     unsigned used = 0;
     for (int c = 0; c < kBlkBins; ++c)
         if (h.bin_count[BIN_BLK0 + c]) used |= c == kBlkBins - 1 ? 4u : 1u;
     if (h.bin_count[BIN_WSORT]) used |= 4u;
-    for (int c = 2; c < kSortBins; ++c)
-        if (h.bin_count[BIN_SORT0 + c]) used |= 2u;
+    for (int c = 0; c < kSortBins; ++c)
+        if (h.bin_count[BIN_SORT0 + c] && sort_stream[c] >= 0) used |= 1u << sort_stream[c];
     for (int i = 0; i < kEscBins; ++i)
         if (h.bin_count[BIN_ESC0 + i] && esc_stream[i] >= 0) used |= 1u << esc_stream[i];
     if ((e = fork(p, s, used))) return e;
@@ -408,11 +410,12 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
     }
     static const char *snames[kSortBins] = {"sort512_symbolic", "sort1k_symbolic",
                                             "sort2k_symbolic", "sort4k_symbolic"};
-    for (int c = kSortBins - 1; c >= 2; --c) {
+    for (int c = kSortBins - 1; c >= 0; --c) {
         const int n = h.bin_count[BIN_SORT0 + c];
-        if (!n) continue;
-        ProfScope ps(snames[c], side(p, 1, s));
-        if ((e = launch_sort(a, c, p->wide_keys, n, side(p, 1, s)))) return e;
+        if (!n || sort_stream[c] < 0) continue;
+        hipStream_t sc = side(p, sort_stream[c], s);
+        ProfScope ps(snames[c], sc);
+        if ((e = launch_sort(a, c, p->wide_keys, n, sc))) return e;
     }
     {
         ProfScope ps("esc_symbolic", s);
@@ -422,9 +425,9 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
                 return e;
         }
     }
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < kSortBins; ++c) {
         const int n = h.bin_count[BIN_SORT0 + c];
-        if (!n) continue;
+        if (!n || sort_stream[c] >= 0) continue;
         ProfScope ps(snames[c], s);
         if ((e = launch_sort(a, c, p->wide_keys, n, s))) return e;
     }
