@@ -235,8 +235,9 @@ def main():
     log(f"plan: {stats}")
 
     def step():
-        api.symbolic(At, Bt, torch.float64, opts, plan=plan, out_colptr=colptr)
-        api.numeric(plan, At.val, Bt.val, rowidx, val)
+        # one library call: symbolic, then numeric queued behind it on the
+        # output arrays of the first call (their capacity is nnz(C))
+        api.multiply(At, Bt, opts, plan=plan, out=(colptr, rowidx, val))
 
     for _ in range(args.warmup):
         step()
@@ -320,14 +321,20 @@ def main():
         times = []
         for r in range(args.cpu_runs):
             c0 = time.perf_counter()
-            oracle.spgemm(A, B)
+            ref = oracle.spgemm(A, B)
             times.append(time.perf_counter() - c0)
             log(f"oracle run {r}: {times[-1]:.2f}s")
+        # the timed steps' output against the oracle's, bit for bit
+        torch.cuda.synchronize()
+        got = (colptr.cpu().numpy(), rowidx[:nnz].cpu().numpy(), val[:nnz].cpu().numpy())
+        same = all(np.array_equal(g, o) for g, o in zip(got, ref))
+        log(f"output of the timed steps equals the oracle's: {same}")
         tmed = statistics.median(times)
         cpu = {"value": round(2.0 * total_op / tmed / 1e9, 5), "unit": "GFLOP/s", "cores": 1,
                "kind": "oracle",
                "sample": f"full workload (symbolic + numeric), median of {args.cpu_runs} "
-                         f"single-thread runs, {tmed:.2f} s each"}
+                         f"single-thread runs, {tmed:.2f} s each",
+               "output_equals_oracle": bool(same)}
 
     # ------------------------------------------------------------ side measurements
     extras = {}

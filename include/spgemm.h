@@ -64,7 +64,8 @@ typedef enum {
     SPGEMM_ERR_HIP = 7,            /* a HIP runtime call failed */
     SPGEMM_ERR_PLAN = 8,           /* plan missing, of the wrong kind, or not in the needed state */
     SPGEMM_ERR_INVALID = 9,        /* invalid option value or argument combination */
-    SPGEMM_ERR_NOT_TUNED = 10      /* no tuning cache entry for the workload (lookup only) */
+    SPGEMM_ERR_NOT_TUNED = 10,     /* no tuning cache entry for the workload (lookup only) */
+    SPGEMM_ERR_CAPACITY = 11       /* spgemm_multiply: the C arrays hold fewer than nnz(C) entries */
 } spgemm_status;
 
 typedef enum { SPGEMM_F32 = 0, SPGEMM_F64 = 1 } spgemm_dtype;
@@ -168,6 +169,31 @@ spgemm_status spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, spgemm_d
  */
 spgemm_status spgemm_numeric(spgemm_plan plan, const void *A_val, const void *B_val,
                              int32_t *C_rowidx, void *C_val, void *stream);
+
+/*
+ * Both phases in one call, for callers that can offer C arrays of some
+ * capacity (typically the previous call's nnz(C) on fixed patterns): the
+ * symbolic phase of spgemm_symbolic (Sections 2.1 and 3.1: Op count, binning,
+ * distinct rows per column, scan) followed by the numeric phase of
+ * spgemm_numeric, same results bit for bit. When the plan has run before, the
+ * numeric phase is queued on the stream right behind the symbolic one, from
+ * the previous call's sizes, and the call waits only for the read-back of
+ * nnz(C); if the sizes read back differ, the numeric phase is queued again
+ * with the right ones (it overwrites every output entry).
+ *   A, B        as spgemm_symbolic, with their value arrays (device, dtype).
+ *   C_colptr    device array [B.ncols + 1], filled.
+ *   C_rowidx, C_val  device arrays of `capacity` entries (int32, dtype),
+ *               caller-allocated; may be NULL when capacity is 0.
+ *   nnzC_host   receives nnz(C).
+ * Returns SPGEMM_ERR_CAPACITY when nnz(C) > capacity: nothing is written to
+ * C_rowidx / C_val, nnzC_host and C_colptr are set and the plan is ready for
+ * spgemm_numeric with larger arrays. Blocks until nnz(C) is known; the numeric
+ * phase is stream-ordered after the return. Single problems only.
+ */
+spgemm_status spgemm_multiply(const spgemm_csc *A, const spgemm_csc *B, spgemm_dtype dt,
+                              const spgemm_options *opt, void *stream,
+                              spgemm_plan *plan_inout, int32_t *C_colptr, int32_t *C_rowidx,
+                              void *C_val, int64_t capacity, int64_t *nnzC_host);
 
 /*
  * Gradients of a loss L with dL/dC = G (given on C's stored entries) with

@@ -19,12 +19,13 @@ STATUS = {
     0: "SPGEMM_OK", 1: "SPGEMM_ERR_NULL", 2: "SPGEMM_ERR_SHAPE", 3: "SPGEMM_ERR_CSC",
     4: "SPGEMM_ERR_DTYPE", 5: "SPGEMM_ERR_INDEX_OVERFLOW", 6: "SPGEMM_ERR_NO_MEMORY",
     7: "SPGEMM_ERR_HIP", 8: "SPGEMM_ERR_PLAN", 9: "SPGEMM_ERR_INVALID",
-    10: "SPGEMM_ERR_NOT_TUNED",
+    10: "SPGEMM_ERR_NOT_TUNED", 11: "SPGEMM_ERR_CAPACITY",
 }
+SPGEMM_ERR_CAPACITY = 11
 
 # every symbol include/spgemm.h declares
 EXPORTS = (
-    "spgemm_symbolic", "spgemm_numeric", "spgemm_backward", "spgemm_batched",
+    "spgemm_symbolic", "spgemm_numeric", "spgemm_multiply", "spgemm_backward", "spgemm_batched",
     "spgemm_plan_get_stats", "spgemm_plan_destroy", "spgemm_status_string", "spgemm_version",
     "spgemm_profile_enable", "spgemm_profile_read", "spgemm_profile_select",
     "spgemm_autotune", "spgemm_tune_key", "spgemm_tune_cache_load", "spgemm_tune_cache_store",
@@ -88,6 +89,8 @@ def lib() -> C.CDLL:
     L.spgemm_symbolic.argtypes = [C.POINTER(Csc), C.POINTER(Csc), C.c_int, C.POINTER(Options), vp,
                                   C.POINTER(vp), vp, i64p]
     L.spgemm_numeric.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.spgemm_multiply.argtypes = [C.POINTER(Csc), C.POINTER(Csc), C.c_int, C.POINTER(Options), vp,
+                                  C.POINTER(vp), vp, vp, vp, C.c_int64, i64p]
     L.spgemm_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.spgemm_batched.argtypes = [i32, C.POINTER(Csc), C.POINTER(Csc), C.c_int, C.POINTER(Options),
                                  vp, C.POINTER(vp), C.POINTER(vp), i64p, C.POINTER(vp),
@@ -107,7 +110,8 @@ def lib() -> C.CDLL:
                                   C.c_char_p, i32]
     L.spgemm_tune_cache_load.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(Options)]
     L.spgemm_tune_cache_store.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(Options), C.c_double]
-    for name in ("spgemm_symbolic", "spgemm_numeric", "spgemm_backward", "spgemm_batched",
+    for name in ("spgemm_symbolic", "spgemm_numeric", "spgemm_multiply", "spgemm_backward",
+                 "spgemm_batched",
                  "spgemm_plan_get_stats", "spgemm_profile_enable", "spgemm_profile_read",
                  "spgemm_autotune", "spgemm_tune_key", "spgemm_tune_cache_load",
                  "spgemm_tune_cache_store"):

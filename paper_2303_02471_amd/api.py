@@ -156,6 +156,9 @@ def symbolic(A: CscTensor, B: CscTensor, dtype=torch.float64, opts=None,
     Passing the previous plan (and its colptr as out_colptr) reuses the
     plan's device workspace: nothing is allocated on repeated calls."""
     plan = plan or Plan()
+    if out_colptr is not None and (out_colptr.numel() != B.ncols + 1 or
+                                   out_colptr.dtype != torch.int32):
+        raise ValueError("out_colptr must be int32 with B.ncols + 1 entries")
     colptr = out_colptr if out_colptr is not None else torch.empty(
         B.ncols + 1, dtype=torch.int32, device=A.colptr.device)
     nnz = C.c_int64(0)
@@ -180,6 +183,52 @@ def numeric(plan: Plan, A_val: torch.Tensor, B_val: torch.Tensor, C_rowidx: torc
     st = _lib.lib().spgemm_numeric(plan.handle, _ptr(A_val), _ptr(B_val), _ptr(C_rowidx),
                                    _ptr(C_val), _stream(stream))
     _lib.check(st, "spgemm_numeric")
+
+
+def multiply(A: CscTensor, B: CscTensor, opts=None, plan: Optional[Plan] = None, out=None,
+             stream=None):
+    """C = A x B in one library call (symbolic, then numeric queued behind it).
+
+    ``out`` = (colptr, rowidx, val) to reuse: rowidx / val of any capacity
+    (typically the previous nnz(C)); when nnz(C) exceeds it, larger arrays are
+    allocated and the numeric phase runs on them. Returns
+    (plan, colptr, rowidx, val, nnz); rowidx / val hold C's entries in [:nnz]."""
+    if A.val is None or B.val is None:
+        raise ValueError("values required")
+    dtype = A.val.dtype
+    if B.val.dtype != dtype:
+        raise TypeError("A and B values must have the same dtype")
+    plan = plan or Plan()
+    dev = A.colptr.device
+    if out is not None:
+        colptr, rowidx, val = out
+        if colptr.numel() != B.ncols + 1:  # another shape: the pointers need their own array
+            colptr = torch.empty(B.ncols + 1, dtype=torch.int32, device=dev)
+    else:
+        colptr = torch.empty(B.ncols + 1, dtype=torch.int32, device=dev)
+        rowidx = torch.empty(0, dtype=torch.int32, device=dev)
+        val = torch.empty(0, dtype=dtype, device=dev)
+    if val.dtype != dtype or rowidx.dtype != torch.int32 or colptr.dtype != torch.int32:
+        raise TypeError("output arrays must be int32 pointers and rows, values of A's dtype")
+    cap = min(rowidx.numel(), val.numel())
+    nnz = C.c_int64(0)
+    da, db = _desc(A, True), _desc(B, True)
+    st = _lib.lib().spgemm_multiply(C.byref(da), C.byref(db), _code(dtype),
+                                    C.byref(opts) if opts is not None else None, _stream(stream),
+                                    C.byref(plan.handle), _ptr(colptr), _ptr(rowidx), _ptr(val),
+                                    cap, C.byref(nnz))
+    if st != _lib.SPGEMM_ERR_CAPACITY:
+        _lib.check(st, "spgemm_multiply")
+    plan.keep = [A.colptr, A.rowidx, B.colptr, B.rowidx, colptr]
+    plan.dtype = dtype
+    plan.nnz = int(nnz.value)
+    plan.shape = (A.nrows, B.ncols)
+    plan.colptr = colptr
+    if st == _lib.SPGEMM_ERR_CAPACITY:
+        rowidx = torch.empty(plan.nnz, dtype=torch.int32, device=dev)
+        val = torch.empty(plan.nnz, dtype=dtype, device=dev)
+        numeric(plan, A.val, B.val, rowidx, val, stream)
+    return plan, colptr, rowidx, val, plan.nnz
 
 
 def matmul(A: CscTensor, B: CscTensor, opts=None, return_plan: bool = False):

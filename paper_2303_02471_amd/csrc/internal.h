@@ -81,7 +81,7 @@ struct Hdr {
     int32_t err;
     int32_t later_maxk;                // largest occurrence index k of any product
     int32_t big_chunks;                // most kChunkB-entry chunks of a column above t_split
-    int32_t pad;
+    int32_t cap_over;                  // nnz(C) exceeds the output capacity of a one-call product
     unsigned long long total_op;
 };
 
@@ -152,6 +152,7 @@ struct KArgs {
     int32_t *lr;            // [products] index of every later product in its column
     const long long *gcp;   // [ncols + 1] entries of C before every global column (nprob > 1)
     long long later_n;      // length of the compact list (numeric phase)
+    long long out_cap;      // entries the caller's C arrays hold (single problem; else no limit)
     int32_t *lo;            // [later_n] output position
     int32_t *lpid;          // [later_n] problem
     int32_t *lkc;           // [later_n] occurrence index k

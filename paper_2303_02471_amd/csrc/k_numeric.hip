@@ -382,7 +382,8 @@ union NumericSmem {
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a, int first, int nbig, int nchunkwg) {
     __shared__ NumericSmem<V> S;
-    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
+    if (__syncthreads_or((__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) |
+                          __atomic_load_n(&a.hdr->cap_over, __ATOMIC_RELAXED)) != 0))
         return;  // every thread takes the same branch
     if ((int)blockIdx.x < nchunkwg) numeric_chunk<V>(a, S.chunk, first, nbig, (int)blockIdx.x);
     else numeric_tile<V>(a, S.tile, (int)blockIdx.x - nchunkwg);
@@ -392,13 +393,20 @@ __global__ __launch_bounds__(kBlock) void k_numeric(KArgs a, int first, int nbig
 // output entries; every entry has at most one product of each index
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_layer(KArgs a, int k, long long n) {
+    // a layer queued behind a phase that stood down finds the list of an
+    // earlier call: it stands down too, and never writes outside C
+    if ((__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) |
+         __atomic_load_n(&a.hdr->cap_over, __ATOMIC_RELAXED)) != 0)
+        return;
     const V *__restrict__ lv = (const V *)a.lv;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (long long)gridDim.x * kBlock) {
         if (a.lkc[i] != k) continue;
-        const Prob d = get_prob(a, a.lpid[i]);
-        V *cv = (V *)d.cv;
+        const int pid = a.lpid[i];
         const int o = a.lo[i];
+        if (pid < 0 || pid >= a.nprob || o < 0 || (long long)o >= a.out_cap) continue;
+        const Prob d = get_prob(a, pid);
+        V *cv = (V *)d.cv;
         cv[o] = cv[o] + lv[i];
     }
 }

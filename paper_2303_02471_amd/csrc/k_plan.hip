@@ -365,6 +365,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(KArgs a, long long *__rest
             if (total > 0x7fffffffll) err = ERR_NNZOVF;
             a.single.ccp[n] = (int32_t)total;
             totals[0] = total;
+            // a numeric phase queued behind this scan must not write past the
+            // caller's arrays
+            if (total > a.out_cap) a.hdr->cap_over = 1;
         } else {
             gcp[n] = total;
         }

@@ -82,6 +82,7 @@ struct spgemm_plan_s {
     static constexpr int kSide = 3;
     hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[kSide] = {nullptr, nullptr, nullptr};
+    hipEvent_t sym_ev = nullptr;  // header read-back of a one-call product
 
     // backward: row view of B
     void *bt = nullptr;
@@ -298,6 +299,7 @@ KArgs make_args(spgemm_plan p) {
     a.lr = p->lr;
     a.gcp = p->gcp;
     a.later_n = p->later_total;
+    a.out_cap = 0x7fffffffffffffffll;
     a.lkc = p->lkc;
     a.lo = p->lo;
     a.lpid = p->lpid;
@@ -333,6 +335,7 @@ hipError_t ensure_side_streams(spgemm_plan p) {
         if ((e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking))) return e;
         if ((e = hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming))) return e;
     }
+    if ((e = hipEventCreateWithFlags(&p->sym_ev, hipEventDisableTiming))) return e;
     return hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
 }
 
@@ -436,10 +439,20 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
 
 // Numeric: one launch over the tiles and the chunks of the columns above
 // t_split, then one small launch per occurrence index of the later products.
-hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
-    const bool f64 = p->dt == SPGEMM_F64;
+// The sizes a numeric launch is planned from (the plan's header and later
+// count): a numeric phase queued before they are read back is valid when
+// they come back unchanged.
+struct NumLaunch {
+    int first = 0, nbig = 0, big_chunks = 0, later_maxk = 0, nptiles = 0;
+    long long later_total = 0;
+    bool operator==(const NumLaunch &o) const {
+        return first == o.first && nbig == o.nbig && big_chunks == o.big_chunks &&
+               later_maxk == o.later_maxk && nptiles == o.nptiles && later_total == o.later_total;
+    }
+};
+
+NumLaunch numeric_launch(spgemm_plan p) {
     const Hdr &h = p->hdr_host;
-    hipError_t e;
     // columns above t_split: the bins from the first one whose largest
     // product count exceeds t_split on (bin-list order)
     int fb = BIN_ESC0;
@@ -452,17 +465,28 @@ hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
         if (bmax > p->tune.t_split) break;
         ++fb;
     }
-    const int first = bin_start(h, fb);
-    int n = 0;
-    for (int b = fb; b < NBINS; ++b) n += h.bin_count[b];
+    NumLaunch L;
+    L.first = bin_start(h, fb);
+    for (int b = fb; b < NBINS; ++b) L.nbig += h.bin_count[b];
+    L.big_chunks = h.big_chunks;
+    L.later_maxk = h.later_maxk;
+    L.later_total = p->later_total;
+    L.nptiles = p->nptiles;
+    return L;
+}
+
+hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
+    const bool f64 = p->dt == SPGEMM_F64;
+    const NumLaunch L = numeric_launch(p);
+    hipError_t e;
     {
         ProfScope ps("numeric", s);
-        if ((e = launch_numeric(a, f64, first, n, h.big_chunks, s))) return e;
+        if ((e = launch_numeric(a, f64, L.first, L.nbig, L.big_chunks, s))) return e;
     }
-    if (p->later_total == 0) return hipSuccess;
+    if (L.later_total == 0) return hipSuccess;
     ProfScope ps("later_layers", s);
-    for (int k = 1; k <= h.later_maxk; ++k)
-        if ((e = launch_layer(a, f64, k, p->later_total, s))) return e;
+    for (int k = 1; k <= L.later_maxk; ++k)
+        if ((e = launch_layer(a, f64, k, L.later_total, s))) return e;
     return hipSuccess;
 }
 
@@ -495,8 +519,19 @@ spgemm_status ensure_products(spgemm_plan p, unsigned long long total) {
 // the host. A planned pass (spec) launches everything from the sizes of the
 // plan's previous call with no read-back in between; when the device finds
 // other sizes it does no product-space work and *retry is set.
+// Outputs of a one-call product (spgemm_multiply): in a planned pass the
+// numeric phase is queued right behind the symbolic one, from the previous
+// call's sizes, and the host waits only for the header read-back.
+struct FusedOut {
+    int32_t *cri;
+    void *cv;
+    long long cap;
+    bool queued;   // a numeric phase was queued in this call's planned pass
+    NumLaunch used;
+};
+
 spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4> &tiles_host,
-                            bool spec, bool *retry) {
+                            bool spec, bool *retry, FusedOut *fo) {
     *retry = false;
     spgemm_status st = ensure_workspace(p);
     if (st) return st;
@@ -522,6 +557,7 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         KArgs a = make_args(p);
         a.spec_total = spec ? p->prod_total : -1;
         a.spec_mask = spec ? mask : 0u;
+        if (spec && fo) a.out_cap = fo->cap;
         return a;
     };
     // A planned launch runs the tally and the placement (needed only by the
@@ -562,7 +598,22 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
     }
     SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, kHdrBytes + 8 * (size_t)p->nprob,
                            hipMemcpyDeviceToHost, s));
-    SPG_TRY(hipStreamSynchronize(s));
+    if (fo && spec && p->ncols > 0 && p->nprob == 1) {
+        // the numeric phase from the previous sizes; it stands down on an
+        // error or capacity flag raised above, and is redone by the caller if
+        // the sizes read back differ
+        SPG_TRY(hipEventRecord(p->sym_ev, s));
+        p->probs[0].cri = fo->cri;
+        p->probs[0].cv = fo->cv;
+        KArgs an = make_args(p);
+        an.out_cap = fo->cap;
+        fo->used = numeric_launch(p);
+        fo->queued = true;
+        SPG_TRY(launch_numeric_phase(p, an, s));
+        SPG_TRY(hipEventSynchronize(p->sym_ev));
+    } else {
+        SPG_TRY(hipStreamSynchronize(s));
+    }
     std::memcpy(&p->hdr_host, p->pinned, sizeof(Hdr));
     int err = p->hdr_host.err;
     if (err & ERR_CSC) return SPGEMM_ERR_CSC;
@@ -587,6 +638,7 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
     const size_t o_v = o_k + align_up(4 * NL, 256);
     const size_t sneed = o_v + vsz * NL;
     if (sneed > p->stage_bytes) {
+        if (fo && fo->queued) (void)hipStreamSynchronize(s);  // the queued phase uses it
         if (p->stage) (void)hipFree(p->stage);
         p->stage = nullptr;
         p->stage_bytes = 0;
@@ -610,17 +662,24 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
 
 // Symbolic phase: a planned pass when the plan has run before, the pass with
 // the mid read-back when it has not or when the sizes changed.
-spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4> &tiles_host) {
+spgemm_status run_symbolic(spgemm_plan p, hipStream_t s, const std::vector<int4> &tiles_host,
+                           FusedOut *fo) {
     bool retry = false;
     if (p->spec_ready && !(p->flags & SPGEMM_NO_PLANNED_LAUNCH)) {
-        const spgemm_status st = symbolic_pass(p, s, tiles_host, true, &retry);
+        const spgemm_status st = symbolic_pass(p, s, tiles_host, true, &retry, fo);
         if (st || !retry) {
             if (st) p->spec_ready = false;
             return st;
         }
     }
     p->spec_ready = false;
-    return symbolic_pass(p, s, tiles_host, false, &retry);
+    if (fo && fo->queued) {
+        // the queued numeric phase stood down; let it drain before the redo
+        // may reallocate what it reads
+        SPG_TRY(hipStreamSynchronize(s));
+        fo->queued = false;
+    }
+    return symbolic_pass(p, s, tiles_host, false, &retry, fo);
 }
 
 spgemm_status run_numeric(spgemm_plan p, hipStream_t s) {
@@ -652,6 +711,7 @@ const char *spgemm_status_string(spgemm_status s) {
         case SPGEMM_ERR_PLAN: return "invalid plan";
         case SPGEMM_ERR_INVALID: return "invalid argument";
         case SPGEMM_ERR_NOT_TUNED: return "no tuning cache entry for the workload";
+        case SPGEMM_ERR_CAPACITY: return "C arrays smaller than nnz(C)";
     }
     return "unknown status";
 }
@@ -661,7 +721,7 @@ int32_t spgemm_version(void) { return kVersion; }
 static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const spgemm_csc *B,
                                      spgemm_dtype dt, const spgemm_options *opt, void *stream,
                                      spgemm_plan *plan_inout, int32_t *const *C_colptr,
-                                     int64_t *nnzC_host, bool batched) {
+                                     int64_t *nnzC_host, bool batched, FusedOut *fo = nullptr) {
     if (!plan_inout || !A || !B || !C_colptr || !nnzC_host) return SPGEMM_ERR_NULL;
     if (dt != SPGEMM_F32 && dt != SPGEMM_F64) return SPGEMM_ERR_DTYPE;
     if (count < 0) return SPGEMM_ERR_INVALID;
@@ -727,7 +787,7 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
         if (fresh) spgemm_plan_destroy(p);
         return hip_status(e);
     }
-    st = run_symbolic(p, s, tiles);
+    st = run_symbolic(p, s, tiles, fo);
     p->last_stream = s;
     if (st) {
         if (fresh) spgemm_plan_destroy(p);
@@ -761,6 +821,42 @@ spgemm_status spgemm_numeric(spgemm_plan p, const void *A_val, const void *B_val
     q.cv = C_val;
     if (nnzc == 0) return SPGEMM_OK;
     return run_numeric(p, (hipStream_t)stream);
+}
+
+spgemm_status spgemm_multiply(const spgemm_csc *A, const spgemm_csc *B, spgemm_dtype dt,
+                              const spgemm_options *opt, void *stream, spgemm_plan *plan_inout,
+                              int32_t *C_colptr, int32_t *C_rowidx, void *C_val, int64_t capacity,
+                              int64_t *nnzC_host) {
+    if (!A || !B || !C_colptr || !nnzC_host || !plan_inout) return SPGEMM_ERR_NULL;
+    if (capacity < 0) return SPGEMM_ERR_INVALID;
+    if ((A->nnz > 0 && !A->val) || (B->nnz > 0 && !B->val)) return SPGEMM_ERR_NULL;
+    if (capacity > 0 && (!C_rowidx || !C_val)) return SPGEMM_ERR_NULL;
+    hipStream_t s = (hipStream_t)stream;
+    FusedOut fo{C_rowidx, C_val, (long long)capacity, false, NumLaunch{}};
+    int32_t *cps[1] = {C_colptr};
+    spgemm_status st = symbolic_common(1, A, B, dt, opt, stream, plan_inout, cps, nnzC_host, false,
+                                       &fo);
+    if (st) return st;
+    spgemm_plan p = *plan_inout;
+    const long long nnzc = p->totals_host.empty() ? 0 : p->totals_host[0];
+    if (nnzc > capacity) {
+        // the queued numeric phase stood down; clear its flag for later calls
+        if (fo.queued) SPG_TRY(hipMemsetAsync(&p->hdr->cap_over, 0, sizeof(int32_t), s));
+        return SPGEMM_ERR_CAPACITY;
+    }
+    Prob &q = p->probs[0];
+    q.av = A->val;
+    q.bv = B->val;
+    q.cri = C_rowidx;
+    q.cv = C_val;
+    if (nnzc == 0) return SPGEMM_OK;
+    if (fo.queued) {
+        if (fo.used == numeric_launch(p)) return SPGEMM_OK;  // already queued, valid
+        // queued from other sizes: its bounds checks may have raised the group
+        // flag, which would make the phase below stand down; clear it first
+        SPG_TRY(hipMemsetAsync(&p->hdr->err, 0, sizeof(int32_t), s));
+    }
+    return run_numeric(p, s);
 }
 
 spgemm_status spgemm_batched(int32_t count, const spgemm_csc *A_host, const spgemm_csc *B_host,
@@ -975,6 +1071,7 @@ void spgemm_plan_destroy(spgemm_plan p) {
         if (p->join_ev[i]) (void)hipEventDestroy(p->join_ev[i]);
     }
     if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+    if (p->sym_ev) (void)hipEventDestroy(p->sym_ev);
     if (p->prod) (void)hipFree(p->prod);
     if (p->stage) (void)hipFree(p->stage);
     if (p->ws) (void)hipFree(p->ws);

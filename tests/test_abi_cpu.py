@@ -45,10 +45,11 @@ def test_every_declared_symbol_exported(L):
 
 def test_status_strings_and_version(L):
     assert L.spgemm_version() == 10000
-    for code in range(10):
+    for code in range(12):
         s = L.spgemm_status_string(code)
         assert isinstance(s, bytes) and len(s) > 0
     assert L.spgemm_status_string(0) == b"ok"
+    assert L.spgemm_status_string(11) != b"unknown status"
     assert L.spgemm_status_string(99) == b"unknown status"
 
 
@@ -61,6 +62,14 @@ def test_null_and_invalid_arguments_rejected_on_host(L):
     assert L.spgemm_symbolic(None, None, 1, None, None, None, None, None) == 1
     assert L.spgemm_symbolic(C.byref(a), C.byref(a), 1, None, None, C.byref(plan), None,
                              C.byref(nnz)) == 1
+    # one-call product: NULL outputs, negative capacity, NULL rows with capacity
+    dummy = C.c_void_p(1)
+    assert L.spgemm_multiply(C.byref(a), C.byref(a), 1, None, None, C.byref(plan), None, None,
+                             None, 0, C.byref(nnz)) == 1
+    assert L.spgemm_multiply(C.byref(a), C.byref(a), 1, None, None, C.byref(plan), dummy, None,
+                             None, -1, C.byref(nnz)) == 9
+    assert L.spgemm_multiply(C.byref(a), C.byref(a), 1, None, None, C.byref(plan), dummy, None,
+                             None, 5, C.byref(nnz)) == 1
     # numeric / backward / stats on a NULL plan
     assert L.spgemm_numeric(None, None, None, None, None, None) == 8
     assert L.spgemm_backward(None, None, None, None, None, None, None, None) == 8

@@ -327,3 +327,53 @@ def test_wide_rows(opts):
     st = plan.stats()
     plan.close()
     assert st["later_max"] >= 1
+
+
+def test_multiply_one_call():
+    """spgemm_multiply: the numeric phase queued behind a planned symbolic one
+    from the previous sizes, redone when the sizes read back differ (another
+    product count, the same count over other bins, the same bins with other
+    output counts so other later-product counts); C arrays too small give the
+    capacity status and leave the plan ready. Every result equals the oracle's."""
+    import torch
+    from paper_2303_02471_amd import api
+    _say("one-call multiply: queued numeric, redo, capacity")
+    rng = np.random.default_rng(23)
+    A = gen.uniform_z(1000, 10, seed=9)
+    B1 = _csc_from_columns(1000, [rng.choice(1000, 10, replace=False) for _ in range(2)], rng)
+    B2 = _csc_from_columns(1000, [rng.choice(1000, 19, replace=False),
+                                  rng.choice(1000, 1, replace=False)], rng)
+    B4 = _csc_from_columns(1000, [rng.choice(1000, 10, replace=False) for _ in range(2)], rng)
+    B3 = gen.uniform_z(1000, 6, seed=8, nrows=1000)
+    At = api.CscTensor.from_host(A)
+    plan, out = None, None
+    seq = [B1, B1, B4, B2, B3, B3, B1]
+    for step, B in enumerate(seq):
+        Bt = api.CscTensor.from_host(B)
+        if step == 5:
+            # new values on the same pattern, through the queued numeric phase
+            At.val.mul_(-0.5)
+            A = gen.CSC(A.nrows, A.ncols, A.colptr, A.rowidx, A.val * -0.5)
+        plan, colptr, ri, v, nnz = api.multiply(At, Bt, None, plan=plan, out=out)
+        torch.cuda.synchronize()
+        ocp, ori, ov = oracle.spgemm(A, B)
+        assert nnz == int(ocp[-1])
+        assert_same_structure(colptr.cpu().numpy(), ri[:nnz].cpu().numpy(), ocp, ori, f"step {step}")
+        assert_values_exact(v[:nnz].cpu().numpy(), ov, f"step {step}")
+        out = (colptr, ri, v)
+    # arrays one entry short: capacity status, the binding allocates and the
+    # numeric phase fills the new arrays; the next call runs normally again
+    Bt = api.CscTensor.from_host(B1)
+    plan, colptr, ri, v, nnz = api.multiply(At, Bt, None, plan=plan, out=out)
+    short = (colptr, ri[:nnz - 1].clone(), v[:nnz - 1].clone())
+    plan, colptr, ri2, v2, nnz2 = api.multiply(At, Bt, None, plan=plan, out=short)
+    assert ri2.numel() == nnz2 == nnz
+    ocp, ori, ov = oracle.spgemm(A, B1)
+    assert_same_structure(colptr.cpu().numpy(), ri2.cpu().numpy(), ocp, ori, "capacity")
+    assert_values_exact(v2.cpu().numpy(), ov, "capacity")
+    plan, colptr, ri3, v3, nnz3 = api.multiply(At, Bt, None, plan=plan, out=(colptr, ri2, v2))
+    torch.cuda.synchronize()
+    assert_values_exact(v3[:nnz3].cpu().numpy(), ov, "after capacity")
+    st = plan.stats()
+    plan.close()
+    assert st["later_max"] >= 1
