@@ -212,6 +212,9 @@ hipError_t launch_numeric(const KArgs &a, bool f64, int first, int nbig, int max
                           hipStream_t s);
 // adds the staged later products of occurrence index k (n of them listed)
 hipError_t launch_layer(const KArgs &a, bool f64, int k, long long n, hipStream_t s);
+// adds every staged later product in one launch; needs later lists in sorted
+// key order (no hash-accumulator columns)
+hipError_t launch_later_runs(const KArgs &a, bool f64, long long n, hipStream_t s);
 // Backward view, built once per single-problem plan: per stored B entry its
 // first product (pofs) and its column's first C entry (cb); per stored A entry
 // (column, offset in the column); a row view of B (rowptr over B's rows,

@@ -411,6 +411,30 @@ __global__ __launch_bounds__(kBlock) void k_layer(KArgs a, int k, long long n) {
     }
 }
 
+// All later products in one launch, for later lists in sorted-key order (every
+// accumulator but the hash one): the later products of one output entry are
+// consecutive there, in occurrence order, so the thread at the head of each
+// such run adds the run in order (the same sums as one launch per k).
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_later_runs(KArgs a, long long n) {
+    if ((__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) |
+         __atomic_load_n(&a.hdr->cap_over, __ATOMIC_RELAXED)) != 0)
+        return;
+    const V *__restrict__ lv = (const V *)a.lv;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const int pid = a.lpid[i];
+        const int o = a.lo[i];
+        if (i > 0 && a.lo[i - 1] == o && a.lpid[i - 1] == pid) continue;  // inside a run
+        if (pid < 0 || pid >= a.nprob || o < 0 || (long long)o >= a.out_cap) continue;
+        const Prob d = get_prob(a, pid);
+        V *cv = (V *)d.cv;
+        V acc = cv[o];
+        for (long long j = i; j < n && a.lo[j] == o && a.lpid[j] == pid; ++j) acc = acc + lv[j];
+        cv[o] = acc;
+    }
+}
+
 hipError_t launch_numeric(const KArgs &a, bool f64, int first, int nbig, int maxchunks,
                           hipStream_t s) {
     const long long nchunk =
@@ -423,6 +447,15 @@ hipError_t launch_numeric(const KArgs &a, bool f64, int first, int nbig, int max
         hipLaunchKernelGGL((k_numeric<double>), grid, dim3(kBlock), 0, s, a, first, nbig, (int)nchunk);
     else
         hipLaunchKernelGGL((k_numeric<float>), grid, dim3(kBlock), 0, s, a, first, nbig, (int)nchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_later_runs(const KArgs &a, bool f64, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const long long want = (n + kBlock - 1) / kBlock;
+    const int grid = (int)std::min<long long>(want, 8192);
+    if (f64) hipLaunchKernelGGL((k_later_runs<double>), dim3(grid), dim3(kBlock), 0, s, a, n);
+    else hipLaunchKernelGGL((k_later_runs<float>), dim3(grid), dim3(kBlock), 0, s, a, n);
     return hipGetLastError();
 }
 

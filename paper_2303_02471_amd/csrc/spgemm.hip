@@ -485,6 +485,11 @@ hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
     }
     if (L.later_total == 0) return hipSuccess;
     ProfScope ps("later_layers", s);
+    // the hash accumulator numbers its later products in settling order; the
+    // others in sorted-key order, where one launch adds them all
+    bool hashed = false;
+    for (int c = 0; c < kBlkBins; ++c) hashed |= p->hdr_host.bin_count[BIN_BLK0 + c] > 0;
+    if (!hashed) return launch_later_runs(a, f64, L.later_total, s);
     for (int k = 1; k <= L.later_maxk; ++k)
         if ((e = launch_layer(a, f64, k, L.later_total, s))) return e;
     return hipSuccess;
