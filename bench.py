@@ -390,9 +390,23 @@ def fwd_bwd(api, gen, np, torch, n=100_000, z=8, reps=20):
         return (time.perf_counter() - t0) * 1e3 / reps
 
     tf, tfb = timeit(fwd), timeit(fb)
-    log(f"fwd {tf:.3f} ms, fwd+bwd {tfb:.3f} ms")
+    # the same step captured once in a HIP graph and replayed (fixed pattern,
+    # the values read from the captured arrays at every replay)
+    api.backward(plan, At.val, Bt.val, Cm.rowidx, G, out=(dA, dB))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(g, stream=cs):
+            fwd()
+            api.backward(plan, At.val, Bt.val, Cm.rowidx, G, out=(dA, dB))
+    torch.cuda.current_stream().wait_stream(cs)
+    tg = timeit(g.replay)
+    log(f"fwd {tf:.3f} ms, fwd+bwd {tfb:.3f} ms, fwd+bwd graph replay {tg:.3f} ms")
     return {"workload": f"n={n}, {z} per column, FP32", "fwd_ms": round(tf, 4),
-            "fwd_bwd_ms": round(tfb, 4), "fwd_bwd_over_fwd": round(tfb / tf, 3)}
+            "fwd_bwd_ms": round(tfb, 4), "fwd_bwd_over_fwd": round(tfb / tf, 3),
+            "fwd_bwd_graph_ms": round(tg, 4), "fwd_bwd_graph_over_fwd": round(tg / tf, 3)}
 
 
 def batched(api, gen, np, torch, count, reps=5, tune=True):

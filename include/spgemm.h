@@ -208,7 +208,9 @@ spgemm_status spgemm_multiply(const spgemm_csc *A, const spgemm_csc *B, spgemm_d
  * result equals the sequential sums bit for bit. Single-problem plans only.
  * The first call builds and caches a view of the two patterns inside the plan
  * (per stored entry: its first product and C column start; a row view of B)
- * and may allocate; later calls on the plan are stream-ordered and do not.
+ * and may allocate; later calls on the plan are stream-ordered, allocate
+ * nothing and queue only kernels (they may be captured in a HIP graph together
+ * with spgemm_numeric on the same plan).
  */
 spgemm_status spgemm_backward(spgemm_plan plan, const void *A_val, const void *B_val,
                               const int32_t *C_rowidx, const void *G_val,

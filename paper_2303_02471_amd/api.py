@@ -247,10 +247,15 @@ def matmul(A: CscTensor, B: CscTensor, opts=None, return_plan: bool = False):
 
 
 def backward(plan: Plan, A_val: torch.Tensor, B_val: torch.Tensor, C_rowidx: torch.Tensor,
-             G_val: torch.Tensor, need_a: bool = True, need_b: bool = True, stream=None):
-    """(dA, dB) of <G, A x B> with respect to the stored values (patterns fixed)."""
-    dA = torch.empty_like(A_val) if need_a else None
-    dB = torch.empty_like(B_val) if need_b else None
+             G_val: torch.Tensor, need_a: bool = True, need_b: bool = True, stream=None,
+             out=None):
+    """(dA, dB) of <G, A x B> with respect to the stored values (patterns fixed).
+    ``out`` = (dA, dB) arrays to fill (either may be None to skip it)."""
+    if out is not None:
+        dA, dB = out
+    else:
+        dA = torch.empty_like(A_val) if need_a else None
+        dB = torch.empty_like(B_val) if need_b else None
     st = _lib.lib().spgemm_backward(plan.handle, _ptr(A_val), _ptr(B_val), _ptr(C_rowidx),
                                     _ptr(G_val), _ptr(dA), _ptr(dB), _stream(stream))
     _lib.check(st, "spgemm_backward")

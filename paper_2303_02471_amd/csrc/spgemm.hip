@@ -970,7 +970,6 @@ spgemm_status spgemm_backward(spgemm_plan p, const void *A_val, const void *B_va
     bb.scratch2 = (long long *)(b + o_scr2);
     bb.nscratch2 = nbs2;
     p->bt_err = (int *)(b + o_err);
-    SPG_TRY(hipMemsetAsync(p->bt_err, 0, sizeof(int), s));
     BwView w{};
     w.E = p->E;
     w.dst = p->dst;
@@ -982,6 +981,9 @@ spgemm_status spgemm_backward(spgemm_plan p, const void *A_val, const void *B_va
     w.rv = bb.rv;
     w.rvp = bb.rvp;
     if (!p->bt_ready) {
+        // the error word is cleared with the view only: later calls queue no
+        // memset, so they can be captured in a HIP graph
+        SPG_TRY(hipMemsetAsync(p->bt_err, 0, sizeof(int), s));
         ProfScope ps("bw_view", s);
         SPG_TRY(launch_bw_view(q, p->E, bb, w, s));
         p->bt_ready = true;
