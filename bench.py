@@ -56,6 +56,10 @@ def parse():
                     help="library defaults instead of autotuned thresholds")
     ap.add_argument("--one-stream", action="store_true",
                     help="library option: no overlap of accumulator kinds (per-kernel timings)")
+    ap.add_argument("--lane-sweep", action="store_true",
+                    help="only the lane-per-column hash accumulator against the wavefront "
+                         "sort-merge on constant-Z inputs (Z in 2,4,5,6,8,10; n 2560 and "
+                         "262144); prints one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--tune-cache", default=None,
@@ -68,6 +72,59 @@ def parse():
     ap.add_argument("--traffic-kernel", default="numeric",
                     help="launch group whose traffic --record-traffic records")
     return ap.parse_args()
+
+
+def lane_sweep(reps=20):
+    """C = A x B with every column of A and B holding exactly Z rows (Op = Z^2
+    per column), the synthetic law of the paper's crossover study, at its size
+    (n = 2560) and at one that fills the GPU (n = 262144). For each, the light
+    columns go once to the wavefront sort-merge and once to the lane-per-column
+    hash accumulator (one stream, so the accumulator's own time is seen):
+    symbolic + numeric per call and the accumulator's event-timed share."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2303_02471_amd import api, inputs as gen
+    rows = []
+    for n in (2560, 262144):
+        for z in (2, 4, 5, 6, 8, 10):
+            A = gen.uniform_z(n, z, seed=41)
+            B = gen.uniform_z(n, z, seed=42)
+            At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
+            row = {"n": n, "z": z, "op_per_column": z * z}
+            ref = None
+            for kind, lane in (("esc", False), ("lane", True)):
+                opts = api.options(one_stream=True, lane_hash=lane)
+                plan, colptr, ri, v, nnz = api.multiply(At, Bt, opts)
+                out = (colptr, ri, v)
+                for _ in range(3):
+                    api.multiply(At, Bt, opts, plan=plan, out=out)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    api.multiply(At, Bt, opts, plan=plan, out=out)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / reps
+                api.profile_select(None)
+                api.profile_enable(True)
+                for _ in range(3):
+                    api.multiply(At, Bt, opts, plan=plan, out=out)
+                torch.cuda.synchronize()
+                api.profile_enable(False)
+                prof = api.profile_read()
+                grp = "lane_symbolic" if lane else "esc_symbolic"
+                acc = prof.get(grp)
+                got = (colptr.cpu().numpy(), ri[:nnz].cpu().numpy(), v[:nnz].cpu().numpy())
+                if ref is None:
+                    ref = got
+                same = all(np.array_equal(g, r) for g, r in zip(got, ref))
+                row[kind] = {"ms": round(ms, 4),
+                             "accumulator_ms": round(acc[1] / acc[0], 4) if acc else None,
+                             "same_output": bool(same)}
+                plan.close()
+            log(f"n={n} z={z}: esc {row['esc']} lane {row['lane']}")
+            rows.append(row)
+    print(json.dumps({"lane_sweep": rows}), flush=True)
 
 
 def copy_calibration():
@@ -190,9 +247,12 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.lane_sweep:
+        lane_sweep()
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                          "described in DESIGN.md but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU only; multi-GPU sharding "
+                          "is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

@@ -90,6 +90,11 @@ typedef struct spgemm_plan_s *spgemm_plan;
                                        accumulators (by default a plan that has run before
                                        launches the whole symbolic phase from its previous
                                        sizes and redoes it only if the device finds others) */
+#define SPGEMM_LANE_HASH 8u /* columns of at most 64 products (the wavefront sort-merge
+                               sub-bins up to 64) go to a lane-per-column hash accumulator
+                               instead: one output column per lane with a lane-private
+                               LDS table, the paper's per-element mapping of HASH
+                               (Section 3.2); same results */
 
 /*
  * Tuning options. Results never depend on them: they only choose which

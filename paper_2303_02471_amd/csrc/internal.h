@@ -189,6 +189,10 @@ hipError_t launch_tally(const KArgs &a, hipStream_t s);
 hipError_t launch_place(const KArgs &a, hipStream_t s);
 // wavefront groups of ESC sub-bin `sub`; wide: 64-bit keys (rows of 2^24 - 1 and more)
 hipError_t launch_esc(const KArgs &a, bool wide, int sub, int groups, hipStream_t s);
+// lane-per-column hash accumulator over ESC sub-bin `sub` (at most 64 products,
+// ncols columns): the same outputs as launch_esc
+hipError_t launch_lane(const KArgs &a, int sub, int ncols, hipStream_t s);
+constexpr int kLaneMaxSub = 4;  // sub-bins 0..4 (up to 64 products) may take it
 // workgroup sort of sort bin `cls` (n columns); wide: 64-bit keys (rows beyond 20 bits)
 hipError_t launch_sort(const KArgs &a, int cls, bool wide, int n, hipStream_t s);
 // windowed workgroup sort (columns from the device header; any grid covers them)

@@ -420,12 +420,21 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
         ProfScope ps(snames[c], sc);
         if ((e = launch_sort(a, c, p->wide_keys, n, sc))) return e;
     }
+    const bool lane = (p->flags & SPGEMM_LANE_HASH) != 0;
     {
         ProfScope ps("esc_symbolic", s);
         for (int i = kEscBins - 1; i >= 0; --i) {
+            if (lane && i <= kLaneMaxSub) continue;
             hipStream_t si = esc_stream[i] < 0 ? s : side(p, esc_stream[i], s);
             if ((e = launch_esc(a, p->wide_esc, i, ceil_div(h.bin_count[BIN_ESC0 + i], 64 >> i), si)))
                 return e;
+        }
+    }
+    if (lane) {
+        ProfScope ps("lane_symbolic", s);
+        for (int i = kLaneMaxSub; i >= 0; --i) {
+            hipStream_t si = esc_stream[i] < 0 ? s : side(p, esc_stream[i], s);
+            if ((e = launch_lane(a, i, h.bin_count[BIN_ESC0 + i], si))) return e;
         }
     }
     for (int c = 0; c < kSortBins; ++c) {
