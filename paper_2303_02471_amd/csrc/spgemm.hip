@@ -376,21 +376,24 @@ int bin_start(const Hdr &h, int b) {
 }
 
 // Symbolic accumulators. The kinds work on disjoint columns and run
-// concurrently so their latencies overlap: the workgroup hash classes (few,
-// long work items) start first on two side streams, the two larger sorts
-// share a third, and the wavefront sort-merge groups with the two smaller
-// sorts run on the caller's stream.
+// concurrently so their latencies overlap: the windowed sort of the largest
+// columns (few, long workgroups that need a whole compute unit's LDS share)
+// starts first on the caller's stream, which needs no event wait, followed by
+// the two smaller sorts; the wavefront sort-merge sub-bins (and the workgroup
+// hash classes when enabled) take one side stream, the two larger sorts
+// another.
 hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream_t s) {
     const Hdr &h = p->hdr_host;
     hipError_t e;
     // stream of each ESC sub-bin and sort class (-1: the caller's, after the
     // ESC sub-bins; sorts on side streams start first, largest class first)
-    static const int esc_stream[kEscBins] = {-1, -1, -1, -1, -1, -1, -1};
+    static const int esc_stream[kEscBins] = {0, 0, 0, 0, 0, 0, 0};
     static const int sort_stream[kSortBins] = {-1, -1, 1, 1};
+    static const int wsort_stream = -1;
     unsigned used = 0;
     for (int c = 0; c < kBlkBins; ++c)
         if (h.bin_count[BIN_BLK0 + c]) used |= c == kBlkBins - 1 ? 4u : 1u;
-    if (h.bin_count[BIN_WSORT]) used |= 4u;
+    if (h.bin_count[BIN_WSORT] && wsort_stream >= 0) used |= 1u << wsort_stream;
     for (int c = 0; c < kSortBins; ++c)
         if (h.bin_count[BIN_SORT0 + c] && sort_stream[c] >= 0) used |= 1u << sort_stream[c];
     for (int i = 0; i < kEscBins; ++i)
@@ -407,9 +410,9 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
         if ((e = launch_block(a, c, n, sc))) return e;
     }
     if (const int n = h.bin_count[BIN_WSORT]) {
-        ProfScope ps("wsort_symbolic", side(p, 2, s));
-        if ((e = launch_wsort(a, p->wide_keys, n, side(p, 2, s))))
-            return e;
+        hipStream_t sw = wsort_stream < 0 ? s : side(p, wsort_stream, s);
+        ProfScope ps("wsort_symbolic", sw);
+        if ((e = launch_wsort(a, p->wide_keys, n, sw))) return e;
     }
     static const char *snames[kSortBins] = {"sort512_symbolic", "sort1k_symbolic",
                                             "sort2k_symbolic", "sort4k_symbolic"};
