@@ -189,6 +189,8 @@ hipError_t launch_tally(const KArgs &a, hipStream_t s);
 hipError_t launch_place(const KArgs &a, hipStream_t s);
 // wavefront groups of ESC sub-bin `sub`; wide: 64-bit keys (rows of 2^24 - 1 and more)
 hipError_t launch_esc(const KArgs &a, bool wide, int sub, int groups, hipStream_t s);
+// every sub-bin in one launch; groups[i] wavefront groups of sub-bin i (0: none)
+hipError_t launch_esc_all(const KArgs &a, bool wide, const int *groups, hipStream_t s);
 // lane-per-column hash accumulator over ESC sub-bin `sub` (at most 64 products,
 // ncols columns): the same outputs as launch_esc
 hipError_t launch_lane(const KArgs &a, int sub, int ncols, hipStream_t s);

@@ -228,6 +228,69 @@ __global__ __launch_bounds__(kBlock) void k_esc(KArgs a) {
         atomicMax(&a.hdr->later_maxk, kmax);
 }
 
+// All sub-bins in one launch, the largest first: position j of the launch
+// order is sub-bin r.sub[j], with the workgroups [r.first[j], r.first[j + 1]).
+struct EscRanges {
+    int first[kEscBins + 1];
+    int sub[kEscBins];
+};
+
+template <typename K, int LS>
+__device__ __forceinline__ void esc_sub(const KArgs &a, EscSmem<K> &S, int blk, int nblk,
+                                        int lane, int &kmax) {
+    constexpr int sb = LS - 2, G = 64 >> sb;
+    int start = 0;
+    for (int b = 0; b < BIN_ESC0 + sb; ++b) start += a.hdr->bin_count[b];
+    const int cnt = a.hdr->bin_count[BIN_ESC0 + sb];
+    const int ngroups = ceil_div(cnt, G);
+    const int wstride = nblk * (kBlock / 64);
+    for (int gi = blk * (kBlock / 64) + (threadIdx.x >> 6); gi < ngroups; gi += wstride)
+        esc_group<K, LS>(a, S, start + gi * G, min(G, cnt - gi * G), lane, kmax);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_esc_all(KArgs a, EscRanges r) {
+    __shared__ EscSmem<K> smem[kBlock / 64];
+    if (a.hdr->err) return;
+    const int lane = lane_id();
+    EscSmem<K> &S = smem[threadIdx.x >> 6];
+    int j = 0;
+    while (j + 1 < kEscBins && (int)blockIdx.x >= r.first[j + 1]) ++j;
+    const int blk = (int)blockIdx.x - r.first[j], nblk = r.first[j + 1] - r.first[j];
+    int kmax = 0;
+    switch (r.sub[j]) {
+        case 0: esc_sub<K, 2>(a, S, blk, nblk, lane, kmax); break;
+        case 1: esc_sub<K, 3>(a, S, blk, nblk, lane, kmax); break;
+        case 2: esc_sub<K, 4>(a, S, blk, nblk, lane, kmax); break;
+        case 3: esc_sub<K, 5>(a, S, blk, nblk, lane, kmax); break;
+        case 4: esc_sub<K, 6>(a, S, blk, nblk, lane, kmax); break;
+        case 5: esc_sub<K, 7>(a, S, blk, nblk, lane, kmax); break;
+        default: esc_sub<K, 8>(a, S, blk, nblk, lane, kmax); break;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+        kmax = max(kmax, __builtin_amdgcn_ds_bpermute((lane ^ d) << 2, kmax));
+    if (lane == 0 && kmax > __atomic_load_n(&a.hdr->later_maxk, __ATOMIC_RELAXED))
+        atomicMax(&a.hdr->later_maxk, kmax);
+}
+
+// groups[i]: wavefront groups of sub-bin i (0 skips it)
+hipError_t launch_esc_all(const KArgs &a, bool wide, const int *groups, hipStream_t s) {
+    EscRanges r{};
+    int tot = 0;
+    for (int j = 0; j < kEscBins; ++j) {
+        const int i = kEscBins - 1 - j;
+        r.sub[j] = i;
+        r.first[j] = tot;
+        tot += ceil_div(groups[i], kBlock / 64);
+    }
+    r.first[kEscBins] = tot;
+    if (tot == 0) return hipSuccess;
+    if (wide) hipLaunchKernelGGL((k_esc_all<unsigned long long>), dim3(tot), dim3(kBlock), 0, s, a, r);
+    else hipLaunchKernelGGL((k_esc_all<unsigned>), dim3(tot), dim3(kBlock), 0, s, a, r);
+    return hipGetLastError();
+}
+
 hipError_t launch_esc(const KArgs &a, bool wide, int sub, int groups, hipStream_t s) {
     if (groups <= 0) return hipSuccess;
     const dim3 grid(ceil_div(groups, kBlock / 64));

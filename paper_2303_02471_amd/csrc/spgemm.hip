@@ -387,7 +387,7 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
     hipError_t e;
     // stream of each ESC sub-bin and sort class (-1: the caller's, after the
     // ESC sub-bins; sorts on side streams start first, largest class first)
-    static const int esc_stream[kEscBins] = {0, 0, 0, 0, 0, 0, 0};
+    static const int esc_side = 0;  // stream of the ESC launch (-1: the caller's)
     static const int sort_stream[kSortBins] = {-1, -1, 1, 1};
     static const int wsort_stream = -1;
     unsigned used = 0;
@@ -397,7 +397,7 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
     for (int c = 0; c < kSortBins; ++c)
         if (h.bin_count[BIN_SORT0 + c] && sort_stream[c] >= 0) used |= 1u << sort_stream[c];
     for (int i = 0; i < kEscBins; ++i)
-        if (h.bin_count[BIN_ESC0 + i] && esc_stream[i] >= 0) used |= 1u << esc_stream[i];
+        if (h.bin_count[BIN_ESC0 + i] && esc_side >= 0) used |= 1u << esc_side;
     if ((e = fork(p, s, used))) return e;
     static const char *bnames[kBlkBins] = {"block512_symbolic", "block1k_symbolic",
                                            "block2k_symbolic", "block4k_symbolic",
@@ -425,18 +425,25 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
     }
     const bool lane = (p->flags & SPGEMM_LANE_HASH) != 0;
     {
-        ProfScope ps("esc_symbolic", s);
-        for (int i = kEscBins - 1; i >= 0; --i) {
-            if (lane && i <= kLaneMaxSub) continue;
-            hipStream_t si = esc_stream[i] < 0 ? s : side(p, esc_stream[i], s);
-            if ((e = launch_esc(a, p->wide_esc, i, ceil_div(h.bin_count[BIN_ESC0 + i], 64 >> i), si)))
-                return e;
+        // on one stream, one launch over the sub-bins saves six kernel
+        // boundaries; beside the other kinds, one launch per sub-bin (largest
+        // first) shares the chip better (measured both ways)
+        int groups[kEscBins];
+        for (int i = 0; i < kEscBins; ++i)
+            groups[i] = (lane && i <= kLaneMaxSub) ? 0 : ceil_div(h.bin_count[BIN_ESC0 + i], 64 >> i);
+        hipStream_t se = esc_side < 0 ? s : side(p, esc_side, s);
+        ProfScope ps("esc_symbolic", se);
+        if (p->flags & SPGEMM_ONE_STREAM) {
+            if ((e = launch_esc_all(a, p->wide_esc, groups, se))) return e;
+        } else {
+            for (int i = kEscBins - 1; i >= 0; --i)
+                if (groups[i] && (e = launch_esc(a, p->wide_esc, i, groups[i], se))) return e;
         }
     }
     if (lane) {
         ProfScope ps("lane_symbolic", s);
         for (int i = kLaneMaxSub; i >= 0; --i) {
-            hipStream_t si = esc_stream[i] < 0 ? s : side(p, esc_stream[i], s);
+            hipStream_t si = esc_side < 0 ? s : side(p, esc_side, s);
             if ((e = launch_lane(a, i, h.bin_count[BIN_ESC0 + i], si))) return e;
         }
     }

@@ -93,7 +93,8 @@ def test_powerlaw_reduced():
     dict(t_split=-1), dict(t_split=1), dict(t_esc=4, t_split=300, hash_cap=64, t_block=-1),
     dict(t_esc=16, t_split=1, t_dense=100000, t_block=1000), dict(hash_cap=16, t_dense=100000),
     dict(t_esc=4, hash_cap=16, dense_rows=1, t_block=-1), dict(t_block=-1), dict(t_block=512),
-    dict(t_block=4096, hash_cap=300), dict(lane_hash=True), dict(lane_hash=True, t_esc=16)])
+    dict(t_block=4096, hash_cap=300), dict(lane_hash=True), dict(lane_hash=True, t_esc=16),
+    dict(one_stream=True), dict(one_stream=True, t_esc=32), dict(one_stream=True, lane_hash=True)])
 def test_forced_bins_identical(opts):
     """Any split of the work between accumulators gives the same bits (the
     t = 0 / t = infinity limits of Section 3.3 and everything between)."""
@@ -298,7 +299,7 @@ def test_planned_launch_and_retry():
 
 
 @pytest.mark.parametrize("opts", [dict(), dict(t_esc=8), dict(t_block=300), dict(t_split=300),
-                                  dict(lane_hash=True)])
+                                  dict(lane_hash=True), dict(one_stream=True)])
 def test_wide_rows(opts):
     """More than 2^24 - 1 rows: the sort bins and the wavefront sort-merge use
     64-bit keys. Columns reach every accumulator (up to about 11,000 products),
