@@ -5,6 +5,19 @@
 
 namespace spg {
 
+// Device memory named through a pointer read from memory (a problem's arrays)
+// is reached with flat instructions unless the type says it is global. Flat
+// loads and stores also count against the LDS wait counter, so every LDS read
+// after them waits for them to complete; through a gmem pointer they are
+// global memory instructions, and LDS work overlaps the gathers in flight.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ gmem<T> *to_gmem(T *p) {
+    return (gmem<T> *)p;
+}
+
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }

@@ -257,6 +257,9 @@ hipError_t launch_bw_view(const Prob &p, const int2 *E, const BwBuild &b, BwView
 hipError_t launch_backward(const Prob &p, const BwView &w, bool f64, const void *av,
                            const void *bv, const void *gv, void *da, void *db, int *err,
                            hipStream_t s);
+// nwords 32-bit words from src to mapped host memory dst, as 8-byte pairs
+// (word, seq)
+hipError_t launch_publish(const void *src, int nwords, void *dst, uint32_t seq, hipStream_t s);
 // exclusive scans of n int32 values (bsum: nbsum partials, in place allowed
 // for the int32 output)
 hipError_t launch_scan_i32(const int32_t *in, int n, long long *bsum, int nbsum, int32_t *out,

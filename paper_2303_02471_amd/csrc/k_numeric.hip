@@ -57,9 +57,10 @@ __global__ __launch_bounds__(kBlock) void k_expand(KArgs a) {
     int bad = 0;
     for_each_segment(a, g0, g1, [&](int, const Prob &d, int j0, int j1) {
         long long base = a.colprod[d.col0 + j0];
-        const int pb = d.bcp[j0], pe = d.bcp[j1];  // checked by the classification
+        const gmem<const int32_t> *bcp = to_gmem(d.bcp);
+        const int pb = bcp[j0], pe = bcp[j1];  // checked by the classification
         const int2 *__restrict__ Ep = a.E + d.ebase;
-        const int *__restrict__ ari = d.ari;
+        const gmem<const int32_t> *__restrict__ ari = to_gmem(d.ari);
         for (int bw = pb; bw < pe; bw += kBlock) {
             const int t = bw + tid;
             int z = 0, acp = 0;
@@ -125,45 +126,51 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
                                                const int *s_col, const V *s_bv, int nbw, int Ew,
                                                Pos &&pos, Cinfo &&cinfo, First &&first,
                                                int &bad) {
-    const V *__restrict__ av = (const V *)d.av;
+    const gmem<const V> *__restrict__ av = to_gmem((const V *)d.av);
     V *__restrict__ lv = (V *)a.lv;
     const int tid = threadIdx.x;
     for (int e0 = 0; e0 < Ew; e0 += PER * kBlock) {
-        V v[PER];
+        V x[PER], y[PER];
         int row[PER], c[PER];
         uint32_t dc[PER];
         long long pp[PER];
+        // All of the thread's loads are issued, without branches, before any
+        // is used, so its gathers of A's values are in flight together. A
+        // slot past the window's end repeats the window's last product and
+        // writes nothing.
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = e0 + u * kBlock + tid;
-            c[u] = -1;
-            if (e < Ew) {
-                const int tt = last_le(s_eoff, nbw, e);
-                const int q = s_acp[tt] + e - s_eoff[tt];
-                c[u] = s_col[tt];
-                pp[u] = pos(tt, e);
-                v[u] = av[q] * s_bv[tt];
-                row[u] = a.prow[pp[u]];  // the expansion's row, read in product order
-                dc[u] = a.dst[pp[u]];
-            }
+            const int ee = min(e, Ew - 1);
+            const int tt = last_le(s_eoff, nbw, ee);
+            const int q = s_acp[tt] + ee - s_eoff[tt];
+            c[u] = e < Ew ? s_col[tt] : -1;
+            pp[u] = pos(tt, ee);
+            y[u] = s_bv[tt];
+            x[u] = av[q];
+            row[u] = a.prow[pp[u]];  // the expansion's row, read in product order
+            dc[u] = a.dst[pp[u]];
         }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) x[u] = x[u] * y[u];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             if (c[u] < 0) continue;
+            const V vu = x[u];
             int c0, clen;
             long long lb;
             cinfo(c[u], c0, clen, lb);
             const int o = (int)(dc[u] & ~kDstLater);
             if (o >= clen) { bad = 1; continue; }
             if (!(dc[u] & kDstLater)) {
-                first(c[u], o, row[u], V(0) + v[u]);
+                first(c[u], o, row[u], V(0) + vu);
             } else {
                 const long long li = lb + a.lr[pp[u]];
                 if (li < 0 || li >= a.later_n) { bad = 1; continue; }
                 a.lo[li] = c0 + o;
                 a.lpid[li] = pid;
                 a.lkc[li] = a.lk[pp[u]];
-                lv[li] = v[u];
+                lv[li] = vu;
             }
         }
     }
@@ -198,20 +205,22 @@ __device__ __forceinline__ void numeric_tile(const KArgs &a, NumSmem<V> &S, int 
     int bad = 0;
     for_each_segment(a, g0, g1, [&](int pid, const Prob &d, int js, int je) {
         const int2 *__restrict__ Ep = a.E + d.ebase;
-        const V *__restrict__ bv = (const V *)d.bv;
+        const gmem<const V> *__restrict__ bv = to_gmem((const V *)d.bv);
+        const gmem<const int32_t> *__restrict__ bcp = to_gmem(d.bcp);
+        const gmem<const int32_t> *__restrict__ ccp = to_gmem((const int32_t *)d.ccp);
         for (int jw = js; jw < je; jw += kColWin) {
             const int nc = min(kColWin, je - jw);
             const int gw = d.col0 + jw;
             int eff = 0;
             for (int c = tid; c <= nc; c += kBlock) {
-                S.s_bcp[c] = d.bcp[jw + c];
-                S.s_c0[c] = d.ccp[jw + c];
+                S.s_bcp[c] = bcp[jw + c];
+                S.s_c0[c] = ccp[jw + c];
             }
             if (tid < nc) {
                 const int op = a.op[gw + tid];
                 const int ok = op <= a.tune.t_split;
                 S.s_ok[tid] = ok;
-                const int c0 = d.ccp[jw + tid];
+                const int c0 = ccp[jw + tid];
                 const long long pc = a.colprod[gw + tid];
                 S.s_pcol[tid] = pc;
                 S.s_lb[tid] = pc - (a.nprob == 1 ? (long long)c0 : a.gcp[gw + tid]);
@@ -222,8 +231,8 @@ __device__ __forceinline__ void numeric_tile(const KArgs &a, NumSmem<V> &S, int 
             if (tid < nc) S.s_ceff[tid] = ex;
             if (tid == 0) S.s_ceff[nc] = tot;
             __syncthreads();
-            int *__restrict__ cri = d.cri;
-            V *__restrict__ cv = (V *)d.cv;
+            gmem<int32_t> *__restrict__ cri = to_gmem(d.cri);
+            gmem<V> *__restrict__ cv = to_gmem((V *)d.cv);
             const int pb = S.s_bcp[0], pe = S.s_bcp[nc];
             int base = 0;  // first product of the B window among the tile columns
             int2 nez = make_int2(0, 0);
@@ -320,9 +329,12 @@ __device__ __forceinline__ void numeric_chunk(const KArgs &a, BigSmem<V> &S, int
     if (tid == 0) S.s_pre = 0;
     __syncthreads();
     if (pre) atomicAdd((unsigned long long *)&S.s_pre, (unsigned long long)pre);
-    const int c0 = d.ccp[j], clen = d.ccp[j + 1] - c0;
+    const gmem<const int32_t> *ccp = to_gmem((const int32_t *)d.ccp);
+    const int c0 = ccp[j], clen = ccp[j + 1] - c0;
     const long long lb0 = a.colprod[g] - (a.nprob == 1 ? (long long)c0 : a.gcp[g]);
-    const V *__restrict__ bv = (const V *)d.bv;
+    const gmem<const V> *__restrict__ bv = to_gmem((const V *)d.bv);
+    gmem<int32_t> *__restrict__ cri = to_gmem(d.cri);
+    gmem<V> *__restrict__ cv = to_gmem((V *)d.cv);
     __syncthreads();
     long long pbase = a.colprod[g] + S.s_pre;
     int bad = 0;
@@ -358,8 +370,8 @@ __device__ __forceinline__ void numeric_chunk(const KArgs &a, BigSmem<V> &S, int
                 lb = lb0;
             },
             [&](int, int o, int row, V v) {
-                d.cri[c0 + o] = row;
-                ((V *)d.cv)[c0 + o] = v;
+                cri[c0 + o] = row;
+                cv[c0 + o] = v;
             },
             bad);
         pbase += Ew;
@@ -406,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_layer(KArgs a, int k, long long n) {
         const int o = a.lo[i];
         if (pid < 0 || pid >= a.nprob || o < 0 || (long long)o >= a.out_cap) continue;
         const Prob d = get_prob(a, pid);
-        V *cv = (V *)d.cv;
+        gmem<V> *cv = to_gmem((V *)d.cv);
         cv[o] = cv[o] + lv[i];
     }
 }
@@ -428,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_later_runs(KArgs a, long long n) {
         if (i > 0 && a.lo[i - 1] == o && a.lpid[i - 1] == pid) continue;  // inside a run
         if (pid < 0 || pid >= a.nprob || o < 0 || (long long)o >= a.out_cap) continue;
         const Prob d = get_prob(a, pid);
-        V *cv = (V *)d.cv;
+        gmem<V> *cv = to_gmem((V *)d.cv);
         V acc = cv[o];
         for (long long j = i; j < n && a.lo[j] == o && a.lpid[j] == pid; ++j) acc = acc + lv[j];
         cv[o] = acc;

@@ -56,41 +56,33 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     }
 
     const int pb = s_bcp[0], pe = s_bcp[nt];
+    const gmem<const int32_t> *__restrict__ bri = to_gmem(d.bri);
+    const gmem<const int32_t> *__restrict__ acp = to_gmem(d.acp);
     err = 0;
     for (int p0 = pb; p0 < pe; p0 += 4 * kBlock) {
-        int kk[4], z[4];
+        // Every load of the pass is issued before any is used: a slot past
+        // the tile's end reads its last entry, an index out of range reads
+        // A's first column pointers; neither result is used.
+        int kk[4], x0[4], x1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) kk[u] = bri[min(p0 + u * kBlock + tid, pe - 1)];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            int p = p0 + u * kBlock + tid;
-            kk[u] = p < pe ? d.bri[p] : -1;
+            const int kc = (kk[u] < 0 || kk[u] >= d.k) ? 0 : kk[u];
+            x0[u] = acp[kc];
+            x1[u] = acp[min(kc + 1, d.k)];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            z[u] = 0;
-            int k = kk[u];
             const int p = p0 + u * kBlock + tid;
-            if (p < pe) {
-                int x0 = 0;
-                if (k < 0 || k >= d.k) {
-                    err = ERR_CSC;
-                } else {
-                    x0 = d.acp[k];
-                    const int x1 = d.acp[k + 1];
-                    if (x0 < 0 || x1 < x0 || x1 > d.nnza) { err = ERR_CSC; x0 = 0; }
-                    else z[u] = x1 - x0;
-                }
-                // the A column each stored B entry selects, for the accumulators
-                a.E[d.ebase + p] = make_int2(x0, z[u]);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int p = p0 + u * kBlock + tid;
-            if (z[u] > 0) {
-                int c = last_le(s_bcp, nt + 1, p);
-                // skip empty columns that share the pointer value
-                atomicAdd(&s_op[c], (unsigned long long)z[u]);
-            }
+            const int k = kk[u];
+            const bool in = p < pe;
+            const bool ok = k >= 0 && k < d.k && x0[u] >= 0 && x1[u] >= x0[u] && x1[u] <= d.nnza;
+            const int s0 = ok ? x0[u] : 0, z = (in && ok) ? x1[u] - x0[u] : 0;
+            if (in && !ok) err = ERR_CSC;
+            // the A column each stored B entry selects, for the accumulators
+            if (in) a.E[d.ebase + p] = make_int2(s0, z);
+            if (z > 0) atomicAdd(&s_op[last_le(s_bcp, nt + 1, p)], (unsigned long long)z);
         }
     }
     if (err) atomicOr(&s_err, err);
@@ -512,6 +504,25 @@ hipError_t launch_scan(const KArgs &a, long long *gcp, long long *bsum, int nblk
         hipLaunchKernelGGL(k_scan_finish, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, a,
                            (const long long *)gcp, totals);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- publish
+// Copies the header and the per-problem totals (nwords 32-bit words) to mapped
+// host memory, each word beside the call's sequence number in one 8-byte
+// store, so the host can read them as soon as the symbolic phase ends while
+// later work stays queued behind it. A word is current when its pair carries
+// the current number: no fence or cache write-back is needed.
+__global__ __launch_bounds__(64) void k_publish(const uint32_t *__restrict__ src, int nwords,
+                                                unsigned long long *dst, uint32_t seq) {
+    for (int i = threadIdx.x; i < nwords; i += 64)
+        __hip_atomic_store(&dst[i], (unsigned long long)src[i] | ((unsigned long long)seq << 32),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_publish(const void *src, int nwords, void *dst, uint32_t seq, hipStream_t s) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, (const uint32_t *)src, nwords,
+                       (unsigned long long *)dst, seq);
     return hipGetLastError();
 }
 

@@ -67,9 +67,11 @@ struct spgemm_plan_s {
     long long *ttot = nullptr;
     int nbsum = 0;
 
-    // pinned host mirror of the header and totals
-    void *pinned = nullptr;
+    // pinned host mirror of the header and totals (raw, then as published
+    // pairs), mapped for the device
+    void *pinned = nullptr, *pinned_dev = nullptr;
     size_t pinned_bytes = 0;
+    uint32_t pub_seq = 0;
     Hdr hdr_host{};
     std::vector<long long> totals_host;
 
@@ -82,7 +84,6 @@ struct spgemm_plan_s {
     static constexpr int kSide = 3;
     hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[kSide] = {nullptr, nullptr, nullptr};
-    hipEvent_t sym_ev = nullptr;  // header read-back of a one-call product
 
     // backward: row view of B
     void *bt = nullptr;
@@ -134,6 +135,50 @@ struct ProfScope {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 constexpr size_t kHdrBytes = (sizeof(Hdr) + 63) / 64 * 64;  // header, then the totals
+// The host mirror: the raw header and totals (pin bytes, read back by copies)
+// and then the same words as published pairs (word, sequence number).
+unsigned long long *pub_pairs_host(spgemm_plan p) {
+    return (unsigned long long *)((char *)p->pinned + p->pinned_bytes);
+}
+
+// Queues the publication of the header and totals, tagged with the next
+// sequence number; later work queued on s runs on behind it.
+hipError_t publish(spgemm_plan p, hipStream_t s) {
+    const uint32_t seq = ++p->pub_seq;
+    return launch_publish(p->hdr, (int)((kHdrBytes + 8 * (size_t)p->nprob) / 4),
+                          (char *)p->pinned_dev + p->pinned_bytes, seq, s);
+}
+
+// Waits until every published pair carries the last sequence number and
+// copies the words to the raw mirror. The stream is polled now and then, so a
+// failed or finished stream ends the wait.
+spgemm_status wait_published(spgemm_plan p, hipStream_t s) {
+    const int nwords = (int)((kHdrBytes + 8 * (size_t)p->nprob) / 4);
+    const unsigned long long *pairs = pub_pairs_host(p);
+    uint32_t *raw = (uint32_t *)p->pinned;
+    unsigned spin = 0;
+    for (int i = 0; i < nwords; ++i) {
+        for (;;) {
+            const unsigned long long v = __atomic_load_n(&pairs[i], __ATOMIC_ACQUIRE);
+            if ((uint32_t)(v >> 32) == p->pub_seq) {
+                raw[i] = (uint32_t)v;
+                break;
+            }
+            if ((++spin & 1023u) == 0) {
+                const hipError_t q = hipStreamQuery(s);
+                // all queued work has ended: the pairs are written by now
+                if (q == hipSuccess) {
+                    const unsigned long long w = __atomic_load_n(&pairs[i], __ATOMIC_ACQUIRE);
+                    if ((uint32_t)(w >> 32) != p->pub_seq) return SPGEMM_ERR_HIP;
+                    raw[i] = (uint32_t)w;
+                    break;
+                }
+                if (q != hipErrorNotReady) return SPGEMM_ERR_HIP;
+            }
+        }
+    }
+    return SPGEMM_OK;
+}
 
 spgemm_status hip_status(hipError_t e) {
     if (e == hipSuccess) return SPGEMM_OK;
@@ -263,10 +308,20 @@ spgemm_status ensure_workspace(spgemm_plan p) {
     const size_t pin = kHdrBytes + 8 * (size_t)std::max(p->nprob, 1);
     if (pin > p->pinned_bytes) {
         if (p->pinned) (void)hipHostFree(p->pinned);
-        p->pinned = nullptr;
-        if (hipHostMalloc(&p->pinned, pin, hipHostMallocDefault) != hipSuccess)
+        p->pinned = p->pinned_dev = nullptr;
+        p->pinned_bytes = 0;
+        // coherent: the device's stores reach host memory without a copy
+        if (hipHostMalloc(&p->pinned, 3 * pin, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess)
             return SPGEMM_ERR_NO_MEMORY;
+        if (hipHostGetDevicePointer(&p->pinned_dev, p->pinned, 0) != hipSuccess) {
+            (void)hipHostFree(p->pinned);
+            p->pinned = p->pinned_dev = nullptr;
+            return SPGEMM_ERR_HIP;
+        }
         p->pinned_bytes = pin;
+        std::memset(p->pinned, 0, 3 * pin);
+        p->pub_seq = 0;  // no pair carries the next number
     }
     return SPGEMM_OK;
 }
@@ -335,7 +390,6 @@ hipError_t ensure_side_streams(spgemm_plan p) {
         if ((e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking))) return e;
         if ((e = hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming))) return e;
     }
-    if ((e = hipEventCreateWithFlags(&p->sym_ev, hipEventDisableTiming))) return e;
     return hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
 }
 
@@ -620,13 +674,11 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         ProfScope ps("scan", s);
         SPG_TRY(launch_scan(al, p->gcp, p->bsum, p->nblk, p->totals, s));
     }
-    SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, kHdrBytes + 8 * (size_t)p->nprob,
-                           hipMemcpyDeviceToHost, s));
+    SPG_TRY(publish(p, s));
     if (fo && spec && p->ncols > 0 && p->nprob == 1) {
         // the numeric phase from the previous sizes; it stands down on an
         // error or capacity flag raised above, and is redone by the caller if
         // the sizes read back differ
-        SPG_TRY(hipEventRecord(p->sym_ev, s));
         p->probs[0].cri = fo->cri;
         p->probs[0].cv = fo->cv;
         KArgs an = make_args(p);
@@ -634,9 +686,10 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         fo->used = numeric_launch(p);
         fo->queued = true;
         SPG_TRY(launch_numeric_phase(p, an, s));
-        SPG_TRY(hipEventSynchronize(p->sym_ev));
-    } else {
-        SPG_TRY(hipStreamSynchronize(s));
+    }
+    {
+        const spgemm_status w = wait_published(p, s);
+        if (w != SPGEMM_OK) return w;
     }
     std::memcpy(&p->hdr_host, p->pinned, sizeof(Hdr));
     int err = p->hdr_host.err;
@@ -1097,7 +1150,6 @@ void spgemm_plan_destroy(spgemm_plan p) {
         if (p->join_ev[i]) (void)hipEventDestroy(p->join_ev[i]);
     }
     if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
-    if (p->sym_ev) (void)hipEventDestroy(p->sym_ev);
     if (p->prod) (void)hipFree(p->prod);
     if (p->stage) (void)hipFree(p->stage);
     if (p->ws) (void)hipFree(p->ws);
