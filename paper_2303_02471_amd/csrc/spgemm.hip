@@ -121,7 +121,10 @@ struct ProfScope {
         if (g_prof.only[0] && std::strncmp(g_prof.only, name, sizeof(g_prof.only)) != 0) return;
         if (g_prof.used == g_prof.recs.size()) {
             ProfRec nr{name, nullptr, nullptr};
-            if (hipEventCreate(&nr.a) != hipSuccess || hipEventCreate(&nr.b) != hipSuccess) return;
+            // timing only: a device-scope release keeps the events light
+            if (hipEventCreateWithFlags(&nr.a, hipEventReleaseToDevice) != hipSuccess ||
+                hipEventCreateWithFlags(&nr.b, hipEventReleaseToDevice) != hipSuccess)
+                return;
             g_prof.recs.push_back(nr);
         }
         r = &g_prof.recs[g_prof.used++];
@@ -386,11 +389,14 @@ int device_cus() {
 hipError_t ensure_side_streams(spgemm_plan p) {
     if (p->fork_ev) return hipSuccess;
     hipError_t e;
+    // the fork and join events only order streams of this device: a
+    // device-scope release is enough (no write-back for the host's view)
+    const unsigned ef = hipEventDisableTiming | hipEventReleaseToDevice;
     for (int i = 0; i < spgemm_plan_s::kSide; ++i) {
         if ((e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking))) return e;
-        if ((e = hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming))) return e;
+        if ((e = hipEventCreateWithFlags(&p->join_ev[i], ef))) return e;
     }
-    return hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+    return hipEventCreateWithFlags(&p->fork_ev, ef);
 }
 
 

@@ -150,6 +150,27 @@ def test_batched_matches_oracle_and_single_path():
             assert np.array_equal(scp, cp) and np.array_equal(sri, ri) and np.array_equal(sv, v)
 
 
+def test_batched_plan_reuse_other_counts():
+    """One batch plan reused for batches of 3, 12 and 2 problems: the host
+    mirror of the header and per-problem totals grows once and is then reused;
+    every batch equals the oracle."""
+    plan = None
+    for k, seed in ((1, 11), (10, 12), (0, 13)):
+        probs = _batch(k, seed=seed, nmax=1500)
+        _say(f"batch plan reuse: {len(probs)} problems, seed {seed}")
+        pairs = [(api.CscTensor.from_host(a), api.CscTensor.from_host(b)) for a, b in probs]
+        plan, colptrs, nnzs = api.batched_symbolic(pairs, torch.float64, plan=plan)
+        ris = [torch.empty(z, dtype=torch.int32, device="cuda") for z in nnzs]
+        vals = [torch.empty(z, dtype=torch.float64, device="cuda") for z in nnzs]
+        api.batched_numeric(plan, pairs, ris, vals)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(probs):
+            ocp, ori, ov = oracle.spgemm(a, b)
+            assert_same_structure(colptrs[i].cpu().numpy(), ris[i].cpu().numpy(), ocp, ori,
+                                  f"batch of {len(probs)}, problem {i}")
+            assert_values_exact(vals[i].cpu().numpy(), ov, f"batch of {len(probs)}, problem {i}")
+
+
 def test_batched_f32():
     _say("batched f32")
     probs = [(a.astype(np.float32), b.astype(np.float32)) for a, b in _batch(12, seed=8)]
