@@ -41,7 +41,11 @@
  * Synchronisation: spgemm_symbolic and the size-query form of spgemm_batched
  * block the host until the output sizes are known (one read-back at the end
  * when the plan has run before with the same product count, two otherwise).
- * Every other call is stream-ordered and returns immediately.
+ * The final read-back is written by a kernel into the plan's mapped, coherent
+ * host memory; the calling thread spins on it (polling the stream, so an
+ * error on the stream ends the wait with SPGEMM_ERR_HIP). A plan must not be
+ * used by two host threads at once. Every other call is stream-ordered and
+ * returns immediately.
  */
 #ifndef SPGEMM_H
 #define SPGEMM_H
