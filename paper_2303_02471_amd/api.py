@@ -248,6 +248,40 @@ def matmul(A: CscTensor, B: CscTensor, opts=None, return_plan: bool = False):
     return (Cm, plan) if return_plan else Cm
 
 
+@dataclass
+class CsrTensor:
+    """CSR matrix held in device tensors (int32 rowptr/colidx, float values).
+    Its three arrays are exactly those of the CSC form of its transpose."""
+
+    nrows: int
+    ncols: int
+    rowptr: torch.Tensor
+    colidx: torch.Tensor
+    val: Optional[torch.Tensor] = None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colidx.numel())
+
+    def transpose_csc(self) -> CscTensor:
+        """The transpose, in CSC, sharing this matrix's arrays (no copy)."""
+        return CscTensor(self.ncols, self.nrows, self.rowptr, self.colidx, self.val)
+
+
+def matmul_rowwise(A: CsrTensor, B: CsrTensor, opts=None) -> CsrTensor:
+    """C = A x B on CSR operands, with sorted columns in every row: the
+    row-wise form of Gustavson's method that Section 2.1 mentions. Row i of C
+    accumulates B's row k scaled by A(i,k) over A's row i in storage order;
+    that is column i of C^T = B^T x A^T, whose CSC arrays are C's CSR arrays,
+    formed from the same products (a rounded product does not depend on the
+    operand order) added in the same order. The column kernels therefore
+    compute it unchanged, on the operands' arrays as they are."""
+    if A.ncols != B.nrows:
+        raise ValueError("A.ncols must equal B.nrows")
+    Ct = matmul(B.transpose_csc(), A.transpose_csc(), opts)
+    return CsrTensor(A.nrows, B.ncols, Ct.colptr, Ct.rowidx, Ct.val)
+
+
 def backward(plan: Plan, A_val: torch.Tensor, B_val: torch.Tensor, C_rowidx: torch.Tensor,
              G_val: torch.Tensor, need_a: bool = True, need_b: bool = True, stream=None,
              out=None):

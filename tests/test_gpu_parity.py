@@ -379,3 +379,55 @@ def test_multiply_one_call():
     st = plan.stats()
     plan.close()
     assert st["later_max"] >= 1
+
+
+def test_rowwise_csr_product():
+    """The row-wise form on CSR operands (Section 2.1). Bit for bit equal to the
+    oracle's row-wise sums, i.e. the column oracle on C^T = B^T x A^T whose CSC
+    arrays are C's CSR arrays; its structure is that of the column-wise product
+    and its values agree with the column-wise oracle within the stated
+    tolerance (the same terms, added in another order)."""
+    import torch
+    from paper_2303_02471_amd import api
+    rng = np.random.default_rng(21)
+    for (m, k, n, dens) in [(300, 200, 250, 0.05), (7, 500, 40, 0.2), (1, 1, 1, 1.0),
+                            (600, 80, 3, 0.3)]:
+        _say(f"row-wise CSR m={m} k={k} n={n}")
+        at = gen.random_tiny(rng, k, m, dens, "normal")  # CSC of A^T = CSR of A
+        bt = gen.random_tiny(rng, n, k, dens, "normal")  # CSC of B^T = CSR of B
+        ta, tb = api.CscTensor.from_host(at), api.CscTensor.from_host(bt)
+        A = api.CsrTensor(m, k, ta.colptr, ta.rowidx, ta.val)
+        B = api.CsrTensor(k, n, tb.colptr, tb.rowidx, tb.val)
+        C = api.matmul_rowwise(A, B)
+        torch.cuda.synchronize()
+        rp, ci, v = C.rowptr.cpu().numpy(), C.colidx.cpu().numpy(), C.val.cpu().numpy()
+        orp, oci, ov = oracle.spgemm(bt, at)
+        assert_same_structure(rp, ci, orp, oci, f"row-wise {m}x{k}x{n}")
+        assert_values_exact(v, ov, f"row-wise {m}x{k}x{n}")
+        # against the column-wise oracle of A x B, transposed on the host
+        a = gen.CSC(m, k, *_csc_of_transpose(at))
+        b = gen.CSC(k, n, *_csc_of_transpose(bt))
+        ccp, cri, cv = oracle.spgemm(a, b)
+        dense_r = np.zeros((m, n))
+        for i in range(m):
+            dense_r[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+        dense_c = np.zeros((m, n))
+        mask_c = np.zeros((m, n), bool)
+        for j in range(n):
+            dense_c[cri[ccp[j]:ccp[j + 1]], j] = cv[ccp[j]:ccp[j + 1]]
+            mask_c[cri[ccp[j]:ccp[j + 1]], j] = True
+        mask_r = np.zeros((m, n), bool)
+        for i in range(m):
+            mask_r[i, ci[rp[i]:rp[i + 1]]] = True
+        assert np.array_equal(mask_r, mask_c), "row-wise structure differs from column-wise"
+        assert np.allclose(dense_r, dense_c, rtol=1e-12, atol=1e-12)
+
+
+def _csc_of_transpose(t):
+    """(colptr, rowidx, val) of the CSC form of the transpose of CSC matrix t
+    (entries of each output column in ascending row order)."""
+    cols = np.repeat(np.arange(t.ncols), np.diff(t.colptr))
+    order = np.lexsort((cols, t.rowidx))
+    counts = np.bincount(t.rowidx, minlength=t.nrows)
+    cp = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    return cp, cols[order].astype(np.int32), np.asarray(t.val)[order]
