@@ -101,3 +101,22 @@ def test_options_validated_on_host(L):
     st = L.spgemm_symbolic(C.byref(a), C.byref(b), 1, None, None, C.byref(plan),
                            C.addressof(fake), C.byref(nnz))
     assert st == 2
+
+
+def test_rowwise_operands_map_to_the_transposed_column_problem():
+    """CSR arrays are the CSC arrays of the transpose: the row-wise call hands
+    B^T x A^T to the column path with the arrays as they are, and refuses
+    operands whose inner sizes differ before any library call."""
+    import torch
+    from paper_2303_02471_amd import api
+    rp = torch.tensor([0, 1, 3], dtype=torch.int32)
+    ci = torch.tensor([2, 0, 1], dtype=torch.int32)
+    v = torch.tensor([1.0, 2.0, 3.0], dtype=torch.float64)
+    A = api.CsrTensor(2, 3, rp, ci, v)
+    t = A.transpose_csc()
+    assert (t.nrows, t.ncols) == (3, 2) and t.nnz == A.nnz == 3
+    assert t.colptr is rp and t.rowidx is ci and t.val is v
+    B = api.CsrTensor(4, 5, torch.zeros(5, dtype=torch.int32), torch.zeros(0, dtype=torch.int32),
+                      torch.zeros(0, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        api.matmul_rowwise(A, B)
