@@ -177,8 +177,8 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
 }
 
 constexpr int kColWin = 256;  // columns per window of a tile
-constexpr int kNumPer = 4;     // products per thread per pass, product-balanced tiles
-constexpr int kNumPerBig = 6;  // products per thread per pass, chunks of large columns
+constexpr int kNumPer = 2;     // products per thread per pass, product-balanced tiles
+constexpr int kNumPerBig = 8;  // products per thread per pass, chunks of large columns
 
 template <typename V>
 struct NumSmem {
