@@ -4,10 +4,10 @@
 // [t * kProdTile, (t + 1) * kProdTile) of the product space, so every tile has
 // about kProdTile products (plus the tail of its last column).
 //
-// Expansion: one workgroup per tile walks the tile's stored B entries in
-// storage order (they are contiguous) and writes the row of every product --
-// the rows of the A column each entry selects, in storage order -- to the
-// product space. The symbolic accumulators stream these rows.
+// Expansion: one workgroup per kExpandTiles consecutive tiles walks their
+// stored B entries in storage order (they are contiguous) and writes the row
+// of every product -- the rows of the A column each entry selects, in storage
+// order -- to the product space. The symbolic accumulators stream these rows.
 //
 // Numeric: the symbolic phase left, per product, its row (the expansion) and
 // a destination: the rank of its output row inside its column, or for a
@@ -46,13 +46,17 @@ struct ExpSmem {
     int scan_tmp[kBlock / 64 + 1];
 };
 
+// product tiles per expansion workgroup (1, 2, 8 and 16 measured slower)
+constexpr int kExpandTiles = 4;
+
 __global__ __launch_bounds__(kBlock) void k_expand(KArgs a) {
     constexpr int PER = 4;
     __shared__ ExpSmem S;
     if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0))
         return;  // every thread takes the same branch
     const int tid = threadIdx.x;
-    const int g0 = a.tilestart[blockIdx.x], g1 = a.tilestart[blockIdx.x + 1];
+    const int t0 = (int)blockIdx.x * kExpandTiles;
+    const int g0 = a.tilestart[t0], g1 = a.tilestart[min(t0 + kExpandTiles, a.nptiles)];
     int *__restrict__ prow = a.prow;
     int bad = 0;
     for_each_segment(a, g0, g1, [&](int, const Prob &d, int j0, int j1) {
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(KArgs a) {
 
 hipError_t launch_expand(const KArgs &a, hipStream_t s) {
     if (a.nptiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand, dim3(a.nptiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_expand, dim3(ceil_div(a.nptiles, kExpandTiles)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
