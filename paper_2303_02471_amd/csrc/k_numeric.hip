@@ -285,6 +285,9 @@ __device__ __forceinline__ void numeric_tile(const KArgs &a, NumSmem<V> &S, int 
                 base += Ew;
                 __syncthreads();
             }
+            // every thread has read this window's bounds (pb, pe) before the
+            // next window overwrites them, also when no B entry ran the loop
+            __syncthreads();
         }
     });
     if (bad) atomicOr(&a.hdr->err, ERR_GROUP);
