@@ -11,8 +11,10 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 # -ffp-contract=off: every product and sum rounded on its own (no FMA).
 # -fno-fast-math is the default; spelled out so nobody drops it by accident.
+# -fopenmp: only oracle_spgemm_f64_parallel has a parallel region (over
+# columns; every column is still one thread's Algorithm 1).
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-          "-Wall", "-Wextra", "-Werror"]
+          "-fopenmp", "-Wall", "-Wextra", "-Werror"]
 
 
 def build(force: bool = True) -> str:

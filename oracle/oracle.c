@@ -19,6 +19,9 @@
 
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 int oracle_check_csc(int32_t nrows, int32_t ncols, const int32_t *colptr,
                      const int32_t *rowidx) {
@@ -386,4 +389,109 @@ int64_t oracle_hash_size(int64_t maxop) {
     int64_t h = 1;
     while (h <= maxop) h *= 2; /* smallest power of two strictly above maxop */
     return h;
+}
+
+/* Columns of C are independent (Section 2.1): each thread takes whole
+ * columns and runs Algorithm 1 on them with SPA arrays of its own. Two
+ * sweeps, as in the single-threaded pair: the distinct rows of every column
+ * (its SPA flags), a prefix sum into the column pointers, then the values. */
+int oracle_spgemm_f64_parallel(int32_t a_nrows, int32_t a_ncols, const int32_t *a_colptr,
+                               const int32_t *a_rowidx, const double *a_val,
+                               int32_t b_nrows, int32_t b_ncols, const int32_t *b_colptr,
+                               const int32_t *b_rowidx, const double *b_val,
+                               int32_t *c_colptr, int64_t *nnz_cap, int32_t *c_rowidx,
+                               double *c_val, int32_t nthreads, int32_t *threads_used) {
+    int rc = check_pair(a_nrows, a_ncols, a_colptr, a_rowidx, b_nrows, b_ncols,
+                        b_colptr, b_rowidx);
+    if (rc) return rc;
+    size_t m = (size_t)(a_nrows > 0 ? a_nrows : 1);
+    int32_t *count = (int32_t *)malloc(sizeof(int32_t) * (size_t)(b_ncols > 0 ? b_ncols : 1));
+    if (!count) return ORACLE_ENOMEM;
+    int failed = 0, used = 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        used = omp_get_num_threads();
+#endif
+        unsigned char *flag = (unsigned char *)calloc(m, 1);
+        int32_t *touched = (int32_t *)malloc(m * sizeof(int32_t));
+        if (!flag || !touched) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 256)
+            for (int32_t j = 0; j < b_ncols; ++j) {
+                int32_t counter = 0;
+                for (int32_t p = b_colptr[j]; p < b_colptr[j + 1]; ++p) {
+                    int32_t k = b_rowidx[p];
+                    for (int32_t q = a_colptr[k]; q < a_colptr[k + 1]; ++q) {
+                        int32_t i = a_rowidx[q];
+                        if (!flag[i]) { flag[i] = 1; touched[counter++] = i; }
+                    }
+                }
+                for (int32_t r = 0; r < counter; ++r) flag[touched[r]] = 0;
+                count[j] = counter;
+            }
+        }
+        free(flag);
+        free(touched);
+    }
+    if (failed) { free(count); return ORACLE_ENOMEM; }
+    int64_t total = 0;
+    c_colptr[0] = 0;
+    for (int32_t j = 0; j < b_ncols; ++j) {
+        total += count[j];
+        if (total > 2147483647LL) { free(count); return ORACLE_EOVERFLOW; }
+        c_colptr[j + 1] = (int32_t)total;
+    }
+    free(count);
+    if (total > *nnz_cap) { *nnz_cap = total; return ORACLE_EOVERFLOW; }
+    *nnz_cap = total;
+#pragma omp parallel
+    {
+        double *spa_values = (double *)calloc(m, sizeof(double));
+        unsigned char *spa_flags = (unsigned char *)calloc(m, 1);
+        int32_t *spa_indices = (int32_t *)malloc(m * sizeof(int32_t));
+        if (!spa_values || !spa_flags || !spa_indices) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 256)
+            for (int32_t j = 0; j < b_ncols; ++j) {
+                int32_t counter = 0;
+                for (int32_t p = b_colptr[j]; p < b_colptr[j + 1]; ++p) {
+                    int32_t k = b_rowidx[p];
+                    double bkj = b_val[p];
+                    for (int32_t q = a_colptr[k]; q < a_colptr[k + 1]; ++q) {
+                        int32_t i = a_rowidx[q];
+                        double tmp_val = a_val[q] * bkj;
+                        spa_values[i] = spa_values[i] + tmp_val;
+                        if (spa_flags[i] == 0) {
+                            spa_flags[i] = 1;
+                            spa_indices[counter++] = i;
+                        }
+                    }
+                }
+                qsort(spa_indices, (size_t)counter, sizeof(int32_t), cmp_i32);
+                for (int32_t r = 0; r < counter; ++r) {
+                    int32_t i = spa_indices[r];
+                    c_rowidx[c_colptr[j] + r] = i;
+                    c_val[c_colptr[j] + r] = spa_values[i];
+                    spa_values[i] = 0.0;
+                    spa_flags[i] = 0;
+                }
+            }
+        }
+        free(spa_values);
+        free(spa_flags);
+        free(spa_indices);
+    }
+    *threads_used = used;
+    return failed ? ORACLE_ENOMEM : ORACLE_OK;
 }

@@ -115,6 +115,20 @@ int oracle_blocking(int32_t n, const int64_t *op_sorted, int32_t bmin, int32_t b
 /* Section 3.2: hash table size H = 2^k with 2^(k-1) <= maxop < 2^k. */
 int64_t oracle_hash_size(int64_t maxop);
 
+/* The FP64 product of oracle_symbolic + oracle_spgemm_f64 with the columns
+ * spread over `nthreads` OpenMP threads (0: the runtime's default). Each
+ * column is still computed by one thread in Algorithm 1's order, with that
+ * thread's own SPA arrays, so the result equals the single-threaded one bit
+ * for bit. c_colptr [b_ncols + 1] is filled; c_rowidx / c_val must hold
+ * *nnz_cap entries, else ORACLE_EOVERFLOW with *nnz_cap set to nnz(C).
+ * *threads_used receives the thread count of the parallel region. */
+int oracle_spgemm_f64_parallel(int32_t a_nrows, int32_t a_ncols, const int32_t *a_colptr,
+                               const int32_t *a_rowidx, const double *a_val,
+                               int32_t b_nrows, int32_t b_ncols, const int32_t *b_colptr,
+                               const int32_t *b_rowidx, const double *b_val,
+                               int32_t *c_colptr, int64_t *nnz_cap, int32_t *c_rowidx,
+                               double *c_val, int32_t nthreads, int32_t *threads_used);
+
 #ifdef __cplusplus
 }
 #endif

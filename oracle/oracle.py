@@ -15,7 +15,7 @@ import numpy as np
 from . import build as _build
 
 __all__ = [
-    "OracleError", "check_csc", "opcount", "symbolic", "spgemm", "absprod",
+    "OracleError", "bind", "check_csc", "opcount", "symbolic", "spgemm", "spgemm_parallel", "absprod",
     "backward", "sort_columns", "blocking", "hash_size", "csc",
 ]
 
@@ -39,6 +39,14 @@ def _load():
     path = _build.LIB
     if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
         _build.build()
+    _lib = bind(path)
+    return _lib
+
+
+def bind(path):
+    """Declare the oracle's C functions on the shared library at `path` (the
+    built oracle, or a copy built from modified source by a test that checks
+    its pins catch a planted mistake)."""
     lib = C.CDLL(path)
     pair = [_i32, _i32, _I32P, _I32P]
     lib.oracle_check_csc.argtypes = [_i32, _i32, _I32P, _I32P]
@@ -52,13 +60,15 @@ def _load():
     lib.oracle_absprod_f64.argtypes = pair + [_F64P] + pair + [_F64P] + [_I32P, _I32P, _F64P, _I32P]
     lib.oracle_sort_columns.argtypes = [_i32, _I64P, _I32P]
     lib.oracle_blocking.argtypes = [_i32, _I64P, _i32, _i32, _I32P, _I32P]
+    lib.oracle_spgemm_f64_parallel.argtypes = pair + [_F64P] + pair + [_F64P] + [
+        _I32P, C.POINTER(C.c_int64), _I32P, _F64P, _i32, C.POINTER(_i32)]
+    lib.oracle_spgemm_f64_parallel.restype = C.c_int
     lib.oracle_hash_size.argtypes = [C.c_int64]
     lib.oracle_hash_size.restype = C.c_int64
     for name in ("oracle_check_csc", "oracle_opcount", "oracle_symbolic", "oracle_spgemm_f64",
                  "oracle_spgemm_f32", "oracle_backward_f64", "oracle_backward_f32",
                  "oracle_absprod_f64", "oracle_sort_columns", "oracle_blocking"):
         getattr(lib, name).restype = C.c_int
-    _lib = lib
     return lib
 
 
@@ -92,27 +102,28 @@ def opcount(a, b) -> np.ndarray:
     return op
 
 
-def symbolic(a, b) -> np.ndarray:
+def symbolic(a, b, lib=None) -> np.ndarray:
     cp = np.zeros(int(b.ncols) + 1, dtype=np.int32)
-    _rc(_load().oracle_symbolic(*_pat(a), *_pat(b), cp), "symbolic")
+    _rc((lib or _load()).oracle_symbolic(*_pat(a), *_pat(b), cp), "symbolic")
     return cp
 
 
-def spgemm(a, b, precision: str = "f64"):
+def spgemm(a, b, precision: str = "f64", lib=None):
     """C = A x B by Algorithm 1. ``precision`` "f64" upcasts the values and
     works in double; "f32" runs the same loops in single precision.
     Returns (colptr, rowidx, val)."""
-    cp = symbolic(a, b)
+    lib = lib or _load()
+    cp = symbolic(a, b, lib)
     nnz = int(cp[-1])
     ri = np.zeros(nnz, dtype=np.int32)
     if precision == "f64":
         cv = np.zeros(nnz, dtype=np.float64)
-        fn = _load().oracle_spgemm_f64
+        fn = lib.oracle_spgemm_f64
         av = np.ascontiguousarray(a.val, dtype=np.float64)
         bv = np.ascontiguousarray(b.val, dtype=np.float64)
     elif precision == "f32":
         cv = np.zeros(nnz, dtype=np.float32)
-        fn = _load().oracle_spgemm_f32
+        fn = lib.oracle_spgemm_f32
         if a.val.dtype != np.float32 or b.val.dtype != np.float32:
             raise OracleError("f32 twin needs float32 inputs")
         av = np.ascontiguousarray(a.val)
@@ -123,12 +134,35 @@ def spgemm(a, b, precision: str = "f64"):
     return cp, ri, cv
 
 
-def absprod(a, b, c_colptr, c_rowidx):
+def spgemm_parallel(a, b, nthreads: int = 0, nnz_hint: int = 0):
+    """C = A x B in FP64 with whole columns spread over OpenMP threads
+    (0: all host cores); identical to spgemm(a, b). Returns (colptr, rowidx,
+    val, threads_used). nnz_hint sizes the outputs (0: computed first)."""
+    lib = _load()
+    av = np.ascontiguousarray(a.val, dtype=np.float64)
+    bv = np.ascontiguousarray(b.val, dtype=np.float64)
+    cp = np.zeros(int(b.ncols) + 1, dtype=np.int32)
+    cap = C.c_int64(max(int(nnz_hint), 0))
+    used = C.c_int32(0)
+    for _ in range(2):
+        ri = np.zeros(max(cap.value, 1), dtype=np.int32)
+        cv = np.zeros(max(cap.value, 1), dtype=np.float64)
+        rc = lib.oracle_spgemm_f64_parallel(*_pat(a), av, *_pat(b), bv, cp, C.byref(cap), ri, cv,
+                                            int(nthreads), C.byref(used))
+        if rc == 4 and cap.value > len(ri):
+            continue  # sized now: run again with room for nnz(C)
+        _rc(rc, "spgemm_parallel")
+        n = int(cp[-1])
+        return cp, ri[:n], cv[:n], int(used.value)
+    raise OracleError("spgemm_parallel: output size changed between calls")
+
+
+def absprod(a, b, c_colptr, c_rowidx, lib=None):
     """sum_k |A(i,k) B(k,j)| and the number of products, on C's pattern."""
     nnz = int(c_colptr[-1])
     s = np.zeros(nnz, dtype=np.float64)
     t = np.zeros(nnz, dtype=np.int32)
-    _rc(_load().oracle_absprod_f64(*_pat(a), np.ascontiguousarray(a.val, dtype=np.float64),
+    _rc((lib or _load()).oracle_absprod_f64(*_pat(a), np.ascontiguousarray(a.val, dtype=np.float64),
                                    *_pat(b), np.ascontiguousarray(b.val, dtype=np.float64),
                                    np.ascontiguousarray(c_colptr, dtype=np.int32),
                                    np.ascontiguousarray(c_rowidx, dtype=np.int32), s, t),
@@ -136,10 +170,11 @@ def absprod(a, b, c_colptr, c_rowidx):
     return s, t
 
 
-def backward(a, b, c_colptr, c_rowidx, g, precision: str = "f64", want_a=True, want_b=True):
+def backward(a, b, c_colptr, c_rowidx, g, precision: str = "f64", want_a=True, want_b=True,
+             lib=None):
     """Gradients of <G, A x B> w.r.t. the stored values of A and B."""
     dt = np.float64 if precision == "f64" else np.float32
-    fn = getattr(_load(), f"oracle_backward_{precision}")
+    fn = getattr(lib or _load(), f"oracle_backward_{precision}")
     av = np.ascontiguousarray(a.val, dtype=dt)
     bv = np.ascontiguousarray(b.val, dtype=dt)
     gv = np.ascontiguousarray(g, dtype=dt)

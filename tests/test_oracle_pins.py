@@ -396,3 +396,26 @@ def test_f32_twin_matches_f64_within_bound():
     s, t = oracle.absprod(A, B, cp, ri)
     u = 2.0 ** -24
     assert np.all(np.abs(v32.astype(np.float64) - v64) <= (t + 1) * u * s * 1.01 + 1e-30)
+
+
+# --------------------------------------------------------------------------- parallel oracle
+
+@pytest.mark.parametrize("nthreads", [1, 3, 0])
+def test_parallel_oracle_identical(nthreads):
+    """The OpenMP oracle spreads whole columns over threads (each column still
+    Algorithm 1 on one thread): output identical bit for bit, including
+    empty columns, rectangular shapes and a size hint that is too small."""
+    cases = [gen.powerlaw(20000, seed=5), (gen.uniform_z(3000, 7, seed=1),
+                                           gen.uniform_z(3000, 9, seed=2))]
+    for A, B in cases:
+        ref = oracle.spgemm(A, B)
+        for hint in (0, 5):
+            cp, ri, v, used = oracle.spgemm_parallel(A, B, nthreads, nnz_hint=hint)
+            assert used >= 1 and (nthreads == 0 or used == nthreads)
+            assert np.array_equal(cp, ref[0]) and np.array_equal(ri, ref[1])
+            assert np.array_equal(v.view(np.uint64), ref[2].view(np.uint64))
+    A = gen.from_dense(np.array([[1.0, 0.0], [0.0, 0.0], [2.0, 3.0]]))
+    B = gen.from_dense(np.array([[0.0, 1.0, 0.0], [0.0, 2.0, 0.0]]))
+    ref = oracle.spgemm(A, B)
+    cp, ri, v, _ = oracle.spgemm_parallel(A, B, nthreads)
+    assert np.array_equal(cp, ref[0]) and np.array_equal(ri, ref[1]) and np.array_equal(v, ref[2])
