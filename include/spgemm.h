@@ -28,7 +28,10 @@
  * Plans: spgemm_symbolic creates (or refreshes) a plan. The plan borrows the
  * A and B pattern arrays (colptr/rowidx) and the C colptr array: they must stay
  * allocated and unchanged while the plan is used. The plan owns its device
- * workspace and frees it in spgemm_plan_destroy.
+ * workspace (from the allocator of spgemm_set_allocator, by default
+ * stream-ordered hipMallocAsync) and frees it in spgemm_plan_destroy. A plan
+ * may be used on another stream than its last call's: the new call is
+ * ordered after the plan's earlier work without a host wait.
  *
  * Errors: every call returns a status code; nothing aborts or throws across
  * the ABI. On error, outputs are unspecified. Input checks that keep every
@@ -84,6 +87,35 @@ typedef struct {
 } spgemm_csc;
 
 typedef struct spgemm_plan_s *spgemm_plan;
+/* Plans made by spgemm_batched (the same object; destroyed with
+ * spgemm_batch_plan_destroy or spgemm_plan_destroy). */
+typedef spgemm_plan spgemm_batch_plan;
+
+/*
+ * Device memory of plans (workspace, per-product arrays, staging, the
+ * backward view). By default a plan takes it with hipMallocAsync on the
+ * stream of the call that needs it and returns it with hipFreeAsync, in
+ * stream order: growing a plan never waits on the host.
+ *
+ * spgemm_set_allocator installs another source for plans created after the
+ * call (each plan keeps the pair it was created with until it is destroyed):
+ *   alloc(bytes, stream, ctx)    returns device memory of the current device
+ *                                usable by work queued on `stream` from now
+ *                                on, or NULL (the call then fails with
+ *                                SPGEMM_ERR_NO_MEMORY).
+ *   free(ptr, bytes, stream, ctx) returns memory from alloc; `stream` is the
+ *                                one the memory was allocated on, and every
+ *                                use of it by the library has been ordered
+ *                                before the work queued on `stream` so far
+ *                                (stream-ordered caching allocators may hand
+ *                                it out again to later work on that stream).
+ * A stream that plan memory was allocated on must outlive the plan. Passing
+ * NULL for both restores the default; exactly one NULL gives SPGEMM_ERR_NULL.
+ * Host only; thread-safe.
+ */
+typedef void *(*spgemm_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*spgemm_free_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
+spgemm_status spgemm_set_allocator(spgemm_alloc_fn alloc, spgemm_free_fn free_fn, void *ctx);
 
 /* flags */
 #define SPGEMM_VALIDATE 1u /* host-side check of both inputs, including repeated rows per column */
@@ -270,19 +302,23 @@ spgemm_status spgemm_profile_read(spgemm_kernel_time *out_host, int32_t max, int
  * from the device: synchronous). */
 spgemm_status spgemm_plan_get_stats(spgemm_plan plan, spgemm_plan_stats *out);
 
-/* Frees the plan and its workspace (synchronises with the plan's last stream). */
+/* Frees the plan and its workspace (returns the device memory in stream order
+ * behind the plan's last work, then synchronises with that stream). */
 void spgemm_plan_destroy(spgemm_plan plan);
+
+/* Frees a plan made by spgemm_batched (the same as spgemm_plan_destroy). */
+void spgemm_batch_plan_destroy(spgemm_batch_plan plan);
 
 /* Static text for a status code. */
 const char *spgemm_status_string(spgemm_status s);
 
 /*
  * Autotuning. Chooses tuning options for a workload by timing candidate
- * settings of t_esc, t_sort, hash_cap and t_dense (the role of the paper's
- * switch threshold t, Section 3.3, and of its hash-size adaptation, Section
- * 3.2): coordinate descent from the defaults, each candidate timed as
- * symbolic + numeric (best of three runs after a warm-up). Options never
- * change results, so neither does tuning.
+ * settings of t_esc, t_block, t_split, hash_cap and dense_rows (the role of
+ * the paper's switch threshold t, Section 3.3, and of its hash-size
+ * adaptation, Section 3.2): coordinate descent from the defaults, each
+ * candidate timed as symbolic + numeric (best of three runs after a
+ * warm-up). Options never change results, so neither does tuning.
  *   count, A_host, B_host  the problems as for spgemm_batched (count == 1:
  *               a single product); value arrays are needed for the timing.
  *   cache_path  JSON file keyed by device and workload signature, or NULL.

@@ -30,7 +30,12 @@ EXPORTS = (
     "spgemm_plan_get_stats", "spgemm_plan_destroy", "spgemm_status_string", "spgemm_version",
     "spgemm_profile_enable", "spgemm_profile_read", "spgemm_profile_select",
     "spgemm_autotune", "spgemm_tune_key", "spgemm_tune_cache_load", "spgemm_tune_cache_store",
+    "spgemm_set_allocator", "spgemm_batch_plan_destroy",
 )
+
+# device memory callbacks of spgemm_set_allocator
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 
 
 class SpgemmError(RuntimeError):
@@ -99,6 +104,10 @@ def lib() -> C.CDLL:
     L.spgemm_plan_get_stats.argtypes = [vp, C.POINTER(PlanStats)]
     L.spgemm_plan_destroy.argtypes = [vp]
     L.spgemm_plan_destroy.restype = None
+    L.spgemm_batch_plan_destroy.argtypes = [vp]
+    L.spgemm_batch_plan_destroy.restype = None
+    L.spgemm_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
+    L.spgemm_set_allocator.restype = C.c_int
     L.spgemm_status_string.argtypes = [C.c_int]
     L.spgemm_status_string.restype = C.c_char_p
     L.spgemm_profile_enable.argtypes = [C.c_int32]

@@ -5,7 +5,9 @@ product runs in the library's HIP kernels, reached through the C ABI.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -18,8 +20,60 @@ __all__ = [
     "CscTensor", "Plan", "options", "symbolic", "numeric", "matmul", "backward",
     "SpGEMMFunction", "batched_symbolic", "batched_numeric", "batched_matmul",
     "profile_enable", "profile_read", "autotune", "tune_key", "tune_cache_load",
-    "tune_cache_store",
+    "tune_cache_store", "set_allocator",
 ]
+
+
+# ---------------------------------------------------------------- plan memory
+# Plans take their device memory from torch's caching allocator (on the
+# stream of the call), so the library's workspace shows up in torch's memory
+# statistics and reuses its cached blocks. The callbacks stay referenced here
+# for the life of the process.
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # out of memory: the library reports SPGEMM_ERR_NO_MEMORY
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, ctx):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+_TORCH_CALLBACKS = (_lib.ALLOC_FN(_torch_alloc), _lib.FREE_FN(_torch_free))
+_installed = None  # callbacks currently installed in the library (kept alive)
+_plans = weakref.WeakSet()  # live plans, closed before the interpreter exits
+
+
+def set_allocator(alloc=None, free=None):
+    """Device memory of plans created from now on: "torch" (the default of
+    this binding: torch's caching allocator), None (the library's own
+    stream-ordered hipMallocAsync), or a pair of ctypes callbacks
+    (_lib.ALLOC_FN, _lib.FREE_FN) that the caller keeps alive."""
+    global _installed
+    if alloc == "torch":
+        alloc, free = _TORCH_CALLBACKS
+    if alloc is None:
+        st = _lib.lib().spgemm_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None)
+    else:
+        st = _lib.lib().spgemm_set_allocator(alloc, free, None)
+    _lib.check(st, "spgemm_set_allocator")
+    _installed = (alloc, free)
+
+
+def _ensure_allocator():
+    if _installed is None:
+        set_allocator("torch")
+
+
+@atexit.register
+def _close_plans():
+    # plans hand their memory back to torch while torch is still alive
+    for p in list(_plans):
+        try:
+            p.close()
+        except Exception:
+            pass
 
 
 def profile_enable(on: bool = True) -> None:
@@ -129,10 +183,12 @@ class Plan:
     """Owns a library plan and keeps the arrays it borrows alive."""
 
     def __init__(self):
+        _ensure_allocator()
         self.handle = C.c_void_p()
         self.keep = []
         self.dtype = None
         self.nnz = None
+        _plans.add(self)
 
     def stats(self) -> dict:
         s = _lib.PlanStats()

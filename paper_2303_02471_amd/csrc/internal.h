@@ -141,6 +141,8 @@ struct KArgs {
     // lies in [t * kProdTile, (t + 1) * kProdTile).
     int32_t *tilestart;     // [nptiles + 1] first global column of every tile
     int32_t nptiles;
+    long long prod_cap;     // products the product-space arrays hold: the expansion and
+                            // the numeric phase never address beyond (ERR_GROUP instead)
     // Products that are not the first of their output entry ("later"
     // products). The symbolic phase gives each its occurrence index k >= 1
     // and its index among the later products of its column (both stored at

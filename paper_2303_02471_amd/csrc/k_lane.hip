@@ -43,9 +43,10 @@ __global__ __launch_bounds__(kLaneWave) void k_lane(KArgs a) {
     int start = 0;
     for (int b = 0; b < BIN_ESC0 + sub; ++b) start += a.hdr->bin_count[b];
     const int ncols = a.hdr->bin_count[BIN_ESC0 + sub];
-    const int ci = blockIdx.x * kLaneWave + lane;
     int kmax = 0;
-    if (ci < ncols) {
+    // the grid may be planned from an earlier call's column count: every
+    // lane strides over the device count
+    for (int ci = blockIdx.x * kLaneWave + lane; ci < ncols; ci += gridDim.x * kLaneWave) {
         const int g = a.binlist[start + ci].x;
         const int op = a.op[g];
         const long long pbase = a.colprod[g];

@@ -96,8 +96,15 @@ __global__ __launch_bounds__(kBlock) void k_expand(KArgs a) {
                     if (e >= Ew) continue;
                     int row = r[u];
                     if (row < 0 || row >= d.m) {
-                        bad = 1;
+                        bad |= ERR_CSC;
                         row = 0;
+                    }
+                    // the A column lengths (E) and the product offsets (from
+                    // Op_j) agree unless the inputs changed under the plan:
+                    // never write beyond the product space
+                    if (base + e >= a.prod_cap) {
+                        bad |= ERR_GROUP;
+                        continue;
                     }
                     prow[base + e] = row;
                 }
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(KArgs a) {
             __syncthreads();
         }
     });
-    if (bad) atomicOr(&a.hdr->err, ERR_CSC);
+    if (bad) atomicOr(&a.hdr->err, bad);
 }
 
 hipError_t launch_expand(const KArgs &a, hipStream_t s) {
@@ -150,6 +157,13 @@ __device__ __forceinline__ void numeric_window(const KArgs &a, int pid, const Pr
             const int q = s_acp[tt] + ee - s_eoff[tt];
             c[u] = e < Ew ? s_col[tt] : -1;
             pp[u] = pos(tt, ee);
+            // a product beyond the product space (inputs changed under the
+            // plan) is read at its last position and never written
+            if (pp[u] >= a.prod_cap) {
+                pp[u] = a.prod_cap - 1;
+                if (c[u] >= 0) bad = 1;
+                c[u] = -1;
+            }
             y[u] = s_bv[tt];
             x[u] = av[q];
             row[u] = a.prow[pp[u]];  // the expansion's row, read in product order

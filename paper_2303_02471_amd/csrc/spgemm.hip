@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -23,8 +24,26 @@
 
 using namespace spg;
 
+// Device memory of a plan, from the allocator the plan was created with: the
+// caller's (spgemm_set_allocator) or stream-ordered hipMallocAsync. Every
+// buffer remembers the stream it was allocated on; it is freed on that stream
+// after that stream has been made to wait for the plan's last work.
+struct DevAllocator {
+    spgemm_alloc_fn alloc = nullptr;
+    spgemm_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+};
+
 struct spgemm_plan_s {
     int device = -1;
+    DevAllocator allocator;
+    hipEvent_t order_ev = nullptr;  // orders one stream after another (no timing)
     spgemm_dtype dt = SPGEMM_F64;
     bool batched = false;
     int nprob = 0;
@@ -35,8 +54,7 @@ struct spgemm_plan_s {
     bool symbolic_ok = false;
 
     // device workspace (one allocation, carved)
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
+    DevBuf ws;
     Hdr *hdr = nullptr;
     int32_t *op = nullptr, *binw = nullptr, *gnnz = nullptr, *col0s = nullptr;
     int4 *binlist = nullptr;
@@ -46,8 +64,7 @@ struct spgemm_plan_s {
     // per-product arrays (own allocation: the product count is known only
     // after the classification): row and destination of every product, and
     // the later list's occurrence indices and ranks
-    void *prod = nullptr;
-    size_t prod_bytes = 0;
+    DevBuf prod;
     int32_t *prow = nullptr;
     uint32_t *dst = nullptr;
     int32_t *lk = nullptr, *lr = nullptr, *tilestart = nullptr;
@@ -55,8 +72,7 @@ struct spgemm_plan_s {
     long long prod_total = 0;  // products the product-space arrays are carved for
     bool spec_ready = false;   // a planned symbolic launch may be tried
     // staging of the later products for the numeric phase (sized by their count)
-    void *stage = nullptr;
-    size_t stage_bytes = 0;
+    DevBuf stage;
     int32_t *lo = nullptr, *lpid = nullptr, *lkc = nullptr;
     void *lv = nullptr;
     long long later_total = 0;  // products that are not the first of their entry
@@ -86,8 +102,7 @@ struct spgemm_plan_s {
     hipEvent_t fork_ev = nullptr, join_ev[kSide] = {nullptr, nullptr, nullptr};
 
     // backward: row view of B
-    void *bt = nullptr;
-    size_t bt_bytes = 0;
+    DevBuf bt;
     bool bt_ready = false;
     int *bt_err = nullptr;
 
@@ -195,6 +210,55 @@ spgemm_status hip_status(hipError_t e) {
         if (e_ != hipSuccess) return hip_status(e_);   \
     } while (0)
 
+std::mutex g_alloc_mu;
+DevAllocator g_alloc;  // process-wide choice for plans created from now on
+
+DevAllocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+// stream `later` waits for the work queued so far on `earlier` (no host wait)
+hipError_t order_after(spgemm_plan p, hipStream_t later, hipStream_t earlier) {
+    if (later == earlier) return hipSuccess;
+    if (!p->order_ev) {
+        hipError_t e = hipEventCreateWithFlags(&p->order_ev,
+                                               hipEventDisableTiming | hipEventReleaseToDevice);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(p->order_ev, earlier);
+    if (e != hipSuccess) return e;
+    return hipStreamWaitEvent(later, p->order_ev, 0);
+}
+
+// Releases b (its last use is ordered before the end of stream `s`).
+void dev_free(spgemm_plan p, DevBuf &b, hipStream_t s) {
+    if (!b.ptr) return;
+    (void)order_after(p, b.stream, s);
+    if (p->allocator.free) p->allocator.free(b.ptr, b.bytes, b.stream, p->allocator.ctx);
+    else (void)hipFreeAsync(b.ptr, b.stream);
+    b = DevBuf{};
+}
+
+// Replaces b by `bytes` of device memory usable in stream order on `s`
+// (contents undefined). The old buffer's last use is ordered before the end
+// of `s`, so nothing waits on the host.
+spgemm_status dev_alloc(spgemm_plan p, DevBuf &b, size_t bytes, hipStream_t s) {
+    dev_free(p, b, s);
+    void *ptr = nullptr;
+    if (p->allocator.alloc) {
+        ptr = p->allocator.alloc(bytes, s, p->allocator.ctx);
+    } else if (hipMallocAsync(&ptr, bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+    }
+    if (!ptr) return SPGEMM_ERR_NO_MEMORY;
+    b.ptr = ptr;
+    b.bytes = bytes;
+    b.stream = s;
+    return SPGEMM_OK;
+}
+
 spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flags) {
     int t_esc = 256, t_dense = 1, dense_rows = 0, cap = 0, t_split = 2048, t_block = 0;
     flags = 0;
@@ -254,7 +318,7 @@ spgemm_status validate_host(const spgemm_csc *m) {
 }
 
 // carve the workspace for the plan's current sizes; grows the allocation
-spgemm_status ensure_workspace(spgemm_plan p) {
+spgemm_status ensure_workspace(spgemm_plan p, hipStream_t s) {
     const size_t n = (size_t)std::max(p->ncols, 1);
     p->nblk = ceil_div(std::max(p->ncols, 1), kScanBlock);
     p->nbsum = p->nblk + 2;
@@ -279,18 +343,11 @@ spgemm_status ensure_workspace(spgemm_plan p) {
     const size_t o_ttot = take(8 * (size_t)std::max(p->ntiles, 1));
     const size_t o_tmax = take(4 * (size_t)std::max(p->ntiles, 1));
     const size_t need = off;
-    if (need > p->ws_bytes) {
-        if (p->ws) {
-            if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
-            (void)hipFree(p->ws);
-            p->ws = nullptr;
-            p->ws_bytes = 0;
-        }
-        if (hipMalloc(&p->ws, need) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
-        p->ws_bytes = need;
+    if (need > p->ws.bytes) {
+        if (spgemm_status st = dev_alloc(p, p->ws, need, s)) return st;
         p->table_dev_copy.clear();
     }
-    char *b = (char *)p->ws;
+    char *b = (char *)p->ws.ptr;
     p->hdr = (Hdr *)(b + o_hdr);
     p->op = (int32_t *)(b + o_op);
     p->binw = (int32_t *)(b + o_binw);
@@ -353,6 +410,7 @@ KArgs make_args(spgemm_plan p) {
     a.dst = p->dst;
     a.tilestart = p->tilestart;
     a.nptiles = p->nptiles;
+    a.prod_cap = p->prod_total;
     a.lk = p->lk;
     a.lr = p->lr;
     a.gcp = p->gcp;
@@ -575,26 +633,19 @@ hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
 }
 
 // Product-space arrays for `total` products (the allocation only grows).
-spgemm_status ensure_products(spgemm_plan p, unsigned long long total) {
+spgemm_status ensure_products(spgemm_plan p, unsigned long long total, hipStream_t s) {
     const size_t P = (size_t)std::max<unsigned long long>(total, 1);
     const size_t q1 = align_up(4 * P, 256);
     p->nptiles = (int)(total / kProdTile) + 1;
     const size_t pneed = 4 * q1 + 4 * ((size_t)p->nptiles + 1);
-    if (pneed > p->prod_bytes) {
-        if (p->prod) {
-            if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
-            (void)hipFree(p->prod);
-        }
-        p->prod = nullptr;
-        p->prod_bytes = 0;
-        if (hipMalloc(&p->prod, pneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
-        p->prod_bytes = pneed;
-    }
-    p->prow = (int32_t *)p->prod;
-    p->dst = (uint32_t *)((char *)p->prod + q1);
-    p->lk = (int32_t *)((char *)p->prod + 2 * q1);
-    p->lr = (int32_t *)((char *)p->prod + 3 * q1);
-    p->tilestart = (int32_t *)((char *)p->prod + 4 * q1);
+    if (pneed > p->prod.bytes)
+        if (spgemm_status st = dev_alloc(p, p->prod, pneed, s)) return st;
+    char *base = (char *)p->prod.ptr;
+    p->prow = (int32_t *)base;
+    p->dst = (uint32_t *)(base + q1);
+    p->lk = (int32_t *)(base + 2 * q1);
+    p->lr = (int32_t *)(base + 3 * q1);
+    p->tilestart = (int32_t *)(base + 4 * q1);
     p->prod_total = (long long)total;
     return SPGEMM_OK;
 }
@@ -617,7 +668,7 @@ struct FusedOut {
 spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4> &tiles_host,
                             bool spec, bool *retry, FusedOut *fo) {
     *retry = false;
-    spgemm_status st = ensure_workspace(p);
+    spgemm_status st = ensure_workspace(p, s);
     if (st) return st;
     if (p->nprob > 1) {
         std::vector<int32_t> c0(p->nprob + 1);
@@ -665,7 +716,7 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         const int err = p->hdr_host.err;
         if (err & ERR_CSC) return SPGEMM_ERR_CSC;
         if (err & ERR_OPOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
-        if ((st = ensure_products(p, p->hdr_host.total_op))) return st;
+        if ((st = ensure_products(p, p->hdr_host.total_op, s))) return st;
     }
     if (p->ncols > 0) {
         const KArgs al = args();
@@ -720,18 +771,16 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
     const size_t o_pid = align_up(4 * NL, 256), o_k = o_pid + align_up(4 * NL, 256);
     const size_t o_v = o_k + align_up(4 * NL, 256);
     const size_t sneed = o_v + vsz * NL;
-    if (sneed > p->stage_bytes) {
-        if (fo && fo->queued) (void)hipStreamSynchronize(s);  // the queued phase uses it
-        if (p->stage) (void)hipFree(p->stage);
-        p->stage = nullptr;
-        p->stage_bytes = 0;
-        if (hipMalloc(&p->stage, sneed) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
-        p->stage_bytes = sneed;
+    if (sneed > p->stage.bytes) {
+        // a numeric phase queued behind this pass still reads the old
+        // staging: it is released in stream order behind it
+        if ((st = dev_alloc(p, p->stage, sneed, s))) return st;
     }
-    p->lo = (int32_t *)p->stage;
-    p->lpid = (int32_t *)((char *)p->stage + o_pid);
-    p->lkc = (int32_t *)((char *)p->stage + o_k);
-    p->lv = (char *)p->stage + o_v;
+    char *sb = (char *)p->stage.ptr;
+    p->lo = (int32_t *)sb;
+    p->lpid = (int32_t *)(sb + o_pid);
+    p->lkc = (int32_t *)(sb + o_k);
+    p->lv = sb + o_v;
     if (p->ncols == 0) {
         // no columns at all: every problem's column pointer is {0}
         for (int i = 0; i < p->nprob; ++i)
@@ -840,17 +889,20 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
     spgemm_plan p = get_or_new_plan(plan_inout);
     if (!p) return SPGEMM_ERR_NO_MEMORY;
     const bool fresh = (*plan_inout == nullptr);
+    if (fresh) p->allocator = current_allocator();
     p->dt = dt;
     p->batched = batched;
     p->nprob = count;
     p->tune = tune;
     p->flags = flags;
     p->probs = std::move(probs);
-    // 32-bit sort keys hold rows below 2^20
+    // 32-bit sort keys (row << 12 | position) hold rows below 2^20 - 1: at
+    // m = 2^20 the key of row 2^20 - 1 at position 4095 would equal the
+    // all-ones padding key
     p->wide_keys = false;
     p->wide_esc = false;
     for (const Prob &q : p->probs) {
-        p->wide_keys |= q.m > (1 << 20);
+        p->wide_keys |= q.m >= (1 << 20);
         p->wide_esc |= q.m >= (1 << 24) - 1;
     }
     p->ncols = (int)ncols;
@@ -870,6 +922,9 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
         if (fresh) spgemm_plan_destroy(p);
         return hip_status(e);
     }
+    // the plan's earlier work (possibly on another stream) comes first
+    if (!fresh && p->last_stream != s)
+        if (hipError_t e = order_after(p, s, p->last_stream)) return hip_status(e);
     st = run_symbolic(p, s, tiles, fo);
     p->last_stream = s;
     if (st) {
@@ -1019,18 +1074,12 @@ spgemm_status spgemm_backward(spgemm_plan p, const void *A_val, const void *B_va
                  o_scr = carve(8 * (size_t)nbs), o_scr2 = carve(8 * (size_t)nbs2),
                  o_err = carve(sizeof(int));
     const size_t need = off;
-    if (need > p->bt_bytes) {
-        if (p->bt) {
-            (void)hipStreamSynchronize(p->last_stream);
-            (void)hipFree(p->bt);
-        }
-        p->bt = nullptr;
-        p->bt_bytes = 0;
+    if (need > p->bt.bytes) {
         p->bt_ready = false;
-        if (hipMalloc(&p->bt, need) != hipSuccess) return SPGEMM_ERR_NO_MEMORY;
-        p->bt_bytes = need;
+        SPG_TRY(order_after(p, s, p->last_stream));
+        if (spgemm_status st = dev_alloc(p, p->bt, need, s)) return st;
     }
-    char *b = (char *)p->bt;
+    char *b = (char *)p->bt.ptr;
     BwBuild bb{};
     bb.pofs = (long long *)(b + o_pofs);
     bb.cb = (int32_t *)(b + o_cb);
@@ -1147,7 +1196,14 @@ spgemm_status spgemm_profile_read(spgemm_kernel_time *out, int32_t max, int32_t 
 
 void spgemm_plan_destroy(spgemm_plan p) {
     if (!p) return;
-    if (p->last_stream || p->ws) (void)hipStreamSynchronize(p->last_stream);
+    // every use of the plan's buffers is ordered before the end of its last
+    // stream; they are released in stream order behind it
+    const hipStream_t s = p->last_stream;
+    dev_free(p, p->prod, s);
+    dev_free(p, p->stage, s);
+    dev_free(p, p->ws, s);
+    dev_free(p, p->bt, s);
+    (void)hipStreamSynchronize(s);
     for (int i = 0; i < spgemm_plan_s::kSide; ++i) {
         if (p->side[i]) {
             (void)hipStreamSynchronize(p->side[i]);
@@ -1156,12 +1212,20 @@ void spgemm_plan_destroy(spgemm_plan p) {
         if (p->join_ev[i]) (void)hipEventDestroy(p->join_ev[i]);
     }
     if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
-    if (p->prod) (void)hipFree(p->prod);
-    if (p->stage) (void)hipFree(p->stage);
-    if (p->ws) (void)hipFree(p->ws);
-    if (p->bt) (void)hipFree(p->bt);
+    if (p->order_ev) (void)hipEventDestroy(p->order_ev);
     if (p->pinned) (void)hipHostFree(p->pinned);
     delete p;
+}
+
+void spgemm_batch_plan_destroy(spgemm_batch_plan p) { spgemm_plan_destroy(p); }
+
+spgemm_status spgemm_set_allocator(spgemm_alloc_fn alloc, spgemm_free_fn free_fn, void *ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return SPGEMM_ERR_NULL;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.free = free_fn;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return SPGEMM_OK;
 }
 
 }  // extern "C"

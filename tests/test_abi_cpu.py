@@ -120,3 +120,17 @@ def test_rowwise_operands_map_to_the_transposed_column_problem():
                       torch.zeros(0, dtype=torch.float64))
     with pytest.raises(ValueError):
         api.matmul_rowwise(A, B)
+
+
+def test_set_allocator_arguments_checked_on_host(L):
+    """spgemm_set_allocator takes both callbacks or neither (host only)."""
+    f = _lib.ALLOC_FN(lambda n, s, c: None)
+    g = _lib.FREE_FN(lambda p, n, s, c: None)
+    assert L.spgemm_set_allocator(f, _lib.FREE_FN(), None) == 1
+    assert L.spgemm_set_allocator(_lib.ALLOC_FN(), g, None) == 1
+    assert L.spgemm_set_allocator(f, g, None) == 0
+    # back to the library's own stream-ordered allocator
+    assert L.spgemm_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None) == 0
+    L.spgemm_batch_plan_destroy(None)  # no-op
+    from paper_2303_02471_amd import api
+    api._installed = None  # the binding installs its own again on the next plan

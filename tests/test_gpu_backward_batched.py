@@ -205,13 +205,14 @@ def test_plan_reuse_new_values():
 
 def test_batched_numeric_graph_replay():
     """Capture the batched numeric phase in a HIP graph; replay it several times
-    with eager work in between; every replay equals the eager result."""
+    with new values copied into the captured inputs and eager work in between;
+    every replay equals the oracle's product on that replay's values."""
     _say("graph replay of batched numeric")
+    rng = np.random.default_rng(55)
     probs = _batch(10, seed=5, nmax=2000)
     pairs = [(api.CscTensor.from_host(a), api.CscTensor.from_host(b)) for a, b in probs]
     outs, plan = api.batched_matmul(pairs, return_plan=True)
     torch.cuda.synchronize()
-    ref = [o.val.clone() for o in outs]
     ris = [o.rowidx for o in outs]
     vals = [torch.zeros_like(o.val) for o in outs]
     api.batched_numeric(plan, pairs, ris, vals)  # uploads the pointer table once
@@ -224,13 +225,23 @@ def test_batched_numeric_graph_replay():
             api.batched_numeric(plan, pairs, ris, vals)
     torch.cuda.current_stream().wait_stream(s)
     for r in range(4):
+        new_probs = []
+        for (a, b), (at, bt) in zip(probs, pairs):
+            av = rng.uniform(-1, 1, a.nnz)
+            bv = rng.uniform(-1, 1, b.nnz)
+            at.val.copy_(torch.from_numpy(av))
+            bt.val.copy_(torch.from_numpy(bv))
+            new_probs.append((gen.CSC(a.nrows, a.ncols, a.colptr, a.rowidx, av),
+                              gen.CSC(b.nrows, b.ncols, b.colptr, b.rowidx, bv)))
         for v in vals:
             v.zero_()
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        for i, (v, rv) in enumerate(zip(vals, ref)):
-            assert torch.equal(v, rv), f"replay {r} problem {i}"
+        for i, ((a, b), v, ri) in enumerate(zip(new_probs, vals, ris)):
+            ocp, ori, ov = oracle.spgemm(a, b)
+            assert np.array_equal(ri.cpu().numpy(), ori), f"replay {r} problem {i}: rows"
+            assert_values_exact(v.cpu().numpy(), ov, f"replay {r} problem {i}")
         # eager work between replays
         _ = gpu_product(*probs[0])
 
@@ -289,7 +300,8 @@ def test_validate_flag_detects_repeated_rows():
 def test_forward_backward_graph_replay():
     """Numeric forward and backward of one plan captured in a HIP graph; the
     graph is replayed with new values of A, B and G copied into the captured
-    inputs, eager work in between; every replay equals the eager result."""
+    inputs, eager work in between; every replay's C, dA and dB equal the
+    oracle's on that replay's values (FP32 twin, bit for bit)."""
     _say("graph replay of numeric forward + backward, FP32 n=3000")
     rng = np.random.default_rng(31)
     A = gen.uniform_z(3000, 6, seed=31, dist="normal", dtype=np.float32)
@@ -300,6 +312,8 @@ def test_forward_backward_graph_replay():
     dA, dB = torch.empty_like(At.val), torch.empty_like(Bt.val)
     api.backward(plan, At.val, Bt.val, Cm.rowidx, G, out=(dA, dB))  # builds the view
     torch.cuda.synchronize()
+    ocp = Cm.colptr.cpu().numpy()
+    ori = Cm.rowidx.cpu().numpy()
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -309,21 +323,26 @@ def test_forward_backward_graph_replay():
             api.backward(plan, At.val, Bt.val, Cm.rowidx, G, out=(dA, dB))
     torch.cuda.current_stream().wait_stream(s)
     for r in range(4):
-        At.val.copy_(torch.from_numpy(rng.standard_normal(A.nnz).astype(np.float32)))
-        Bt.val.copy_(torch.from_numpy(rng.standard_normal(B.nnz).astype(np.float32)))
-        G.copy_(torch.from_numpy(rng.standard_normal(Cm.nnz).astype(np.float32)))
+        av = rng.standard_normal(A.nnz).astype(np.float32)
+        bv = rng.standard_normal(B.nnz).astype(np.float32)
+        gv = rng.standard_normal(Cm.nnz).astype(np.float32)
+        At.val.copy_(torch.from_numpy(av))
+        Bt.val.copy_(torch.from_numpy(bv))
+        G.copy_(torch.from_numpy(gv))
         Cm.val.zero_()
         dA.zero_()
         dB.zero_()
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        got = (Cm.val.clone(), dA.clone(), dB.clone())
-        # eager work between replays, and the eager reference
-        api.numeric(plan, At.val, Bt.val, Cm.rowidx, Cm.val)
-        eA, eB = api.backward(plan, At.val, Bt.val, Cm.rowidx, G)
-        torch.cuda.synchronize()
-        assert torch.equal(got[0], Cm.val), f"replay {r}: C"
-        assert torch.equal(got[1], eA), f"replay {r}: dA"
-        assert torch.equal(got[2], eB), f"replay {r}: dB"
+        An = gen.CSC(A.nrows, A.ncols, A.colptr, A.rowidx, av)
+        Bn = gen.CSC(B.nrows, B.ncols, B.colptr, B.rowidx, bv)
+        wcp, wri, wv = oracle.spgemm(An, Bn, "f32")
+        assert np.array_equal(ocp, wcp) and np.array_equal(ori, wri), f"replay {r}: structure"
+        assert_values_exact(Cm.val.cpu().numpy(), wv, f"replay {r}: C")
+        odA, odB = oracle.backward(An, Bn, wcp, wri, gv, "f32")
+        assert_values_exact(dA.cpu().numpy(), odA, f"replay {r}: dA")
+        assert_values_exact(dB.cpu().numpy(), odB, f"replay {r}: dB")
+        # eager work between replays
+        _ = gpu_product(A, B, dtype=np.float32)
     plan.close()
