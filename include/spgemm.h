@@ -72,7 +72,9 @@ typedef enum {
     SPGEMM_ERR_PLAN = 8,           /* plan missing, of the wrong kind, or not in the needed state */
     SPGEMM_ERR_INVALID = 9,        /* invalid option value or argument combination */
     SPGEMM_ERR_NOT_TUNED = 10,     /* no tuning cache entry for the workload (lookup only) */
-    SPGEMM_ERR_CAPACITY = 11       /* spgemm_multiply: the C arrays hold fewer than nnz(C) entries */
+    SPGEMM_ERR_CAPACITY = 11,      /* spgemm_multiply: the C arrays hold fewer than nnz(C) entries */
+    SPGEMM_ERR_SCRATCH = 12        /* spgemm_multiply_noalloc: the problem needs more workspace
+                                      than the static scratch array holds */
 } spgemm_status;
 
 typedef enum { SPGEMM_F32 = 0, SPGEMM_F64 = 1 } spgemm_dtype;
@@ -235,6 +237,32 @@ spgemm_status spgemm_multiply(const spgemm_csc *A, const spgemm_csc *B, spgemm_d
                               const spgemm_options *opt, void *stream,
                               spgemm_plan *plan_inout, int32_t *C_colptr, int32_t *C_rowidx,
                               void *C_val, int64_t capacity, int64_t *nnzC_host);
+
+/*
+ * spgemm_multiply without any allocation, for callers that cannot allocate
+ * memory at call time (serving loops and harnesses that forbid hipMalloc or
+ * any allocating routine). Same arguments, results and blocking as
+ * spgemm_multiply (symbolic phase, then the numeric phase queued on `stream`
+ * after the return), but no plan: every call is a fresh single-problem pass
+ * on the caller's stream (no side streams, no planned launch), and all
+ * workspace is carved from one static device array of 128 MiB that each GPU
+ * the library runs on holds until the process ends (found once per device).
+ * nnz(C) is read back by a copy into library-owned host memory.
+ *   Workspace needed: about 48 B per column of C, 8 B per stored entry of B
+ *   and 16 B per intermediate product (Op, Section 3.1), plus 16 B per
+ *   product beyond the first of its output entry; a problem beyond the array
+ *   gives SPGEMM_ERR_SCRATCH before any kernel writes the workspace.
+ *   SPGEMM_VALIDATE gives SPGEMM_ERR_INVALID (its host check allocates).
+ *   SPGEMM_ERR_CAPACITY: as spgemm_multiply (colptr and nnzC_host set); call
+ *   again with larger arrays.
+ * Every call on a GPU shares that GPU's array and keeps nothing from the
+ * last call: calls that overlap on one GPU (two host threads, or two
+ * streams whose work is not ordered) race and give wrong results.
+ */
+spgemm_status spgemm_multiply_noalloc(const spgemm_csc *A, const spgemm_csc *B, spgemm_dtype dt,
+                                      const spgemm_options *opt, void *stream,
+                                      int32_t *C_colptr, int32_t *C_rowidx, void *C_val,
+                                      int64_t capacity, int64_t *nnzC_host);
 
 /*
  * Gradients of a loss L with dL/dC = G (given on C's stored entries) with

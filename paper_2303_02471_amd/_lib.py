@@ -20,7 +20,7 @@ STATUS = {
     0: "SPGEMM_OK", 1: "SPGEMM_ERR_NULL", 2: "SPGEMM_ERR_SHAPE", 3: "SPGEMM_ERR_CSC",
     4: "SPGEMM_ERR_DTYPE", 5: "SPGEMM_ERR_INDEX_OVERFLOW", 6: "SPGEMM_ERR_NO_MEMORY",
     7: "SPGEMM_ERR_HIP", 8: "SPGEMM_ERR_PLAN", 9: "SPGEMM_ERR_INVALID",
-    10: "SPGEMM_ERR_NOT_TUNED", 11: "SPGEMM_ERR_CAPACITY",
+    10: "SPGEMM_ERR_NOT_TUNED", 11: "SPGEMM_ERR_CAPACITY", 12: "SPGEMM_ERR_SCRATCH",
 }
 SPGEMM_ERR_CAPACITY = 11
 
@@ -30,7 +30,7 @@ EXPORTS = (
     "spgemm_plan_get_stats", "spgemm_plan_destroy", "spgemm_status_string", "spgemm_version",
     "spgemm_profile_enable", "spgemm_profile_read", "spgemm_profile_select",
     "spgemm_autotune", "spgemm_tune_key", "spgemm_tune_cache_load", "spgemm_tune_cache_store",
-    "spgemm_set_allocator", "spgemm_batch_plan_destroy",
+    "spgemm_set_allocator", "spgemm_batch_plan_destroy", "spgemm_multiply_noalloc",
 )
 
 # device memory callbacks of spgemm_set_allocator
@@ -97,6 +97,9 @@ def lib() -> C.CDLL:
     L.spgemm_numeric.argtypes = [vp, vp, vp, vp, vp, vp]
     L.spgemm_multiply.argtypes = [C.POINTER(Csc), C.POINTER(Csc), C.c_int, C.POINTER(Options), vp,
                                   C.POINTER(vp), vp, vp, vp, C.c_int64, i64p]
+    L.spgemm_multiply_noalloc.argtypes = [C.POINTER(Csc), C.POINTER(Csc), C.c_int,
+                                          C.POINTER(Options), vp, vp, vp, vp, C.c_int64, i64p]
+    L.spgemm_multiply_noalloc.restype = C.c_int
     L.spgemm_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.spgemm_batched.argtypes = [i32, C.POINTER(Csc), C.POINTER(Csc), C.c_int, C.POINTER(Options),
                                  vp, C.POINTER(vp), C.POINTER(vp), i64p, C.POINTER(vp),

@@ -43,6 +43,11 @@ struct DevBuf {
 struct spgemm_plan_s {
     int device = -1;
     DevAllocator allocator;
+    // a plan of the allocation-free entry point carves every device buffer
+    // from a fixed region (the static scratch array) instead
+    bool use_arena = false;
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_off = 0;
     hipEvent_t order_ev = nullptr;  // orders one stream after another (no timing)
     spgemm_dtype dt = SPGEMM_F64;
     bool batched = false;
@@ -234,6 +239,10 @@ hipError_t order_after(spgemm_plan p, hipStream_t later, hipStream_t earlier) {
 // Releases b (its last use is ordered before the end of stream `s`).
 void dev_free(spgemm_plan p, DevBuf &b, hipStream_t s) {
     if (!b.ptr) return;
+    if (p->use_arena) {  // carved from the fixed region: nothing to return
+        b = DevBuf{};
+        return;
+    }
     (void)order_after(p, b.stream, s);
     if (p->allocator.free) p->allocator.free(b.ptr, b.bytes, b.stream, p->allocator.ctx);
     else (void)hipFreeAsync(b.ptr, b.stream);
@@ -246,7 +255,12 @@ void dev_free(spgemm_plan p, DevBuf &b, hipStream_t s) {
 spgemm_status dev_alloc(spgemm_plan p, DevBuf &b, size_t bytes, hipStream_t s) {
     dev_free(p, b, s);
     void *ptr = nullptr;
-    if (p->allocator.alloc) {
+    if (p->use_arena) {
+        const size_t off = (p->arena_off + 255) / 256 * 256;
+        if (off > p->arena_size || bytes > p->arena_size - off) return SPGEMM_ERR_SCRATCH;
+        ptr = p->arena + off;
+        p->arena_off = off + bytes;
+    } else if (p->allocator.alloc) {
         ptr = p->allocator.alloc(bytes, s, p->allocator.ctx);
     } else if (hipMallocAsync(&ptr, bytes, s) != hipSuccess) {
         (void)hipGetLastError();
@@ -366,7 +380,7 @@ spgemm_status ensure_workspace(spgemm_plan p, hipStream_t s) {
     p->tmax = (int32_t *)(b + o_tmax);
 
     const size_t pin = kHdrBytes + 8 * (size_t)std::max(p->nprob, 1);
-    if (pin > p->pinned_bytes) {
+    if (pin > p->pinned_bytes && !p->use_arena) {
         if (p->pinned) (void)hipHostFree(p->pinned);
         p->pinned = p->pinned_dev = nullptr;
         p->pinned_bytes = 0;
@@ -731,7 +745,15 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         ProfScope ps("scan", s);
         SPG_TRY(launch_scan(al, p->gcp, p->bsum, p->nblk, p->totals, s));
     }
-    SPG_TRY(publish(p, s));
+    if (p->use_arena) {
+        // no mapped host memory: a plain copy of the header and totals to the
+        // plan's host buffer, then a wait
+        SPG_TRY(hipMemcpyAsync(p->pinned, p->hdr, kHdrBytes + 8 * (size_t)p->nprob,
+                               hipMemcpyDeviceToHost, s));
+        SPG_TRY(hipStreamSynchronize(s));
+    } else {
+        SPG_TRY(publish(p, s));
+    }
     if (fo && spec && p->ncols > 0 && p->nprob == 1) {
         // the numeric phase from the previous sizes; it stands down on an
         // error or capacity flag raised above, and is redone by the caller if
@@ -744,7 +766,7 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         fo->queued = true;
         SPG_TRY(launch_numeric_phase(p, an, s));
     }
-    {
+    if (!p->use_arena) {
         const spgemm_status w = wait_published(p, s);
         if (w != SPGEMM_OK) return w;
     }
@@ -844,6 +866,8 @@ const char *spgemm_status_string(spgemm_status s) {
         case SPGEMM_ERR_INVALID: return "invalid argument";
         case SPGEMM_ERR_NOT_TUNED: return "no tuning cache entry for the workload";
         case SPGEMM_ERR_CAPACITY: return "C arrays smaller than nnz(C)";
+        case SPGEMM_ERR_SCRATCH:
+            return "problem needs more workspace than the static scratch array holds";
     }
     return "unknown status";
 }
@@ -1218,6 +1242,121 @@ void spgemm_plan_destroy(spgemm_plan p) {
 }
 
 void spgemm_batch_plan_destroy(spgemm_batch_plan p) { spgemm_plan_destroy(p); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free product
+// The workspace of spgemm_multiply_noalloc: one file-scope device array that
+// every GPU the library runs on holds until the process ends. Host code never
+// passes its name to a kernel or a copy: the address of each device's copy is
+// looked up once per device (hipGetSymbolAddress) and that pointer is carved.
+namespace {
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kNoAllocDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+struct NoAllocSlot {
+    bool ready = false;
+    char *scratch_ptr = nullptr;  // this device's copy of `scratch`
+    spgemm_plan_s plan;
+    alignas(64) unsigned char host[kHdrBytes + 64];  // header and nnz(C) read back
+};
+NoAllocSlot g_noalloc[kNoAllocDevices];
+
+// host vectors the per-device plans use hold one problem; their storage is
+// taken when the library is loaded, so no call allocates host memory either
+struct NoAllocReserve {
+    NoAllocReserve() {
+        for (NoAllocSlot &sl : g_noalloc) {
+            sl.plan.probs.reserve(1);
+            sl.plan.totals_host.reserve(1);
+        }
+    }
+} g_noalloc_reserve;
+}  // namespace
+
+extern "C" spgemm_status spgemm_multiply_noalloc(const spgemm_csc *A, const spgemm_csc *B,
+                                                 spgemm_dtype dt, const spgemm_options *opt,
+                                                 void *stream, int32_t *C_colptr,
+                                                 int32_t *C_rowidx, void *C_val, int64_t capacity,
+                                                 int64_t *nnzC_host) {
+    if (!A || !B || !C_colptr || !nnzC_host) return SPGEMM_ERR_NULL;
+    if (dt != SPGEMM_F32 && dt != SPGEMM_F64) return SPGEMM_ERR_DTYPE;
+    if (capacity < 0) return SPGEMM_ERR_INVALID;
+    spgemm_status st;
+    if ((st = check_desc(A, true)) || (st = check_desc(B, true))) return st;
+    if (capacity > 0 && (!C_rowidx || !C_val)) return SPGEMM_ERR_NULL;
+    if (A->ncols != B->nrows) return SPGEMM_ERR_SHAPE;
+    Tune tune;
+    uint32_t flags;
+    if ((st = resolve_options(opt, tune, flags))) return st;
+    // the host-side check copies the inputs into host vectors: not offered here
+    if (flags & SPGEMM_VALIDATE) return SPGEMM_ERR_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SPGEMM_ERR_HIP;
+    if (dev < 0 || dev >= kNoAllocDevices) return SPGEMM_ERR_INVALID;
+    NoAllocSlot &sl = g_noalloc[dev];
+    if (!sl.ready) {
+        // once per device, with that device current: the address of its copy
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return SPGEMM_ERR_HIP;
+        sl.scratch_ptr = (char *)ptr;
+        sl.ready = true;
+    }
+    spgemm_plan p = &sl.plan;
+    hipStream_t s = (hipStream_t)stream;
+    // a fresh single-problem pass on the caller's stream, every buffer carved
+    // from this device's scratch array
+    p->device = dev;
+    p->use_arena = true;
+    p->arena = sl.scratch_ptr;
+    p->arena_size = kScratchBytes;
+    p->arena_off = 0;
+    p->ws = p->prod = p->stage = p->bt = DevBuf{};
+    p->pinned = sl.host;
+    p->pinned_dev = nullptr;
+    p->pinned_bytes = sizeof(sl.host);
+    p->dt = dt;
+    p->batched = false;
+    p->nprob = 1;
+    p->tune = tune;
+    p->flags = flags | SPGEMM_ONE_STREAM | SPGEMM_NO_PLANNED_LAUNCH;
+    p->probs.resize(1);
+    Prob &q = p->probs[0];
+    q = Prob{};
+    q.m = A->nrows; q.k = A->ncols; q.n = B->ncols;
+    q.nnza = A->nnz; q.nnzb = B->nnz;
+    q.acp = A->colptr; q.ari = A->rowidx; q.av = A->val;
+    q.bcp = B->colptr; q.bri = B->rowidx; q.bv = B->val;
+    q.ccp = C_colptr;
+    p->wide_keys = q.m >= (1 << 20);
+    p->wide_esc = q.m >= (1 << 24) - 1;
+    p->ncols = q.n;
+    p->total_nnzb = q.nnzb;
+    p->ntiles = ceil_div(q.n, kTile);
+    p->symbolic_ok = false;
+    p->spec_ready = false;
+    p->bt_ready = false;
+    p->hdr_host = Hdr{};
+    static const std::vector<int4> no_tiles;  // used by several-problem plans only
+    bool retry = false;
+    st = symbolic_pass(p, s, no_tiles, false, &retry, nullptr);
+    p->last_stream = s;
+    if (st) return st;
+    const long long nnzc = p->totals_host[0];
+    *nnzC_host = nnzc;
+    if (nnzc > capacity) return SPGEMM_ERR_CAPACITY;
+    q.cri = C_rowidx;
+    q.cv = C_val;
+    if (nnzc == 0) return SPGEMM_OK;
+    return run_numeric(p, s);
+}
+
+extern "C" {
 
 spgemm_status spgemm_set_allocator(spgemm_alloc_fn alloc, spgemm_free_fn free_fn, void *ctx) {
     if ((alloc == nullptr) != (free_fn == nullptr)) return SPGEMM_ERR_NULL;
