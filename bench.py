@@ -218,7 +218,9 @@ def per_column_work(A, B, t_esc=256, t_block=2 ** 31 - 1):
     esc = (op > 0) & (op <= esc_max)
     blk = (op > esc_max) & (op > t_block)
     srt = (op > esc_max) & ~blk
-    return op, nb, {"esc": esc,
+    # direct-gather accumulators: wavefront groups (esc), one-column waves up
+    # to 1024 products (wave), heavy columns above (heavy)
+    return op, nb, {"esc": esc, "wave": srt & (op <= 1024), "heavy": srt & (op > 1024),
                     "sort512": srt & (op <= 512), "sort1k": srt & (op > 512) & (op <= 1024),
                     "sort2k": srt & (op > 1024) & (op <= 2048),
                     "sort4k": srt & (op > 2048) & (op <= 4096), "wsort": srt & (op > 4096),
@@ -343,6 +345,8 @@ def main():
         kbytes[f"{name}_symbolic"] = sym
     # one numeric launch does every column (tiles and chunks of large ones)
     kbytes["numeric"] = kernel_bytes(op, nb, nnzc, op > 0, vb)[0]
+    heavy_prod = int(op[bins["heavy"]].sum())
+    kbytes["heavy_plan"] = 4 * int(bins["heavy"].sum())
     # expansion: (A column start, length) per stored B entry, A row read and
     # product row written per product
     kbytes["expand"] = 8 * B.nnz + 8 * int(op.sum())

@@ -30,6 +30,7 @@ enum Bin : int {
     BIN_ESC0 = 1,   // Op <= 4
     BIN_ESC6 = 7,   // Op <= 256
     BIN_SORT0 = 8,  // Op <= 512
+    BIN_SORT2 = 10, // Op <= 2048
     BIN_SORT3 = 11, // Op <= 4096
     BIN_WSORT = 12, // Op > 4096
     BIN_BLK0 = 13,  // Op <= 512
@@ -83,6 +84,9 @@ struct Hdr {
     int32_t big_chunks;                // most kChunkB-entry chunks of a column above t_split
     int32_t cap_over;                  // nnz(C) exceeds the output capacity of a one-call product
     unsigned long long total_op;
+    unsigned long long heavy_prod;     // products of the heavy columns (bins SORT3, WSORT)
+    int32_t heavy_win;                 // row windows of the heavy columns
+    int32_t pad_;
 };
 
 // binw[g] = bin | (window flags << 8); the workgroup accumulator records how
@@ -125,7 +129,7 @@ struct KArgs {
     Hdr *hdr;
     int32_t *op;            // [ncols]
     int32_t *binw;          // [ncols] bin of every global column, window flags
-    int4 *binlist;          // [ncols] (global column, first stored B entry, B entries, 0),
+    int4 *binlist;          // [ncols] (global column, first stored B entry, B entries, Op_j),
                             // grouped by bin
     int32_t *gnnz;          // [ncols]
     int2 *E;                // [sum of nnz(B)] (A column start, A column length) of every
@@ -159,6 +163,22 @@ struct KArgs {
     int32_t *lpid;          // [later_n] problem
     int32_t *lkc;           // [later_n] occurrence index k
     void *lv;               // [later_n] value (V)
+    // Heavy columns of the direct-gather accumulators (bins SORT3 and WSORT,
+    // adjacent in the bin list, position li among them): first product in the
+    // heavy scratch, first row window, and the scratch itself.
+    long long *hoff;        // [heavy columns + 1]
+    int32_t *wbase;         // [heavy columns + 1]
+    int32_t *wcnt;          // [windows] output entries of every window (symbolic phase)
+    int32_t *winmap;        // [windows] heavy column (position li) of every window
+    int32_t *hrow;          // [heavy products] row of every product of a heavy column
+    void *hval;             // [heavy products] its value A(i,k) B(k,j) (numeric phase, V)
+    long long heavy_cap;    // heavy products / windows the scratch holds: a launch planned
+    int32_t win_cap;        // from an earlier call that finds more is redone
+    // Numeric phase run at the column positions of the plan's previous
+    // structure (single problem, before this call's counts are scanned): it
+    // also records every column's entry count, and a count that differs
+    // from the previous structure asks for a redo (ERR_RETRY).
+    int32_t spec_fill;
 };
 
 // Destination code of a product: the rank of its output row inside its
@@ -223,13 +243,30 @@ hipError_t launch_layer(const KArgs &a, bool f64, int k, long long n, hipStream_
 // adds every staged later product in one launch; needs later lists in sorted
 // key order (no hash-accumulator columns)
 hipError_t launch_later_runs(const KArgs &a, bool f64, long long n, hipStream_t s);
+// Direct-gather accumulators (no per-product arrays between the phases).
+// fill = false: distinct rows per column (gnnz; window counts of heavy
+// columns); fill = true: rows and values of C. wide: 64-bit keys (rows of
+// 2^21 - 1 and more).
+int wave_bin_items(int bin, int ncols);
+hipError_t launch_acc_wave(const KArgs &a, int bin, int items, bool wide, bool fill, bool f64,
+                           hipStream_t s);
+// offsets and windows of the heavy columns; totals to the header
+hipError_t launch_heavy_plan(const KArgs &a, hipStream_t s);
+// expansion of the ncols heavy columns and their nwin windows
+hipError_t launch_heavy(const KArgs &a, int ncols, int nwin, bool wide, bool fill, bool f64,
+                        hipStream_t s);
+// rank of every product's row in its C column (binary search of C's sorted
+// rows), for the backward view
+hipError_t launch_bw_dst(const Prob &p, const int2 *E, const long long *pofs, const int32_t *bcol,
+                         const int32_t *cri, uint32_t *dst, int *err, hipStream_t s);
+
 // Backward view, built once per single-problem plan: per stored B entry its
 // first product (pofs) and its column's first C entry (cb); per stored A entry
 // (column, offset in the column); a row view of B (rowptr over B's rows,
 // entries by ascending column) holding (B entry, cb) and the first product.
 struct BwView {
     const int2 *E;            // the plan's (A column start, length) per stored B entry
-    const uint32_t *dst;      // the plan's product destinations
+    const uint32_t *dst;      // rank of every product's row in its C column
     long long nnzc;           // stored entries of C
     const long long *pofs;    // [nnz(B)]
     const int32_t *cb;        // [nnz(B)]
@@ -251,6 +288,7 @@ struct BwBuild {
     int nscratch;
     long long *scratch2;  // scan partials of the product counts (nscratch2)
     int nscratch2;
+    uint32_t *dst;        // [products] rank of every product's row in its C column
 };
 hipError_t launch_bw_view(const Prob &p, const int2 *E, const BwBuild &b, BwView &w,
                           hipStream_t s);

@@ -8,13 +8,13 @@
 // matches a plain sequential loop bit for bit.
 //
 // Every term is one product of the forward pass: stored B entry t of column j
-// times the u-th entry of A's column bri[t]. The symbolic phase recorded that
-// product's rank among the entries of C's column j (dst, flag bit aside), so
-// G(i,j) sits at ccp[j] + rank: no search of C's rows. A view built once per
-// plan holds, per stored B entry, its first product (pofs) and its column's
-// first C entry (cb); per stored A entry, its column and offset in it; and a
-// row view of B (entries of each row by ascending column) with the same two
-// values per entry, so the dA loop reads them without an indirection.
+// times the u-th entry of A's column bri[t]. A view built once per plan
+// records that product's rank among the entries of C's column j (dst, by a
+// binary search of C's sorted rows), so G(i,j) sits at ccp[j] + rank; it also
+// holds, per stored B entry, its first product (pofs) and its column's first C
+// entry (cb); per stored A entry, its column and offset in it; and a row view
+// of B (entries of each row by ascending column) with the same two values per
+// entry, so the dA loop reads them without an indirection.
 #include "devutil.h"
 
 namespace spg {
@@ -190,6 +190,46 @@ __global__ __launch_bounds__(kBlock) void k_bv_pack(int nnzb, const int32_t *pos
     rvp[r] = pofs[t];
 }
 
+// rank of every product's row inside its C column (C's rows are ascending:
+// a binary search), thread per stored B entry walking its A column
+__global__ __launch_bounds__(kBlock) void k_bv_dst(Prob p, const int2 *__restrict__ E,
+                                                   const long long *__restrict__ pofs,
+                                                   const int32_t *__restrict__ bcol,
+                                                   const int32_t *__restrict__ cri,
+                                                   uint32_t *__restrict__ dst, int *err) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= p.nnzb) return;
+    const int j = bcol[t];
+    const int c0 = p.ccp[j], c1 = p.ccp[j + 1];
+    const int2 e = E[t];
+    const long long base = pofs[t];
+    int bad = 0;
+    for (int u = 0; u < e.y; ++u) {
+        const int row = p.ari[e.x + u];
+        int lo = c0, hi = c1;  // first position whose row is not below `row`
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cri[mid] < row) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo >= c1 || cri[lo] != row) {  // C does not hold the product's row
+            bad = 1;
+            dst[base + u] = 0;
+        } else {
+            dst[base + u] = (uint32_t)(lo - c0);
+        }
+    }
+    if (bad) atomicOr(err, ERR_CSC);
+}
+
+hipError_t launch_bw_dst(const Prob &p, const int2 *E, const long long *pofs, const int32_t *bcol,
+                         const int32_t *cri, uint32_t *dst, int *err, hipStream_t s) {
+    if (p.nnzb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bv_dst, dim3(ceil_div(p.nnzb, kBlock)), dim3(kBlock), 0, s, p, E, pofs,
+                       bcol, cri, dst, err);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_bw_view(const Prob &p, const int2 *E, const BwBuild &b, BwView &w,
                           hipStream_t s) {
@@ -220,6 +260,7 @@ hipError_t launch_bw_view(const Prob &p, const int2 *E, const BwBuild &b, BwView
                            (const int32_t *)b.pos, (const int32_t *)b.cb,
                            (const long long *)b.pofs, b.rv, b.rvp);
     w.E = E;
+    w.dst = b.dst;
     w.pofs = b.pofs;
     w.cb = b.cb;
     w.aview = b.aview;

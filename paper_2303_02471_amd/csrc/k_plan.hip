@@ -102,11 +102,14 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
         if (op64 > 0x7fffffffull) { err = ERR_OPOVF; op64 = 0x7fffffffull; }
         tot += op64;
         const int op = (int)op64;
+        // the sort-merge bins take a column by its products or its stored B
+        // entries, whichever is more (a work item holds both)
+        const int size = max(op, s_bcp[c + 1] - s_bcp[c]);
         int bin;
         if (op == 0) bin = BIN_EMPTY;
-        else if (op <= esc_max) bin = BIN_ESC0 + max(ceil_log2(op), 2) - 2;
+        else if (size <= esc_max) bin = BIN_ESC0 + max(ceil_log2(size), 2) - 2;
         else if (op > a.tune.t_block) bin = BIN_BLK0 + blk_class(op);
-        else if (op <= kSortMax) bin = BIN_SORT0 + max(ceil_log2(op), 9) - 9;
+        else if (size <= kSortMax) bin = BIN_SORT0 + max(ceil_log2(size), 9) - 9;
         else bin = BIN_WSORT;
         if (op > a.tune.t_split) maxch = max(maxch, ceil_div(s_bcp[c + 1] - s_bcp[c], kChunkB));
         a.op[g] = op;
@@ -187,11 +190,15 @@ hipError_t launch_tally(const KArgs &a, hipStream_t s) {
 
 // ---------------------------------------------------------------- place
 // Same tiling. Each tile writes its columns to its range of every bin list
-// (the tally's per-tile positions), in any order inside the range.
+// (the tally's per-tile positions) in column order, so the columns that one
+// wavefront of an accumulator takes lie close together (their per-column
+// data and their output in C share cache lines). The rank of a column inside
+// its bin is counted with wavefront ballots per bin, then the counts of the
+// waves before it.
 __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
+    constexpr int PER = kTile / kBlock, NW = kBlock / 64;
     __shared__ int s_start[NBINS];
-    __shared__ int s_cnt[NBINS];
-    __shared__ int s_base[NBINS];
+    __shared__ int s_cnt[PER * NW][NBINS];  // columns of every bin per (pass, wave), then prefix
 
     if (__syncthreads_or((__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) & (ERR_CSC | ERR_OPOVF)) != 0))
         return;  // every thread takes the same branch
@@ -206,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
     }
     const int col0 = a.nprob == 1 ? 0 : a.table[pid].col0;
     const int nt = j1 - j0;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) {
         int run = 0;
         for (int b = 0; b < NBINS; ++b) {
@@ -214,34 +221,39 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
             run += a.hdr->bin_count[b];
         }
     }
-    if (tid < NBINS) {
-        s_cnt[tid] = 0;
-        s_base[tid] = a.th[blockIdx.x * NBINS + tid];
-    }
-    __syncthreads();
-
-    constexpr int PER = kTile / kBlock;
+    // column c = 64 (NW u + w) + lane: passes and waves in column order
     int rank[PER], binv[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        int c = tid + u * kBlock;
-        binv[u] = -1;
-        if (c < nt) {
-            binv[u] = a.binw[col0 + j0 + c];
-            rank[u] = atomicAdd(&s_cnt[binv[u]], 1);
+        const int c = 64 * (NW * u + w) + lane;
+        binv[u] = c < nt ? a.binw[col0 + j0 + c] : -1;
+        rank[u] = 0;
+        for (int b = 0; b < NBINS; ++b) {
+            const unsigned long long m = ballot(binv[u] == b);
+            if (binv[u] == b) rank[u] = popc64(m & mask_lt());
+            if (lane == 0) s_cnt[NW * u + w][b] = popc64(m);
         }
     }
     __syncthreads();
-    if (tid < NBINS) s_base[tid] += s_start[tid];
+    // exclusive prefix over (pass, wave) per bin, from the tile's first
+    // position in the bin
+    if (tid < NBINS) {
+        int run = s_start[tid] + a.th[blockIdx.x * NBINS + tid];
+        for (int x = 0; x < PER * NW; ++x) {
+            const int v = s_cnt[x][tid];
+            s_cnt[x][tid] = run;
+            run += v;
+        }
+    }
     __syncthreads();
     const int32_t *bcp = a.nprob == 1 ? a.single.bcp : a.table[pid].bcp;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        int c = tid + u * kBlock;
+        const int c = 64 * (NW * u + w) + lane;
         if (c >= nt) continue;
         const int g = col0 + j0 + c;
         const int bs = bcp[j0 + c], nb = bcp[j0 + c + 1] - bs;
-        a.binlist[s_base[binv[u]] + rank[u]] = make_int4(g, bs, nb, 0);
+        a.binlist[s_cnt[NW * u + w][binv[u]] + rank[u]] = make_int4(g, bs, nb, a.op[g]);
     }
 }
 

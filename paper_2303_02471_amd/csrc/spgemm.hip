@@ -113,6 +113,24 @@ struct spgemm_plan_s {
 
     bool wide_keys = false;  // some problem has 2^20 rows or more: 64-bit sort keys
     bool wide_esc = false;   // some problem has 2^24 - 1 rows or more: 64-bit ESC keys
+    bool wide_acc = false;   // some problem has 2^21 - 1 rows or more: 64-bit keys of the
+                             // direct-gather accumulators
+
+    // Direct-gather accumulators (the default: no hash-accumulator or
+    // lane-hash option): no per-product arrays; heavy columns expand into a
+    // scratch of heavy_cap products with win_cap window counts
+    bool direct = true;
+    long long *hoff = nullptr;
+    int32_t *wbase = nullptr;
+    int32_t *wcnt = nullptr, *hrow = nullptr, *winmap = nullptr;
+    void *hval = nullptr;
+    long long heavy_cap = 0;
+    int32_t win_cap = 0;
+    // the column pointers of the last structure (single problem): a
+    // one-call product may run its numeric phase at these positions first
+    int32_t *saved_cp = nullptr;
+    bool saved_ok = false;
+    long long saved_total = 0;
 
     hipStream_t last_stream = nullptr;
 };
@@ -356,10 +374,13 @@ spgemm_status ensure_workspace(spgemm_plan p, hipStream_t s) {
     const size_t o_th = take(4 * (size_t)NBINS * std::max(p->ntiles, 1));
     const size_t o_ttot = take(8 * (size_t)std::max(p->ntiles, 1));
     const size_t o_tmax = take(4 * (size_t)std::max(p->ntiles, 1));
+    const size_t o_hoff = take(8 * (n + 1)), o_wbase = take(4 * (n + 1));
+    const size_t o_saved = take(4 * (n + 1));
     const size_t need = off;
     if (need > p->ws.bytes) {
         if (spgemm_status st = dev_alloc(p, p->ws, need, s)) return st;
         p->table_dev_copy.clear();
+        p->saved_ok = false;
     }
     char *b = (char *)p->ws.ptr;
     p->hdr = (Hdr *)(b + o_hdr);
@@ -378,6 +399,9 @@ spgemm_status ensure_workspace(spgemm_plan p, hipStream_t s) {
     p->th = (int32_t *)(b + o_th);
     p->ttot = (long long *)(b + o_ttot);
     p->tmax = (int32_t *)(b + o_tmax);
+    p->hoff = (long long *)(b + o_hoff);
+    p->wbase = (int32_t *)(b + o_wbase);
+    p->saved_cp = (int32_t *)(b + o_saved);
 
     const size_t pin = kHdrBytes + 8 * (size_t)std::max(p->nprob, 1);
     if (pin > p->pinned_bytes && !p->use_arena) {
@@ -434,6 +458,14 @@ KArgs make_args(spgemm_plan p) {
     a.lo = p->lo;
     a.lpid = p->lpid;
     a.lv = p->lv;
+    a.hoff = p->hoff;
+    a.wbase = p->wbase;
+    a.wcnt = p->wcnt;
+    a.winmap = p->winmap;
+    a.hrow = p->hrow;
+    a.hval = p->hval;
+    a.heavy_cap = p->heavy_cap;
+    a.win_cap = p->win_cap;
     return a;
 }
 
@@ -588,6 +620,71 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
     return join(p, s, used);
 }
 
+// Scratch of the direct-gather accumulators' heavy columns: rows and values
+// of `prod` products and the counts of `win` windows (only grows).
+spgemm_status ensure_heavy(spgemm_plan p, long long prod, int win, hipStream_t s) {
+    const size_t P = (size_t)std::max<long long>(prod, 1), Wn = (size_t)std::max(win, 1);
+    const size_t vsz = p->dt == SPGEMM_F64 ? 8 : 4;
+    const size_t o_val = align_up(4 * P, 256), o_win = o_val + align_up(vsz * P, 256);
+    const size_t o_map = o_win + align_up(4 * Wn, 256);
+    const size_t need = o_map + 4 * Wn;
+    if (need > p->prod.bytes || prod > p->heavy_cap || win > p->win_cap) {
+        if (need > p->prod.bytes)
+            if (spgemm_status st = dev_alloc(p, p->prod, need, s)) return st;
+        p->heavy_cap = (long long)P;
+        p->win_cap = (int)Wn;
+    }
+    char *b = (char *)p->prod.ptr;
+    p->hrow = (int32_t *)b;
+    p->hval = b + o_val;
+    p->wcnt = (int32_t *)(b + o_win);
+    p->winmap = (int32_t *)(b + o_map);
+    return SPGEMM_OK;
+}
+
+// The direct-gather accumulators of every bin, counting (fill = false) or
+// filling C. The heavy columns (above 1024 products, the largest work) start
+// first on the caller's stream; the wavefront groups of the lightest columns
+// take one side stream, the one-column waves (up to 1024 products) another.
+hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t s, bool fill) {
+    const Hdr &h = p->hdr_host;
+    const bool f64 = p->dt == SPGEMM_F64;
+    hipError_t e;
+    unsigned used = 0;
+    for (int i = 0; i < kEscBins; ++i)
+        if (h.bin_count[BIN_ESC0 + i]) used |= 1u;
+    for (int c = 0; c < 2; ++c)
+        if (h.bin_count[BIN_SORT0 + c]) used |= 2u;
+    if ((e = fork(p, s, used))) return e;
+    // columns above 1024 products (bins SORT2, SORT3, WSORT) are heavy
+    const int nheavy =
+        h.bin_count[BIN_SORT2] + h.bin_count[BIN_SORT3] + h.bin_count[BIN_WSORT];
+    if (nheavy) {
+        ProfScope ps(fill ? "heavy_numeric" : "heavy_symbolic", s);
+        if ((e = launch_heavy(a, nheavy, h.heavy_win, p->wide_acc, fill, f64, s))) return e;
+    }
+    {
+        hipStream_t sw = side(p, 1, s);
+        ProfScope ps(fill ? "wave_numeric" : "wave_symbolic", sw);
+        for (int c = 1; c >= 0; --c) {
+            const int n = h.bin_count[BIN_SORT0 + c];
+            if (n && (e = launch_acc_wave(a, BIN_SORT0 + c, n, p->wide_acc, fill, f64, sw)))
+                return e;
+        }
+    }
+    {
+        hipStream_t se = side(p, 0, s);
+        ProfScope ps(fill ? "esc_numeric" : "esc_symbolic", se);
+        for (int i = kEscBins - 1; i >= 0; --i) {
+            const int n = h.bin_count[BIN_ESC0 + i];
+            if (n && (e = launch_acc_wave(a, BIN_ESC0 + i, wave_bin_items(BIN_ESC0 + i, n),
+                                          p->wide_acc, fill, f64, se)))
+                return e;
+        }
+    }
+    return join(p, s, used);
+}
+
 // Numeric: one launch over the tiles and the chunks of the columns above
 // t_split, then one small launch per occurrence index of the later products.
 // The sizes a numeric launch is planned from (the plan's header and later
@@ -627,6 +724,7 @@ NumLaunch numeric_launch(spgemm_plan p) {
 }
 
 hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
+    if (p->direct) return launch_direct_accumulators(p, a, s, true);
     const bool f64 = p->dt == SPGEMM_F64;
     const NumLaunch L = numeric_launch(p);
     hipError_t e;
@@ -713,7 +811,8 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
     // accumulators) on a side stream while the product offsets and the
     // expansion run on the caller's; the offsets kernel stops the expansion if
     // the products outgrow the planned product space.
-    const bool overlap = spec && p->ncols > 0 && !(p->flags & SPGEMM_ONE_STREAM);
+    // (The direct-gather accumulators have nothing to overlap them with.)
+    const bool overlap = spec && !p->direct && p->ncols > 0 && !(p->flags & SPGEMM_ONE_STREAM);
     {
         const KArgs a = args();
         { ProfScope ps("classify", s); SPG_TRY(launch_classify(a, s)); }
@@ -721,6 +820,10 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         hipStream_t sp = overlap ? p->side[0] : s;
         { ProfScope ps("tally", sp); SPG_TRY(launch_tally(a, sp)); }
         { ProfScope ps("place", sp); SPG_TRY(launch_place(a, sp)); }
+        if (p->direct && p->ncols > 0) {
+            ProfScope ps("heavy_plan", s);
+            SPG_TRY(launch_heavy_plan(a, s));
+        }
     }
     if (!spec) {
         // the bin sizes fix the grids and the product count the allocation
@@ -730,9 +833,36 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         const int err = p->hdr_host.err;
         if (err & ERR_CSC) return SPGEMM_ERR_CSC;
         if (err & ERR_OPOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
-        if ((st = ensure_products(p, p->hdr_host.total_op, s))) return st;
+        if (p->direct) {
+            if ((st = ensure_heavy(p, (long long)p->hdr_host.heavy_prod, p->hdr_host.heavy_win, s)))
+                return st;
+        } else if ((st = ensure_products(p, p->hdr_host.total_op, s))) {
+            return st;
+        }
     }
-    if (p->ncols > 0) {
+    // A planned one-call product on a plan whose last structure is known runs
+    // its numeric phase now, at that structure's column positions, counting
+    // every column's entries as it goes; the scan then builds this call's
+    // column pointers from those counts. A count that differs asks for a redo.
+    const bool speculate = p->direct && spec && fo && p->nprob == 1 && p->saved_ok &&
+                           p->saved_total <= fo->cap && p->ncols > 0;
+    if (p->ncols > 0 && p->direct) {
+        const KArgs al = args();
+        if (speculate) {
+            KArgs af = al;
+            af.single.cri = fo->cri;
+            af.single.cv = fo->cv;
+            af.single.ccp = p->saved_cp;
+            af.spec_fill = 1;
+            SPG_TRY(launch_direct_accumulators(p, af, s, true));
+            fo->queued = true;
+            fo->used = numeric_launch(p);
+        } else {
+            SPG_TRY(launch_direct_accumulators(p, al, s, false));
+        }
+        ProfScope ps("scan", s);
+        SPG_TRY(launch_scan(al, p->gcp, p->bsum, p->nblk, p->totals, s));
+    } else if (p->ncols > 0) {
         const KArgs al = args();
         {
             // first product of every column (exclusive scan of Op_j), tiles
@@ -754,7 +884,7 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
     } else {
         SPG_TRY(publish(p, s));
     }
-    if (fo && spec && p->ncols > 0 && p->nprob == 1) {
+    if (fo && spec && p->ncols > 0 && p->nprob == 1 && !speculate) {
         // the numeric phase from the previous sizes; it stands down on an
         // error or capacity flag raised above, and is redone by the caller if
         // the sizes read back differ
@@ -783,11 +913,31 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         std::memcpy(p->totals_host.data(), (char *)p->pinned + kHdrBytes, 8 * (size_t)p->nprob);
     if (err & (ERR_GROUP | ERR_RETRY)) return SPGEMM_ERR_CSC;
     if (err & ERR_NNZOVF) return SPGEMM_ERR_INDEX_OVERFLOW;
-    // staging of the later products: every product beyond the first of its entry
+    // products beyond the first of their entry (the staged later products of
+    // the product-space accumulators)
     long long nnz_all = 0;
     for (long long t : p->totals_host) nnz_all += t;
     p->later_total = (long long)p->hdr_host.total_op - nnz_all;
     if (p->later_total < 0) return SPGEMM_ERR_CSC;  // cannot happen
+    if (p->direct) {
+        // a later planned pass compares its product total with this one
+        p->prod_total = (long long)p->hdr_host.total_op;
+        if (p->nprob == 1 && p->ncols > 0 && !speculate) {
+            // the structure a later one-call product may start from
+            SPG_TRY(hipMemcpyAsync(p->saved_cp, p->probs[0].ccp, 4 * ((size_t)p->ncols + 1),
+                                   hipMemcpyDeviceToDevice, s));
+            p->saved_total = p->totals_host[0];
+            p->saved_ok = true;
+        }
+        if (p->ncols == 0) {
+            for (int i = 0; i < p->nprob; ++i)
+                SPG_TRY(hipMemsetAsync(p->probs[i].ccp, 0, sizeof(int32_t), s));
+            SPG_TRY(hipStreamSynchronize(s));
+        }
+        p->symbolic_ok = true;
+        p->spec_ready = p->ncols > 0;
+        return SPGEMM_OK;
+    }
     const size_t NL = (size_t)std::max<long long>(p->later_total, 1);
     const size_t vsz = p->dt == SPGEMM_F64 ? 8 : 4;
     const size_t o_pid = align_up(4 * NL, 256), o_k = o_pid + align_up(4 * NL, 256);
@@ -925,10 +1075,17 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
     // all-ones padding key
     p->wide_keys = false;
     p->wide_esc = false;
+    p->wide_acc = false;
     for (const Prob &q : p->probs) {
         p->wide_keys |= q.m >= (1 << 20);
         p->wide_esc |= q.m >= (1 << 24) - 1;
+        p->wide_acc |= q.m >= (1 << 21) - 1;
     }
+    // the hash accumulator and the lane-per-column hash run on the product
+    // space; every other choice on the direct-gather accumulators
+    const bool direct = tune.t_block == 0x7fffffff && !(flags & SPGEMM_LANE_HASH);
+    if (!fresh && direct != p->direct) p->spec_ready = false;
+    p->direct = direct;
     p->ncols = (int)ncols;
     p->total_nnzb = nnzb_total;
     p->ntiles = (int)tiles.size();
@@ -1013,7 +1170,9 @@ spgemm_status spgemm_multiply(const spgemm_csc *A, const spgemm_csc *B, spgemm_d
     q.cv = C_val;
     if (nnzc == 0) return SPGEMM_OK;
     if (fo.queued) {
-        if (fo.used == numeric_launch(p)) return SPGEMM_OK;  // already queued, valid
+        // already queued and valid: the direct-gather accumulators cover any
+        // sizes from any grid; the others were planned from the same sizes
+        if (p->direct || fo.used == numeric_launch(p)) return SPGEMM_OK;
         // queued from other sizes: its bounds checks may have raised the group
         // flag, which would make the phase below stand down; clear it first
         SPG_TRY(hipMemsetAsync(&p->hdr->err, 0, sizeof(int32_t), s));
@@ -1096,7 +1255,8 @@ spgemm_status spgemm_backward(spgemm_plan p, const void *A_val, const void *B_va
                  o_fill = carve(4 * std::max<size_t>(k, 1)), o_colj = carve(4 * nb),
                  o_pos = carve(4 * nb), o_bcol = carve(4 * nb), o_len = carve(4 * nb),
                  o_scr = carve(8 * (size_t)nbs), o_scr2 = carve(8 * (size_t)nbs2),
-                 o_err = carve(sizeof(int));
+                 o_err = carve(sizeof(int)),
+                 o_dst = carve(4 * (size_t)std::max<unsigned long long>(p->hdr_host.total_op, 1));
     const size_t need = off;
     if (need > p->bt.bytes) {
         p->bt_ready = false;
@@ -1120,10 +1280,11 @@ spgemm_status spgemm_backward(spgemm_plan p, const void *A_val, const void *B_va
     bb.nscratch = nbs;
     bb.scratch2 = (long long *)(b + o_scr2);
     bb.nscratch2 = nbs2;
+    bb.dst = (uint32_t *)(b + o_dst);
     p->bt_err = (int *)(b + o_err);
     BwView w{};
     w.E = p->E;
-    w.dst = p->dst;
+    w.dst = bb.dst;
     w.nnzc = p->totals_host[0];
     w.pofs = bb.pofs;
     w.cb = bb.cb;
@@ -1137,6 +1298,7 @@ spgemm_status spgemm_backward(spgemm_plan p, const void *A_val, const void *B_va
         SPG_TRY(hipMemsetAsync(p->bt_err, 0, sizeof(int), s));
         ProfScope ps("bw_view", s);
         SPG_TRY(launch_bw_view(q, p->E, bb, w, s));
+        SPG_TRY(launch_bw_dst(q, p->E, bb.pofs, bb.bcol, C_rowidx, bb.dst, p->bt_err, s));
         p->bt_ready = true;
     }
     {
@@ -1335,6 +1497,10 @@ extern "C" spgemm_status spgemm_multiply_noalloc(const spgemm_csc *A, const spge
     q.ccp = C_colptr;
     p->wide_keys = q.m >= (1 << 20);
     p->wide_esc = q.m >= (1 << 24) - 1;
+    p->wide_acc = q.m >= (1 << 21) - 1;
+    p->direct = tune.t_block == 0x7fffffff && !(flags & SPGEMM_LANE_HASH);
+    p->heavy_cap = 0;
+    p->win_cap = 0;
     p->ncols = q.n;
     p->total_nnzb = q.nnzb;
     p->ntiles = ceil_div(q.n, kTile);

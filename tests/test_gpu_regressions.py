@@ -169,3 +169,44 @@ def test_block_accumulator_forward_backward_size(opts):
     st = plan.stats()
     plan.close()
     assert st["cols_block"] > 0, st
+
+
+def test_one_call_product_after_structure_change():
+    """A one-call product on a plan that has run before starts its numeric
+    phase at the previous structure's column positions. Here the second call
+    keeps every column's product count, bin and the product total, but one
+    column's two selected A columns now share all their rows (fewer output
+    entries): the counts differ, the call is redone, and the result equals
+    the oracle's. Then the first inputs again."""
+    _say("one-call product, structure change with equal product counts")
+    rng = np.random.default_rng(23)
+    A = gen.uniform_z(2000, 6, seed=21)
+    ri = A.rowidx.copy()
+    ri[A.colptr[1]:A.colptr[2]] = ri[A.colptr[0]:A.colptr[1]]  # column 1 = column 0's rows
+    A = gen.CSC(A.nrows, A.ncols, A.colptr, ri, A.val)
+    B1 = gen.uniform_z(2000, 5, seed=22)
+    # column 7 of B: A columns 0 and 2 (12 distinct rows), then 0 and 1 (6)
+    def with_col7(B, rows):
+        cp = B.colptr.astype(np.int64)
+        cols = [B.rowidx[cp[j]:cp[j + 1]] for j in range(B.ncols)]
+        vals = [B.val[cp[j]:cp[j + 1]] for j in range(B.ncols)]
+        cols[7] = np.array(rows, np.int32)
+        vals[7] = rng.uniform(-1, 1, len(rows))
+        ncp = np.zeros(B.ncols + 1, np.int64)
+        ncp[1:] = np.cumsum([len(c) for c in cols])
+        return gen.CSC(B.nrows, B.ncols, ncp.astype(np.int32), np.concatenate(cols),
+                       np.concatenate(vals))
+    Ba, Bb = with_col7(B1, [0, 2]), with_col7(B1, [0, 1])
+    At = api.CscTensor.from_host(A)
+    plan, out = None, None
+    for step, B in enumerate((Ba, Ba, Bb, Bb, Ba)):
+        Bt = api.CscTensor.from_host(B)
+        plan, colptr, ri_, v, nnz = api.multiply(At, Bt, plan=plan, out=out)
+        out = (colptr, ri_, v)
+        torch.cuda.synchronize()
+        ocp, ori, ov = oracle.spgemm(A, B)
+        assert nnz == int(ocp[-1]), f"step {step}"
+        assert_same_structure(colptr.cpu().numpy(), ri_[:nnz].cpu().numpy(), ocp, ori,
+                              f"step {step}")
+        assert_values_exact(v[:nnz].cpu().numpy(), ov, f"step {step}")
+    plan.close()

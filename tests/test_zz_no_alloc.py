@@ -91,11 +91,11 @@ def test_noalloc_capacity_and_scratch_limit():
     st, cp, _, _, nnz = _noalloc(At, Bt, int(ocp[-1]) - 1)
     assert st == _lib.SPGEMM_ERR_CAPACITY and nnz == ocp[-1]
     assert np.array_equal(cp.cpu().numpy(), ocp)
-    # 12.8 M products need more than the 128 MiB array
-    Ab = gen.uniform_z(200_000, 8, seed=8)
-    Bb = gen.uniform_z(200_000, 8, seed=9)
-    Abt, Bbt = api.CscTensor.from_host(Ab), api.CscTensor.from_host(Bb)
-    st, _, _, _, _ = _noalloc(Abt, Bbt, 1)
+    # 16 M products in columns of 1600 (expanded, 12 B each in FP64) need
+    # more than the 128 MiB array
+    Ab = gen.uniform_z(10_000, 40, seed=8)
+    Abt = api.CscTensor.from_host(Ab)
+    st, _, _, _, _ = _noalloc(Abt, Abt, 1)
     assert st == 12, f"status {st}"
     msg = _lib.lib().spgemm_status_string(12)
     assert b"scratch" in msg
