@@ -56,6 +56,9 @@ def parse():
                     help="library defaults instead of autotuned thresholds")
     ap.add_argument("--one-stream", action="store_true",
                     help="library option: no overlap of accumulator kinds (per-kernel timings)")
+    ap.add_argument("--radix-esc", action="store_true",
+                    help="library option: columns above 1024 products on the global radix ESC "
+                         "(Section 4) instead of row windows")
     ap.add_argument("--lane-sweep", action="store_true",
                     help="only the lane-per-column hash accumulator against the wavefront "
                          "sort-merge on constant-Z inputs (Z in 2,4,5,6,8,10; n 2560 and "
@@ -274,8 +277,9 @@ def main():
     At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
     vb = 8
     tuning = None
-    if args.no_autotune or args.t_esc or args.hash_cap:
-        opts = api.options(t_esc=args.t_esc, hash_cap=args.hash_cap, one_stream=args.one_stream)
+    if args.no_autotune or args.t_esc or args.hash_cap or args.radix_esc:
+        opts = api.options(t_esc=args.t_esc, hash_cap=args.hash_cap, one_stream=args.one_stream,
+                           radix_esc=args.radix_esc)
     else:
         # thresholds chosen by the library's autotuner (outside the timed region;
         # the options never change results)

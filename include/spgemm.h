@@ -133,6 +133,11 @@ spgemm_status spgemm_set_allocator(spgemm_alloc_fn alloc, spgemm_free_fn free_fn
                                instead: one output column per lane with a lane-private
                                LDS table, the paper's per-element mapping of HASH
                                (Section 3.2); same results */
+#define SPGEMM_RADIX_ESC 16u /* columns above 1024 products go to the global ESC of Section 4
+                                instead of row windows: groups of consecutive such columns
+                                holding 10,000 products or more, each sorted by (column, row)
+                                with a stable radix sort of 5 or 6 bits per round; same
+                                results (ignored with SPGEMM_LANE_HASH or t_block != 0) */
 
 /*
  * Tuning options. Results never depend on them: they only choose which

@@ -13,6 +13,7 @@ SPGEMM_VALIDATE = 1
 SPGEMM_ONE_STREAM = 2
 SPGEMM_NO_PLANNED_LAUNCH = 4
 SPGEMM_LANE_HASH = 8
+SPGEMM_RADIX_ESC = 16
 SPGEMM_TUNE_LOOKUP_ONLY = 1
 SPGEMM_TUNE_REFRESH = 2
 

@@ -172,6 +172,7 @@ struct KArgs {
     int32_t *winmap;        // [windows] heavy column (position li) of every window
     int32_t *hrow;          // [heavy products] row of every product of a heavy column
     void *hval;             // [heavy products] its value A(i,k) B(k,j) (numeric phase, V)
+    uint32_t *hperm;        // [2 heavy_cap] product indices of the radix sort (SPGEMM_RADIX_ESC)
     long long heavy_cap;    // heavy products / windows the scratch holds: a launch planned
     int32_t win_cap;        // from an earlier call that finds more is redone
     // Numeric phase run at the column positions of the plan's previous
@@ -252,9 +253,16 @@ hipError_t launch_acc_wave(const KArgs &a, int bin, int items, bool wide, bool f
                            hipStream_t s);
 // offsets and windows of the heavy columns; totals to the header
 hipError_t launch_heavy_plan(const KArgs &a, hipStream_t s);
+// global ESC with radix sort over groups of heavy columns (after the heavy
+// expansion); rowbits: bits of the largest row index
+hipError_t launch_esc_radix(const KArgs &a, long long heavy_products, int rowbits, bool fill,
+                            bool f64, hipStream_t s);
 // expansion of the ncols heavy columns and their nwin windows
+// heavy columns: windows, or (radix) the global radix ESC; heavy_products and
+// rowbits size the radix launch
 hipError_t launch_heavy(const KArgs &a, int ncols, int nwin, bool wide, bool fill, bool f64,
-                        hipStream_t s);
+                        hipStream_t s, bool radix, long long heavy_products, int rowbits);
+inline int row_bits(int m) { return m <= 1 ? 0 : 32 - __builtin_clz((unsigned)(m - 1)); }
 // rank of every product's row in its C column (binary search of C's sorted
 // rows), for the backward view
 hipError_t launch_bw_dst(const Prob &p, const int2 *E, const long long *pofs, const int32_t *bcol,

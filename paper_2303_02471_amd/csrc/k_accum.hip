@@ -1202,8 +1202,17 @@ hipError_t launch_heavy_plan(const KArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_heavy(const KArgs &a, int ncols, int nwin, bool wide, bool fill, bool f64,
-                        hipStream_t s) {
+                        hipStream_t s, bool radix, long long heavy_products, int rowbits) {
     if (ncols <= 0) return hipSuccess;
+    if (radix) {
+        // expansion in product order, then the global radix ESC over groups
+        if (!fill) hipLaunchKernelGGL((k_heavy_expand<float, false>), dim3(ncols), dim3(kBlock), 0, s, a);
+        else if (f64) hipLaunchKernelGGL((k_heavy_expand<double, true>), dim3(ncols), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_heavy_expand<float, true>), dim3(ncols), dim3(kBlock), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_esc_radix(a, heavy_products, rowbits, fill, f64, s);
+    }
     hipLaunchKernelGGL(k_win_map, dim3(ceil_div(ncols, kBlock)), dim3(kBlock), 0, s, a);
     if (!fill) {
         hipLaunchKernelGGL((k_heavy_expand<float, false>), dim3(ncols), dim3(kBlock), 0, s, a);

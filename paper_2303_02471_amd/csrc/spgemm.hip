@@ -124,6 +124,8 @@ struct spgemm_plan_s {
     int32_t *wbase = nullptr;
     int32_t *wcnt = nullptr, *hrow = nullptr, *winmap = nullptr;
     void *hval = nullptr;
+    uint32_t *hperm = nullptr;  // radix-sort indices (SPGEMM_RADIX_ESC)
+    int rowbits = 0;            // bits of the largest row index over the problems
     long long heavy_cap = 0;
     int32_t win_cap = 0;
     // the column pointers of the last structure (single problem): a
@@ -464,6 +466,7 @@ KArgs make_args(spgemm_plan p) {
     a.winmap = p->winmap;
     a.hrow = p->hrow;
     a.hval = p->hval;
+    a.hperm = p->hperm;
     a.heavy_cap = p->heavy_cap;
     a.win_cap = p->win_cap;
     return a;
@@ -621,24 +624,27 @@ hipError_t launch_symbolic_accumulators(spgemm_plan p, const KArgs &a, hipStream
 }
 
 // Scratch of the direct-gather accumulators' heavy columns: rows and values
-// of `prod` products and the counts of `win` windows (only grows).
+// of `prod` products and the counts of `win` windows. The capacities only grow
+// and the layout follows them (not this call's sizes): a launch planned from
+// an earlier call may use all of them.
 spgemm_status ensure_heavy(spgemm_plan p, long long prod, int win, hipStream_t s) {
-    const size_t P = (size_t)std::max<long long>(prod, 1), Wn = (size_t)std::max(win, 1);
-    const size_t vsz = p->dt == SPGEMM_F64 ? 8 : 4;
-    const size_t o_val = align_up(4 * P, 256), o_win = o_val + align_up(vsz * P, 256);
+    const size_t P = (size_t)std::max<long long>({prod, 1, p->heavy_cap});
+    const size_t Wn = (size_t)std::max({win, 1, p->win_cap});
+    const size_t o_val = align_up(4 * P, 256), o_win = o_val + align_up(8 * P, 256);
     const size_t o_map = o_win + align_up(4 * Wn, 256);
-    const size_t need = o_map + 4 * Wn;
-    if (need > p->prod.bytes || prod > p->heavy_cap || win > p->win_cap) {
-        if (need > p->prod.bytes)
-            if (spgemm_status st = dev_alloc(p, p->prod, need, s)) return st;
-        p->heavy_cap = (long long)P;
-        p->win_cap = (int)Wn;
-    }
+    // two index arrays of the radix sort (SPGEMM_RADIX_ESC)
+    const size_t o_perm = o_map + align_up(4 * Wn, 256);
+    const size_t need = (p->flags & SPGEMM_RADIX_ESC) ? o_perm + 8 * P : o_map + 4 * Wn;
+    if (need > p->prod.bytes)
+        if (spgemm_status st = dev_alloc(p, p->prod, need, s)) return st;
+    p->heavy_cap = (long long)P;
+    p->win_cap = (int)Wn;
     char *b = (char *)p->prod.ptr;
     p->hrow = (int32_t *)b;
     p->hval = b + o_val;
     p->wcnt = (int32_t *)(b + o_win);
     p->winmap = (int32_t *)(b + o_map);
+    p->hperm = (p->flags & SPGEMM_RADIX_ESC) ? (uint32_t *)(b + o_perm) : nullptr;
     return SPGEMM_OK;
 }
 
@@ -661,7 +667,10 @@ hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t
         h.bin_count[BIN_SORT2] + h.bin_count[BIN_SORT3] + h.bin_count[BIN_WSORT];
     if (nheavy) {
         ProfScope ps(fill ? "heavy_numeric" : "heavy_symbolic", s);
-        if ((e = launch_heavy(a, nheavy, h.heavy_win, p->wide_acc, fill, f64, s))) return e;
+        const bool radix = (p->flags & SPGEMM_RADIX_ESC) != 0;
+        if ((e = launch_heavy(a, nheavy, h.heavy_win, p->wide_acc, fill, f64, s, radix,
+                              (long long)h.heavy_prod, p->rowbits)))
+            return e;
     }
     {
         hipStream_t sw = side(p, 1, s);
@@ -1076,10 +1085,12 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
     p->wide_keys = false;
     p->wide_esc = false;
     p->wide_acc = false;
+    p->rowbits = 0;
     for (const Prob &q : p->probs) {
         p->wide_keys |= q.m >= (1 << 20);
         p->wide_esc |= q.m >= (1 << 24) - 1;
         p->wide_acc |= q.m >= (1 << 21) - 1;
+        p->rowbits = std::max(p->rowbits, row_bits(q.m));
     }
     // the hash accumulator and the lane-per-column hash run on the product
     // space; every other choice on the direct-gather accumulators
@@ -1498,6 +1509,7 @@ extern "C" spgemm_status spgemm_multiply_noalloc(const spgemm_csc *A, const spge
     p->wide_keys = q.m >= (1 << 20);
     p->wide_esc = q.m >= (1 << 24) - 1;
     p->wide_acc = q.m >= (1 << 21) - 1;
+    p->rowbits = row_bits(q.m);
     p->direct = tune.t_block == 0x7fffffff && !(flags & SPGEMM_LANE_HASH);
     p->heavy_cap = 0;
     p->win_cap = 0;
