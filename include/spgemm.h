@@ -133,6 +133,16 @@ spgemm_status spgemm_set_allocator(spgemm_alloc_fn alloc, spgemm_free_fn free_fn
                                instead: one output column per lane with a lane-private
                                LDS table, the paper's per-element mapping of HASH
                                (Section 3.2); same results */
+#define SPGEMM_LANE_BLOCKED 32u /* columns of at most t_lane products go to lane-per-column
+                                   blocks (Section 3.1): sorted by decreasing Op_j, cut by the
+                                   Blocking Algorithm (b_min, b_max), one block per wavefront,
+                                   one column per lane stepping one product at a time as in
+                                   Algorithm 3, each lane with a private hash table whose size
+                                   adapts to the block (HASH, Section 3.2); same results
+                                   (ignored with SPGEMM_LANE_HASH or t_block != 0) */
+#define SPGEMM_LANE_SPARS 64u /* with SPGEMM_LANE_BLOCKED: a private dense accumulator over
+                                 all rows per lane instead (SPARS, Algorithm 3); needs
+                                 A.nrows <= 4096, else SPGEMM_ERR_INVALID */
 #define SPGEMM_RADIX_ESC 16u /* columns above 1024 products go to the global ESC of Section 4
                                 instead of row windows: groups of consecutive such columns
                                 holding 10,000 products or more, each sorted by (column, row)
@@ -164,6 +174,13 @@ spgemm_status spgemm_set_allocator(spgemm_alloc_fn alloc, spgemm_free_fn free_fn
  *   t_split     numeric phase: columns with more products than this are
  *               split over several workgroups (chunks of stored B entries);
  *               >= 1, -1 = never; default 2048.
+ *   t_lane      SPGEMM_LANE_BLOCKED: columns with at most this many products
+ *               (rounded up to a power of two, at most t_esc) go to the lane
+ *               blocks (the paper's switch threshold t of Section 3.3);
+ *               1..64, default 64.
+ *   b_min,      SPGEMM_LANE_BLOCKED: smallest and largest block of the
+ *   b_max       Blocking Algorithm (Section 3.1); 1 <= b_min <= b_max <= 64;
+ *               defaults 16 and 64 (the paper's variable block size).
  */
 typedef struct {
     int32_t t_esc;
@@ -173,6 +190,9 @@ typedef struct {
     uint32_t flags;
     int32_t t_split;
     int32_t t_block;
+    int32_t t_lane;
+    int32_t b_min;
+    int32_t b_max;
 } spgemm_options;
 /* Work statistics of a plan, for reports and tests. */
 typedef struct {
@@ -191,6 +211,9 @@ typedef struct {
     int32_t cols_hash;          /* workgroup columns with a hash-table row window */
     int32_t cols_split;         /* workgroup columns with a window split after overflowing */
     int32_t cols_sort;          /* columns in the workgroup sort-merge accumulator */
+    int32_t lane_cols;          /* SPGEMM_LANE_BLOCKED: columns in lane-per-column blocks */
+    int32_t lane_blocks;        /* SPGEMM_LANE_BLOCKED: blocks of the Blocking Algorithm in the
+                                   last symbolic or numeric launch */
 } spgemm_plan_stats;
 /*
  * Symbolic phase of C = A x B (structure only).

@@ -14,6 +14,8 @@ SPGEMM_ONE_STREAM = 2
 SPGEMM_NO_PLANNED_LAUNCH = 4
 SPGEMM_LANE_HASH = 8
 SPGEMM_RADIX_ESC = 16
+SPGEMM_LANE_BLOCKED = 32
+SPGEMM_LANE_SPARS = 64
 SPGEMM_TUNE_LOOKUP_ONLY = 1
 SPGEMM_TUNE_REFRESH = 2
 
@@ -53,7 +55,8 @@ class Csc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("t_esc", C.c_int32), ("t_dense", C.c_int32), ("dense_rows", C.c_int32),
                 ("hash_cap", C.c_int32), ("flags", C.c_uint32), ("t_split", C.c_int32),
-                ("t_block", C.c_int32)]
+                ("t_block", C.c_int32), ("t_lane", C.c_int32), ("b_min", C.c_int32),
+                ("b_max", C.c_int32)]
 
 
 class PlanStats(C.Structure):
@@ -61,7 +64,8 @@ class PlanStats(C.Structure):
                 ("cols_empty", C.c_int32), ("cols_esc", C.c_int32), ("cols_block", C.c_int32),
                 ("esc_groups", C.c_int32), ("nprob", C.c_int32), ("later_max", C.c_int32),
                 ("pad", C.c_int32), ("later_products", C.c_int64), ("cols_direct", C.c_int32),
-                ("cols_hash", C.c_int32), ("cols_split", C.c_int32), ("cols_sort", C.c_int32)]
+                ("cols_hash", C.c_int32), ("cols_split", C.c_int32), ("cols_sort", C.c_int32),
+                ("lane_cols", C.c_int32), ("lane_blocks", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

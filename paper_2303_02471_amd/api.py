@@ -132,14 +132,19 @@ class CscTensor:
 def options(t_esc: int = 0, t_dense: int = 0, dense_rows: int = 0, hash_cap: int = 0,
             t_split: int = 0, t_block: int = 0, validate: bool = False,
             one_stream: bool = False, planned: bool = True,
-            lane_hash: bool = False, radix_esc: bool = False) -> _lib.Options:
+            lane_hash: bool = False, radix_esc: bool = False, lane_blocked: bool = False,
+            lane_spars: bool = False, t_lane: int = 0, b_min: int = 0,
+            b_max: int = 0) -> _lib.Options:
     """Tuning options (zero = library default). They never change results."""
     flags = (_lib.SPGEMM_VALIDATE if validate else 0) | \
         (_lib.SPGEMM_ONE_STREAM if one_stream else 0) | \
         (0 if planned else _lib.SPGEMM_NO_PLANNED_LAUNCH) | \
         (_lib.SPGEMM_LANE_HASH if lane_hash else 0) | \
-        (_lib.SPGEMM_RADIX_ESC if radix_esc else 0)
-    return _lib.Options(t_esc, t_dense, dense_rows, hash_cap, flags, t_split, t_block)
+        (_lib.SPGEMM_RADIX_ESC if radix_esc else 0) | \
+        (_lib.SPGEMM_LANE_BLOCKED if lane_blocked else 0) | \
+        (_lib.SPGEMM_LANE_SPARS if lane_spars else 0)
+    return _lib.Options(t_esc, t_dense, dense_rows, hash_cap, flags, t_split, t_block, t_lane,
+                        b_min, b_max)
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:

@@ -102,6 +102,8 @@ struct Tune {
     int32_t t_split;     // columns with more products are split over several numeric workgroups
     int32_t t_block;     // columns with more products go to the workgroup hash accumulator
                          // (instead of the sort-merge ones)
+    int32_t t_lane;      // lane-per-column blocks: columns of at most t_lane products
+    int32_t b_min, b_max;  // block sizes of the Blocking Algorithm
 };
 
 // Kernel arguments common to all planning / accumulation kernels.
@@ -258,6 +260,26 @@ hipError_t launch_heavy_plan(const KArgs &a, hipStream_t s);
 hipError_t launch_esc_radix(const KArgs &a, long long heavy_products, int rowbits, bool fill,
                             bool f64, hipStream_t s);
 // expansion of the ncols heavy columns and their nwin windows
+// Lane-per-column blocks of the sorted light columns (SPGEMM_LANE_BLOCKED)
+constexpr int kLbMaxT = 64;                  // largest t (products of a lane column)
+constexpr int kLbMaxDesc = 4 * kLbMaxT + 8;  // block descriptors of one plan
+constexpr int kSparsMaxRows = 4096;          // rows of a SPARS lane accumulator
+struct LbArgs {
+    int32_t t;          // lane columns: Op_j <= t (the first nsub ESC sub-bins)
+    int32_t b_min, b_max;
+    int32_t nsub;
+    int32_t mslab;      // rows of a SPARS value slab (largest m)
+    int32_t *hist;      // [t + 1] lane columns per Op value (zero between calls)
+    int32_t *pos;       // [t + 1] next position of every Op value in the sorted order
+    int32_t *counts;    // [2] blocks, descriptors
+    int4 *desc;         // [kLbMaxDesc] (first position, blocks, block size, first block)
+    int4 *sorted;       // [ncap] bin entries by decreasing Op
+    int32_t ncap;       // entries `sorted` holds (the plan's columns)
+    void *dense;        // value slabs, one per wavefront of the block launch
+};
+hipError_t launch_lane_blocked(const KArgs &a, const LbArgs &lb, int ncols_hint, int grid_cap,
+                               bool spars, bool fill, bool f64, hipStream_t s);
+
 // heavy columns: windows, or (radix) the global radix ESC; heavy_products and
 // rowbits size the radix launch
 hipError_t launch_heavy(const KArgs &a, int ncols, int nwin, bool wide, bool fill, bool f64,

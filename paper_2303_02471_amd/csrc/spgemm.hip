@@ -126,6 +126,11 @@ struct spgemm_plan_s {
     void *hval = nullptr;
     uint32_t *hperm = nullptr;  // radix-sort indices (SPGEMM_RADIX_ESC)
     int rowbits = 0;            // bits of the largest row index over the problems
+    int maxm = 0;               // largest row count over the problems
+    // lane-per-column blocks (SPGEMM_LANE_BLOCKED): sort, blocks and value slabs
+    DevBuf lbuf;
+    LbArgs lb{};
+    int lb_grid = 0;            // wavefronts of the block launch (one value slab each)
     long long heavy_cap = 0;
     int32_t win_cap = 0;
     // the column pointers of the last structure (single problem): a
@@ -295,6 +300,7 @@ spgemm_status dev_alloc(spgemm_plan p, DevBuf &b, size_t bytes, hipStream_t s) {
 
 spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flags) {
     int t_esc = 256, t_dense = 1, dense_rows = 0, cap = 0, t_split = 2048, t_block = 0;
+    int t_lane = kLbMaxT, b_min = 16, b_max = 64;
     flags = 0;
     if (opt) {
         if (opt->t_esc) t_esc = opt->t_esc;
@@ -303,8 +309,14 @@ spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flag
         cap = opt->hash_cap;
         if (opt->t_split) t_split = opt->t_split;
         if (opt->t_block) t_block = opt->t_block;
+        if (opt->t_lane) t_lane = opt->t_lane;
+        if (opt->b_min) b_min = opt->b_min;
+        if (opt->b_max) b_max = opt->b_max;
         flags = opt->flags;
     }
+    if (flags & SPGEMM_LANE_SPARS) flags |= SPGEMM_LANE_BLOCKED;
+    if (t_lane < 1 || t_lane > kLbMaxT) return SPGEMM_ERR_INVALID;
+    if (b_min < 1 || b_max < b_min || b_max > 64) return SPGEMM_ERR_INVALID;
     if (t_esc < 4 || t_esc > kEscMaxProducts) return SPGEMM_ERR_INVALID;
     if (t_dense < 1) return SPGEMM_ERR_INVALID;
     if (dense_rows < 0) return SPGEMM_ERR_INVALID;
@@ -319,6 +331,9 @@ spgemm_status resolve_options(const spgemm_options *opt, Tune &t, uint32_t &flag
     t.hash_cap = cap;
     t.t_split = t_split < 0 ? 0x7fffffff : t_split;
     t.t_block = t_block < 0 ? 0 : (t_block == 0 ? 0x7fffffff : t_block);
+    t.t_lane = t_lane;
+    t.b_min = b_min;
+    t.b_max = b_max;
     return SPGEMM_OK;
 }
 
@@ -648,6 +663,49 @@ spgemm_status ensure_heavy(spgemm_plan p, long long prod, int win, hipStream_t s
     return SPGEMM_OK;
 }
 
+// Lane-per-column blocks (SPGEMM_LANE_BLOCKED): the sort, the block
+// descriptors and one value slab per wavefront of the block launch (128 slots
+// of 64 lanes for HASH, all rows of 64 lanes for SPARS), at most 128 MiB of
+// slabs. The Op histogram starts at zero and every launch leaves it so.
+spgemm_status ensure_lblock(spgemm_plan p, hipStream_t s) {
+    if (!(p->flags & SPGEMM_LANE_BLOCKED)) return SPGEMM_OK;
+    const bool spars = (p->flags & SPGEMM_LANE_SPARS) != 0;
+    if (spars && p->maxm > kSparsMaxRows) return SPGEMM_ERR_INVALID;
+    int nsub = 1;
+    while ((4 << (nsub - 1)) < p->tune.t_lane) ++nsub;
+    nsub = std::min(nsub, p->tune.esc_bins);
+    const int mslab = spars ? std::max(p->maxm, 1) : 0;
+    const size_t slab = (size_t)(spars ? mslab : 2 * kLbMaxT) * 64 * 8;
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>(2048, ((size_t)128 << 20) / slab));
+    // hist and pos: kLbMaxT + 1 ints each (Op values 1..t)
+    const size_t o_pos = align_up(4 * (size_t)(kLbMaxT + 1), 256);
+    const size_t o_cnt = o_pos + align_up(4 * (size_t)(kLbMaxT + 1), 256);
+    const size_t o_desc = o_cnt + 256;
+    const size_t o_sorted = align_up(o_desc + 16 * (size_t)kLbMaxDesc, 256);
+    const size_t o_dense = align_up(o_sorted + 16 * (size_t)std::max(p->ncols, 1), 256);
+    const size_t need = o_dense + (size_t)grid * slab;
+    if (need > p->lbuf.bytes) {
+        if (spgemm_status st = dev_alloc(p, p->lbuf, need, s)) return st;
+        SPG_TRY(hipMemsetAsync(p->lbuf.ptr, 0, 4 * (kLbMaxT + 1), s));
+    }
+    char *b = (char *)p->lbuf.ptr;
+    LbArgs &lb = p->lb;
+    lb.t = 4 << (nsub - 1);
+    lb.b_min = p->tune.b_min;
+    lb.b_max = p->tune.b_max;
+    lb.nsub = nsub;
+    lb.mslab = mslab;
+    lb.hist = (int32_t *)b;
+    lb.pos = (int32_t *)(b + o_pos);
+    lb.counts = (int32_t *)(b + o_cnt);
+    lb.desc = (int4 *)(b + o_desc);
+    lb.sorted = (int4 *)(b + o_sorted);
+    lb.ncap = std::max(p->ncols, 1);
+    lb.dense = b + o_dense;
+    p->lb_grid = grid;
+    return SPGEMM_OK;
+}
+
 // The direct-gather accumulators of every bin, counting (fill = false) or
 // filling C. The heavy columns (above 1024 products, the largest work) start
 // first on the caller's stream; the wavefront groups of the lightest columns
@@ -684,7 +742,17 @@ hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t
     {
         hipStream_t se = side(p, 0, s);
         ProfScope ps(fill ? "esc_numeric" : "esc_symbolic", se);
+        // the lightest sub-bins as lane-per-column blocks
+        const bool lbk = (p->flags & SPGEMM_LANE_BLOCKED) != 0;
+        if (lbk) {
+            int nl = 0;
+            for (int i = 0; i < p->lb.nsub; ++i) nl += h.bin_count[BIN_ESC0 + i];
+            if ((e = launch_lane_blocked(a, p->lb, nl, p->lb_grid,
+                                         (p->flags & SPGEMM_LANE_SPARS) != 0, fill, f64, se)))
+                return e;
+        }
         for (int i = kEscBins - 1; i >= 0; --i) {
+            if (lbk && i < p->lb.nsub) continue;
             const int n = h.bin_count[BIN_ESC0 + i];
             if (n && (e = launch_acc_wave(a, BIN_ESC0 + i, wave_bin_items(BIN_ESC0 + i, n),
                                           p->wide_acc, fill, f64, se)))
@@ -856,6 +924,7 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
     const bool speculate = p->direct && spec && fo && p->nprob == 1 && p->saved_ok &&
                            p->saved_total <= fo->cap && p->ncols > 0;
     if (p->ncols > 0 && p->direct) {
+        if ((st = ensure_lblock(p, s))) return st;
         const KArgs al = args();
         if (speculate) {
             KArgs af = al;
@@ -1086,7 +1155,9 @@ static spgemm_status symbolic_common(int32_t count, const spgemm_csc *A, const s
     p->wide_esc = false;
     p->wide_acc = false;
     p->rowbits = 0;
+    p->maxm = 0;
     for (const Prob &q : p->probs) {
+        p->maxm = std::max(p->maxm, q.m);
         p->wide_keys |= q.m >= (1 << 20);
         p->wide_esc |= q.m >= (1 << 24) - 1;
         p->wide_acc |= q.m >= (1 << 21) - 1;
@@ -1350,6 +1421,11 @@ spgemm_status spgemm_plan_get_stats(spgemm_plan p, spgemm_plan_stats *out) {
     }
     s.later_max = h.later_maxk;
     s.later_products = (int64_t)p->later_total;
+    if ((p->flags & SPGEMM_LANE_BLOCKED) && p->direct && p->lbuf.ptr) {
+        for (int i = 0; i < p->lb.nsub; ++i) s.lane_cols += h.bin_count[BIN_ESC0 + i];
+        if (hipMemcpy(&s.lane_blocks, p->lb.counts, 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return SPGEMM_ERR_HIP;
+    }
     *out = s;
     return SPGEMM_OK;
 }
@@ -1400,6 +1476,7 @@ void spgemm_plan_destroy(spgemm_plan p) {
     dev_free(p, p->stage, s);
     dev_free(p, p->ws, s);
     dev_free(p, p->bt, s);
+    dev_free(p, p->lbuf, s);
     (void)hipStreamSynchronize(s);
     for (int i = 0; i < spgemm_plan_s::kSide; ++i) {
         if (p->side[i]) {
@@ -1489,7 +1566,7 @@ extern "C" spgemm_status spgemm_multiply_noalloc(const spgemm_csc *A, const spge
     p->arena = sl.scratch_ptr;
     p->arena_size = kScratchBytes;
     p->arena_off = 0;
-    p->ws = p->prod = p->stage = p->bt = DevBuf{};
+    p->ws = p->prod = p->stage = p->bt = p->lbuf = DevBuf{};
     p->pinned = sl.host;
     p->pinned_dev = nullptr;
     p->pinned_bytes = sizeof(sl.host);
@@ -1510,6 +1587,7 @@ extern "C" spgemm_status spgemm_multiply_noalloc(const spgemm_csc *A, const spge
     p->wide_esc = q.m >= (1 << 24) - 1;
     p->wide_acc = q.m >= (1 << 21) - 1;
     p->rowbits = row_bits(q.m);
+    p->maxm = q.m;
     p->direct = tune.t_block == 0x7fffffff && !(flags & SPGEMM_LANE_HASH);
     p->heavy_cap = 0;
     p->win_cap = 0;
