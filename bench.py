@@ -79,25 +79,34 @@ def parse():
 
 def lane_sweep(reps=20):
     """C = A x B with every column of A and B holding exactly Z rows (Op = Z^2
-    per column), the synthetic law of the paper's crossover study, at its size
-    (n = 2560) and at one that fills the GPU (n = 262144). For each, the light
-    columns go once to the wavefront sort-merge and once to the lane-per-column
-    hash accumulator (one stream, so the accumulator's own time is seen):
-    symbolic + numeric per call and the accumulator's event-timed share."""
+    per column), the synthetic law of the paper's crossover study (Section
+    5.2). A is 2560 x 2560; B has 2560 rows and n columns: n = 2560 (the
+    paper's size) and n = 262144 (enough columns to fill the GPU while the
+    rows stay within a dense per-lane accumulator). Each case runs the light
+    columns through four accumulators on one stream: the wavefront sort-merge
+    (default), the lane-per-column hash on the product space
+    (SPGEMM_LANE_HASH), and the sorted, blocked lane columns of Section 3.1
+    with a per-lane hash (SPGEMM_LANE_BLOCKED, HASH) or a per-lane dense
+    accumulator (SPGEMM_LANE_SPARS, SPARS). Per one-call product: wall time
+    and the event-timed accumulator groups."""
     import numpy as np
     import torch
     sys.path.insert(0, ROOT)
     from paper_2303_02471_amd import api, inputs as gen
+    kinds = (("esc", {}), ("lane_hash", {"lane_hash": True}),
+             ("blocked_hash", {"lane_blocked": True}),
+             ("blocked_spars", {"lane_blocked": True, "lane_spars": True}))
+    groups = ("esc_symbolic", "esc_numeric", "lane_symbolic", "numeric")
     rows = []
     for n in (2560, 262144):
         for z in (2, 4, 5, 6, 8, 10):
-            A = gen.uniform_z(n, z, seed=41)
-            B = gen.uniform_z(n, z, seed=42)
+            A = gen.uniform_z(2560, z, seed=41)
+            B = gen.uniform_z(n, z, seed=42, nrows=2560)
             At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
-            row = {"n": n, "z": z, "op_per_column": z * z}
+            row = {"m": 2560, "n": n, "z": z, "op_per_column": z * z}
             ref = None
-            for kind, lane in (("esc", False), ("lane", True)):
-                opts = api.options(one_stream=True, lane_hash=lane)
+            for kind, kw in kinds:
+                opts = api.options(one_stream=True, **kw)
                 plan, colptr, ri, v, nnz = api.multiply(At, Bt, opts)
                 out = (colptr, ri, v)
                 for _ in range(3):
@@ -115,17 +124,17 @@ def lane_sweep(reps=20):
                 torch.cuda.synchronize()
                 api.profile_enable(False)
                 prof = api.profile_read()
-                grp = "lane_symbolic" if lane else "esc_symbolic"
-                acc = prof.get(grp)
+                acc = sum(prof[g][1] / prof[g][0] for g in groups if g in prof and prof[g][0])
                 got = (colptr.cpu().numpy(), ri[:nnz].cpu().numpy(), v[:nnz].cpu().numpy())
                 if ref is None:
                     ref = got
                 same = all(np.array_equal(g, r) for g, r in zip(got, ref))
-                row[kind] = {"ms": round(ms, 4),
-                             "accumulator_ms": round(acc[1] / acc[0], 4) if acc else None,
-                             "same_output": bool(same)}
+                st = plan.stats()
+                row[kind] = {"ms": round(ms, 4), "accumulator_ms": round(acc, 4),
+                             "same_output": bool(same), "lane_blocks": st["lane_blocks"]}
                 plan.close()
-            log(f"n={n} z={z}: esc {row['esc']} lane {row['lane']}")
+            log(f"n={n} z={z}: " + " ".join(f"{k} {row[k]['ms']:.3f}/{row[k]['accumulator_ms']:.3f}"
+                                           for k, _ in kinds))
             rows.append(row)
     print(json.dumps({"lane_sweep": rows}), flush=True)
 

@@ -35,17 +35,62 @@ namespace spg {
 
 constexpr int kLbMaxH = 2 * kLbMaxT;  // largest HASH table (max Op_j = 64 gives 128)
 
+// Stable ranks of a wavefront's active lanes by key: every active lane gets
+// the number of active lanes below it with its key; the lowest lane of each
+// key (its leader) also gets the key's count. One pass per distinct key.
+__device__ __forceinline__ void rank_by_key(int key, bool act, int lane, int &rank, int &cnt,
+                                            bool &leader) {
+    unsigned long long rem = ballot(act);
+    rank = 0;
+    cnt = 0;
+    leader = false;
+    while (rem) {
+        const int src = __builtin_ctzll(rem);
+        const int k = __builtin_amdgcn_readlane(key, src);
+        const bool mine = act && key == k;
+        const unsigned long long m = ballot(mine);
+        if (mine) {
+            rank = popc64(m & mask_lt());
+            cnt = popc64(m);
+            leader = lane == src;
+        }
+        rem &= ~m;
+    }
+}
+
 // Counting sort by decreasing Op: histogram of the lane columns' products.
+// Lanes of one value add once per wavefront into LDS, the workgroup once per
+// value into the global histogram (columns of one Op would otherwise all
+// meet on one address).
 __global__ __launch_bounds__(kBlock) void k_lb_hist(KArgs a, LbArgs lb) {
-    if (__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED)) return;
+    __shared__ int s_h[kLbMaxT + 1];
+    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0)) return;
     int start = 0, n = 0;
     for (int b = 0; b < BIN_ESC0; ++b) start += a.hdr->bin_count[b];
     for (int s = 0; s < lb.nsub; ++s) n += a.hdr->bin_count[BIN_ESC0 + s];
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const int op = a.binlist[start + i].w;
-        if (op < 1 || op > lb.t) atomicOr(&a.hdr->err, ERR_GROUP);  // cannot happen
-        else atomicAdd(&lb.hist[op], 1);
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int v = tid; v <= kLbMaxT; v += kBlock) s_h[v] = 0;
+    __syncthreads();
+    bool badop = false;
+    for (int i0 = blockIdx.x * kBlock; i0 < n; i0 += gridDim.x * kBlock) {
+        const int i = i0 + tid;
+        int op = 0;
+        if (i < n) {
+            op = a.binlist[start + i].w;
+            if (op < 1 || op > lb.t) {  // cannot happen
+                badop = true;
+                op = 0;
+            }
+        }
+        int rk, c;
+        bool lead;
+        rank_by_key(op, op > 0, lane, rk, c, lead);
+        if (lead) atomicAdd(&s_h[op], c);
     }
+    __syncthreads();
+    for (int v = 1 + tid; v <= lb.t; v += kBlock)
+        if (s_h[v]) atomicAdd(&lb.hist[v], s_h[v]);
+    if (badop) atomicOr(&a.hdr->err, ERR_GROUP);
 }
 
 // Positions of every Op value in the sorted order, then the blocks. One
@@ -99,19 +144,54 @@ __global__ __launch_bounds__(64) void k_lb_plan(KArgs a, LbArgs lb) {
     lb.counts[1] = nd;
 }
 
-// Columns into the sorted order (within one Op value in any order).
+// Columns into the sorted order (within one Op value in any order): per
+// chunk of the workgroup, every Op value reserves its range with one global
+// add, every column takes its place by its rank in the chunk.
 __global__ __launch_bounds__(kBlock) void k_lb_scatter(KArgs a, LbArgs lb) {
-    if (__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED)) return;
+    __shared__ int s_c[kLbMaxT + 1], s_b[kLbMaxT + 1];
+    if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0)) return;
     int start = 0, n = 0;
     for (int b = 0; b < BIN_ESC0; ++b) start += a.hdr->bin_count[b];
     for (int s = 0; s < lb.nsub; ++s) n += a.hdr->bin_count[BIN_ESC0 + s];
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const int4 ent = a.binlist[start + i];
-        if (ent.w < 1 || ent.w > lb.t) continue;  // flagged by the histogram
-        const int at = atomicAdd(&lb.pos[ent.w], 1);
-        if (at < lb.ncap) lb.sorted[at] = ent;
-        else atomicOr(&a.hdr->err, ERR_GROUP);  // cannot happen
+    const int tid = threadIdx.x, lane = tid & 63;
+    bool over = false;
+    for (int i0 = blockIdx.x * kBlock; i0 < n; i0 += gridDim.x * kBlock) {
+        for (int v = tid; v <= kLbMaxT; v += kBlock) s_c[v] = 0;
+        __syncthreads();
+        const int i = i0 + tid;
+        int4 ent = make_int4(0, 0, 0, 0);
+        if (i < n) ent = a.binlist[start + i];
+        const int op = (i < n && ent.w >= 1 && ent.w <= lb.t) ? ent.w : 0;  // else flagged
+        int rk, c;
+        bool lead;
+        rank_by_key(op, op > 0, lane, rk, c, lead);
+        // the wavefront's range inside the chunk's count of its value,
+        // taken by the key's leader and handed to the key's lanes
+        int local = 0, wbase = 0;
+        if (lead) wbase = atomicAdd(&s_c[op], c);
+        {
+            unsigned long long rem = ballot(op > 0);
+            while (rem) {
+                const int src = __builtin_ctzll(rem);
+                const int k = __builtin_amdgcn_readlane(op, src);
+                const int b = __builtin_amdgcn_readlane(wbase, src);
+                const unsigned long long m = ballot(op > 0 && op == k);
+                if (op > 0 && op == k) local = b + rk;
+                rem &= ~m;
+            }
+        }
+        __syncthreads();
+        for (int v = 1 + tid; v <= lb.t; v += kBlock)
+            if (s_c[v]) s_b[v] = atomicAdd(&lb.pos[v], s_c[v]);
+        __syncthreads();
+        if (op > 0) {
+            const int at = s_b[op] + local;
+            if (at < lb.ncap) lb.sorted[at] = ent;
+            else over = true;  // cannot happen
+        }
+        __syncthreads();
     }
+    if (over) atomicOr(&a.hdr->err, ERR_GROUP);
 }
 
 // HASH tables (slot h of lane l at h * 64 + l) or SPARS flags and row lists

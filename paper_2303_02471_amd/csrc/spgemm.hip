@@ -665,8 +665,8 @@ spgemm_status ensure_heavy(spgemm_plan p, long long prod, int win, hipStream_t s
 
 // Lane-per-column blocks (SPGEMM_LANE_BLOCKED): the sort, the block
 // descriptors and one value slab per wavefront of the block launch (128 slots
-// of 64 lanes for HASH, all rows of 64 lanes for SPARS), at most 128 MiB of
-// slabs. The Op histogram starts at zero and every launch leaves it so.
+// of 64 lanes for HASH, all rows of 64 lanes for SPARS), at most 1 GiB of
+// slabs and 2048 wavefronts. The Op histogram starts at zero and every launch leaves it so.
 spgemm_status ensure_lblock(spgemm_plan p, hipStream_t s) {
     if (!(p->flags & SPGEMM_LANE_BLOCKED)) return SPGEMM_OK;
     const bool spars = (p->flags & SPGEMM_LANE_SPARS) != 0;
@@ -676,7 +676,7 @@ spgemm_status ensure_lblock(spgemm_plan p, hipStream_t s) {
     nsub = std::min(nsub, p->tune.esc_bins);
     const int mslab = spars ? std::max(p->maxm, 1) : 0;
     const size_t slab = (size_t)(spars ? mslab : 2 * kLbMaxT) * 64 * 8;
-    const int grid = (int)std::max<size_t>(1, std::min<size_t>(2048, ((size_t)128 << 20) / slab));
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>(2048, ((size_t)1 << 30) / slab));
     // hist and pos: kLbMaxT + 1 ints each (Op values 1..t)
     const size_t o_pos = align_up(4 * (size_t)(kLbMaxT + 1), 256);
     const size_t o_cnt = o_pos + align_up(4 * (size_t)(kLbMaxT + 1), 256);
