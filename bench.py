@@ -56,6 +56,13 @@ def parse():
                     help="library defaults instead of autotuned thresholds")
     ap.add_argument("--one-stream", action="store_true",
                     help="library option: no overlap of accumulator kinds (per-kernel timings)")
+    ap.add_argument("--cold-steps", type=int, default=5,
+                    help="single steps timed after writing a 512 MiB buffer (caches flushed), "
+                         "beside as many single warm steps")
+    ap.add_argument("--configs", action="store_true",
+                    help="only the small configurations (A*A n=1000 diagonal+4; Laplacian^2 "
+                         "64x64; A*A n=4096 40/col): GPU one-call product and the oracle on 1 "
+                         "and N host threads; prints one JSON line")
     ap.add_argument("--radix-esc", action="store_true",
                     help="library option: columns above 1024 products on the global radix ESC "
                          "(Section 4) instead of row windows")
@@ -136,7 +143,117 @@ def lane_sweep(reps=20):
             log(f"n={n} z={z}: " + " ".join(f"{k} {row[k]['ms']:.3f}/{row[k]['accumulator_ms']:.3f}"
                                            for k, _ in kinds))
             rows.append(row)
-    print(json.dumps({"lane_sweep": rows}), flush=True)
+    # fixed block sizes (b_min = b_max, as in the paper's synthetic study,
+    # where every block reaches b_max), n = 262144
+    bmax_rows = []
+    n = 262144
+    for z in (2, 5, 8):
+        A = gen.uniform_z(2560, z, seed=41)
+        B = gen.uniform_z(n, z, seed=42, nrows=2560)
+        At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
+        for kind, kw in kinds[2:]:
+            for bmax in (8, 16, 32, 64):
+                opts = api.options(one_stream=True, b_min=bmax, b_max=bmax, **kw)
+                plan, colptr, ri, v, nnz = api.multiply(At, Bt, opts)
+                out = (colptr, ri, v)
+                for _ in range(3):
+                    api.multiply(At, Bt, opts, plan=plan, out=out)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    api.multiply(At, Bt, opts, plan=plan, out=out)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / reps
+                bmax_rows.append({"z": z, "kind": kind, "b_max": bmax, "ms": round(ms, 4),
+                                  "lane_blocks": plan.stats()["lane_blocks"]})
+                plan.close()
+            log(f"b_max sweep z={z} {kind}: " +
+                " ".join(f"{r['b_max']}:{r['ms']:.3f}" for r in bmax_rows[-4:]))
+    print(json.dumps({"lane_sweep": rows, "bmax_sweep": bmax_rows}), flush=True)
+
+
+def host_threads():
+    """Threads the N-thread oracle uses: OMP_NUM_THREADS when set (the GPU
+    box sets it to its CPU share), else every host core."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    return n if n > 0 else (os.cpu_count() or 1)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def configs_table(reps=50):
+    """The small configurations, each C = A x A in FP64: A n=1000 with its
+    diagonal and 4 random rows per column; the 5-point Laplacian on 64 x 64;
+    A n=4096 with 40 random rows per column. Per configuration: the one-call
+    product on the GPU (plan and output arrays reused; median of `reps`
+    synchronised calls and the pipelined mean), GFLOP/s (2 x products),
+    compulsory GB/s (|A| + |A| + |C|), the oracle on one thread and on N
+    threads (median of 3), and the output compared with the oracle's."""
+    import numpy as np
+    import torch
+    import oracle
+    sys.path.insert(0, ROOT)
+    from paper_2303_02471_amd import api, inputs as gen
+    cases = (("1: A*A n=1000 diag+4", gen.diag_plus_random(1000, 4, seed=0)),
+             ("2a: Laplacian^2 64x64", gen.laplacian_2d(64)),
+             ("2b: A*A n=4096 40/col", gen.uniform_z(4096, 40, seed=0)))
+    nthr = host_threads()
+    out = []
+    for name, A in cases:
+        At = api.CscTensor.from_host(A)
+        plan, colptr, ri, v, nnz = api.multiply(At, At)
+        o = (colptr, ri, v)
+        for _ in range(5):
+            api.multiply(At, At, plan=plan, out=o)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            c0 = time.perf_counter()
+            api.multiply(At, At, plan=plan, out=o)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - c0)
+        c0 = time.perf_counter()
+        for _ in range(reps):
+            api.multiply(At, At, plan=plan, out=o)
+        torch.cuda.synchronize()
+        tpipe = (time.perf_counter() - c0) / reps
+        ops = int(plan.stats()["total_products"])
+        got = (colptr.cpu().numpy(), ri[:nnz].cpu().numpy(), v[:nnz].cpu().numpy())
+        plan.close()
+        t1, tn = [], []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            ref = oracle.spgemm(A, A)
+            t1.append(time.perf_counter() - c0)
+            c0 = time.perf_counter()
+            _, _, _, used = oracle.spgemm_parallel(A, A, nthreads=nthr, nnz_hint=nnz)
+            tn.append(time.perf_counter() - c0)
+        same = all(np.array_equal(g, r) for g, r in zip(got, ref))
+        tg = statistics.median(ts)
+        comp = 2 * csc_bytes(A.ncols, A.nnz, 8) + csc_bytes(A.ncols, nnz, 8)
+        row = {"config": name, "products": ops, "nnz_c": int(nnz),
+               "gpu_ms": round(tg * 1e3, 4), "gpu_pipelined_ms": round(tpipe * 1e3, 4),
+               "gflops": round(2 * ops / tg / 1e9, 3),
+               "compulsory_GBps": round(comp / tg / 1e9, 2),
+               "compulsory_frac": round(comp / tg / 1e9 / HBM_PEAK_GBS, 5),
+               "oracle_1thread_ms": round(statistics.median(t1) * 1e3, 3),
+               "oracle_nthread_ms": round(statistics.median(tn) * 1e3, 3), "threads": used,
+               "output_equals_oracle": bool(same)}
+        log(str(row))
+        out.append(row)
+    print(json.dumps({"configs": out, "nproc": os.cpu_count(), "cpu_model": cpu_model()}),
+          flush=True)
 
 
 def copy_calibration():
@@ -263,6 +380,9 @@ def main():
         return
     if args.lane_sweep:
         lane_sweep()
+        return
+    if args.configs:
+        configs_table()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU only; multi-GPU sharding "
@@ -391,6 +511,43 @@ def main():
         csc_bytes(B.ncols, nnz, vb)
     log(f"dominant kernel {dom}: {achieved:.0f} GB/s")
 
+    # ------------------------------------------------------------ cold steps
+    # Single steps, each after a 512 MiB buffer is written (twice the MALL,
+    # many times the L2s): the inputs come from HBM. The same number of single
+    # warm steps (no flush, same synchronisation) is timed beside them.
+    cold = None
+    if args.cold_steps > 0:
+        flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+
+        def single(flushed):
+            if flushed:
+                flush.fill_(1)
+            torch.cuda.synchronize()
+            api.profile_select(dom)
+            api.profile_enable(True)
+            c0 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            t = time.perf_counter() - c0
+            api.profile_enable(False)
+            launches, tot = api.profile_read()[dom]
+            api.profile_select(None)
+            return t * 1e3, tot / launches
+
+        warm1 = [single(False) for _ in range(args.cold_steps)]
+        cold1 = [single(True) for _ in range(args.cold_steps)]
+        cms = statistics.median(x[0] for x in cold1)
+        cdom = statistics.median(x[1] for x in cold1)
+        cold = {"ms_per_step": round(cms, 4), "value": round(2.0 * total_op / (cms * 1e-3) / 1e9, 2),
+                "warm_single_ms_per_step": round(statistics.median(x[0] for x in warm1), 4),
+                "flush_bytes": 512 << 20, "steps": args.cold_steps,
+                "hbm_compulsory_frac": round(compulsory / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "dominant_avg_launch_ms": round(cdom, 4),
+                "dominant_warm_single_ms": round(statistics.median(x[1] for x in warm1), 4),
+                "dominant_frac": round(kbytes[dom] / (cdom * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del flush
+        log(f"cold single steps: {cold}")
+
     # ------------------------------------------------------------ CPU baseline (the oracle)
     cpu = None
     if not args.no_cpu_baseline:
@@ -407,11 +564,27 @@ def main():
         same = all(np.array_equal(g, o) for g, o in zip(got, ref))
         log(f"output of the timed steps equals the oracle's: {same}")
         tmed = statistics.median(times)
+        # the same oracle with whole columns spread over host threads
+        nthr = host_threads()
+        ptimes, used, psame = [], 0, True
+        for r in range(args.cpu_runs):
+            c0 = time.perf_counter()
+            pcp, pri, pv, used = oracle.spgemm_parallel(A, B, nthreads=nthr, nnz_hint=nnz)
+            ptimes.append(time.perf_counter() - c0)
+            psame &= all(np.array_equal(g, o) for g, o in zip((pcp, pri, pv), ref))
+            log(f"oracle on {used} threads, run {r}: {ptimes[-1]:.2f}s")
+        pmed = statistics.median(ptimes)
         cpu = {"value": round(2.0 * total_op / tmed / 1e9, 5), "unit": "GFLOP/s", "cores": 1,
                "kind": "oracle",
                "sample": f"full workload (symbolic + numeric), median of {args.cpu_runs} "
                          f"single-thread runs, {tmed:.2f} s each",
-               "output_equals_oracle": bool(same)}
+               "output_equals_oracle": bool(same),
+               "threads": {"value": round(2.0 * total_op / pmed / 1e9, 5), "unit": "GFLOP/s",
+                           "cores": used, "seconds": round(pmed, 3),
+                           "sample": f"full workload, median of {args.cpu_runs} runs, whole "
+                                     f"columns over {used} OpenMP threads",
+                           "equals_single_thread": bool(psame)},
+               "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
     # ------------------------------------------------------------ side measurements
     extras = {}
@@ -432,6 +605,7 @@ def main():
         "hbm_compulsory_GBps": round(compulsory / (ms * 1e-3) / 1e9, 1),
         "hbm_compulsory_frac": round(compulsory / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
+        "cold": cold,
         "tuning": tuning,
         "kernels": kernels,
         "cpu_baseline": cpu,
