@@ -271,8 +271,13 @@ def copy_calibration():
 
 
 # launch group -> kernel symbol (FP64 runs)
-KERNEL_SYMBOL = {"numeric": "k_numeric<double>", "expand": "k_expand",
-                 "wsort_symbolic": "k_wsort<unsigned int>"}
+# launch groups whose HBM traffic --record-traffic can record: the kernels of
+# one launch of the group (their per-dispatch traffic adds up)
+KERNEL_SYMBOL = {"heavy_numeric": ("k_win_map", "k_heavy_expand<double, true>",
+                                   "k_acc_window<unsigned int, double, true>"),
+                 "wave_numeric": ("k_acc_wave<unsigned int, double, 16, 1024, true>",
+                                  "k_acc_wave<unsigned int, double, 8, 512, true>"),
+                 "numeric": ("k_numeric<double>",), "expand": ("k_expand",)}
 
 
 def _src_digest():
@@ -308,9 +313,20 @@ def record_traffic(args):
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the same
     counter reads for a plain 1 GiB device copy."""
     fdir, wdir, cfdir, cwdir = args.record_traffic
-    sym = KERNEL_SYMBOL[args.traffic_kernel]
-    fetch, nf = _per_dispatch(_pmc_rows(fdir), "FETCH_SIZE", sym)
-    write, nw = _per_dispatch(_pmc_rows(wdir), "WRITE_SIZE", sym)
+    syms = KERNEL_SYMBOL[args.traffic_kernel]
+    frows, wrows = _pmc_rows(fdir), _pmc_rows(wdir)
+    fetch = write = 0.0
+    nf, nw = [], []
+    for sym in syms:
+        f1, n1 = _per_dispatch(frows, "FETCH_SIZE", sym)
+        w1, n2 = _per_dispatch(wrows, "WRITE_SIZE", sym)
+        if f1 is None or w1 is None:
+            raise SystemExit(f"no {sym} dispatch in the counter runs")
+        fetch += f1
+        write += w1
+        nf.append(n1)
+        nw.append(n2)
+    sym = list(syms)
     cfetch, _ = _per_dispatch(_pmc_rows(cfdir), "FETCH_SIZE", "copyBuffer")
     cwrite, _ = _per_dispatch(_pmc_rows(cwdir), "WRITE_SIZE", "copyBuffer")
     gib_kib = float(1 << 20)
