@@ -325,24 +325,22 @@ __device__ __forceinline__ void item_sort_compress(const KArgs &a, const Prob &d
 #pragma unroll
         for (int r = 0; r < KPL; ++r) L.key[s0 + r] = key[r];
         wsync();
-        // a key's position bits index the values inside its segment
-        int orow[KPL];
-        V oval[KPL];
+        // A key's position bits index the values inside its segment. Every
+        // head sums its run in order and leaves the sum in its own product's
+        // slot, which no other run reads.
 #pragma unroll
         for (int r = 0; r < KPL; ++r) {
-            orow[r] = -1;
-            oval[r] = V(0);
             if (!head[r]) continue;
             const int s = s0 + r, ss = s & ~(S - 1), send = ss + S;
             const K row = key[r] >> kKeyBits;
-            V acc = V(0) + L.val[ss + (int)(key[r] & (K)(S - 1))];
+            const int own = ss + (int)(key[r] & (K)(S - 1));
+            V acc = V(0) + L.val[own];
             for (int q = s + 1; q < send; ++q) {
                 const K kq = L.key[q];
                 if (kq == KMAX || (kq >> kKeyBits) != row) break;
                 acc = acc + L.val[ss + (int)(kq & (K)(S - 1))];
             }
-            orow[r] = (int)row;
-            oval[r] = acc;
+            L.val[own] = acc;
         }
         // output start of every column; a count that differs from the
         // symbolic phase's means other inputs (nothing is written then)
@@ -354,13 +352,13 @@ __device__ __forceinline__ void item_sort_compress(const KArgs &a, const Prob &d
             if (a.spec_fill) a.gnnz[gcol[lane]] = L.seg_out[lane];
         }
         wsync();
-        // staged at segment start + run index, then written out
+        // head keys staged at segment start + run index, then written out:
+        // the row from the key, the sum from the slot its position bits name
 #pragma unroll
         for (int r = 0; r < KPL; ++r) {
             if (!head[r]) continue;
             const int ss = (s0 + r) & ~(S - 1);
-            L.key[ss + run[r]] = (K)(unsigned)orow[r];
-            L.val[ss + run[r]] = oval[r];
+            L.key[ss + run[r]] = key[r];
         }
         wsync();
         gmem<int32_t> *cri = to_gmem(d.cri);
@@ -372,8 +370,9 @@ __device__ __forceinline__ void item_sort_compress(const KArgs &a, const Prob &d
                 bad = 1;
             } else {
                 for (int i = lane; i < nout; i += 64) {
-                    cri[c0 + i] = (int32_t)(unsigned)L.key[i];
-                    cv[c0 + i] = L.val[i];
+                    const K k = L.key[i];
+                    cri[c0 + i] = (int32_t)(k >> kKeyBits);
+                    cv[c0 + i] = L.val[(int)(k & (K)(S - 1))];
                 }
             }
         } else {
@@ -388,8 +387,9 @@ __device__ __forceinline__ void item_sort_compress(const KArgs &a, const Prob &d
                     continue;
                 }
                 if (i < L.seg_out[cc]) {
-                    cri[c0 + i] = (int32_t)(unsigned)L.key[s];
-                    cv[c0 + i] = L.val[s];
+                    const K k = L.key[s];
+                    cri[c0 + i] = (int32_t)(k >> kKeyBits);
+                    cv[c0 + i] = L.val[cc * S + (int)(k & (K)(S - 1))];
                 }
             }
         }
@@ -513,8 +513,9 @@ __device__ __forceinline__ bool item_gather(const KArgs &a, const Prob &d,
     const gmem<const V> *__restrict__ av = to_gmem((const V *)d.av);
     int row[KPL];
     bool live[KPL];
-    V x[KPL], bm[KPL];
-    // every gather of the lane issued before any is used
+    V x[KPL];
+    // every gather of the lane issued before any is used (the B value of
+    // each position stays in LDS until its product replaces it)
 #pragma unroll
     for (int r = 0; r < KPL; ++r) {
         const int s = r * 64 + lane, cc = s / S, i = s & (S - 1);
@@ -522,10 +523,7 @@ __device__ __forceinline__ bool item_gather(const KArgs &a, const Prob &d,
         live[r] = ok && cc < ncol && i < opv[cc] && qs != kHeadNone;
         const int q = live[r] ? qs + i : 0;
         row[r] = live[r] ? ari[q] : 0;
-        if (FILL) {
-            x[r] = live[r] ? av[q] : V(0);
-            bm[r] = L.val[s];
-        }
+        if (FILL) x[r] = live[r] ? av[q] : V(0);
     }
     wsync();  // every lane has read the filled heads
     bool badrow = false;
@@ -539,7 +537,7 @@ __device__ __forceinline__ bool item_gather(const KArgs &a, const Prob &d,
             live[r] = false;
         }
         L.key[s] = live[r] ? (((K)(unsigned)row[r] << kKeyBits) | (K)(unsigned)i) : KMAX;
-        if (FILL && live[r]) L.val[s] = x[r] * bm[r];
+        if (FILL && live[r]) L.val[s] = x[r] * L.val[s];
     }
     if (ballot(badrow) && lane == 0) atomicOr(&a.hdr->err, ERR_CSC);
     wsync();
@@ -795,7 +793,7 @@ __global__ __launch_bounds__(64) void k_acc_lane(KArgs a, int bin) {
 // One workgroup; the totals go to the header (the host sizes the scratch from
 // them). A planned launch whose scratch is too small is redone.
 constexpr int kWinKpl = 16;                     // positions per lane of a window's buffer
-constexpr int kWinTarget = 64 * kWinKpl * 3 / 4;  // planned products per window
+constexpr int kWinTarget = 64 * kWinKpl * 7 / 8;  // planned products per window
 
 __global__ __launch_bounds__(1024) void k_heavy_plan(KArgs a) {
     constexpr int T = 1024;
@@ -1096,30 +1094,25 @@ __global__ __launch_bounds__(64) void k_acc_window(KArgs a) {
 #pragma unroll
                 for (int r = 0; r < KPL; ++r) L.key[s0 + r] = key[r];
                 wsync();
-                int orow[KPL];
-                V oval[KPL];
+                // every head sums its run in order into its own product's
+                // slot, then its key is staged at its run index
 #pragma unroll
                 for (int r = 0; r < KPL; ++r) {
-                    orow[r] = -1;
-                    oval[r] = V(0);
                     if (!head[r]) continue;
                     const K row = key[r] >> kKeyBits;
-                    V acc = V(0) + L.val[(int)(key[r] & (K)(N - 1))];
+                    const int own = (int)(key[r] & (K)(N - 1));
+                    V acc = V(0) + L.val[own];
                     for (int q = s0 + r + 1; q < N; ++q) {
                         const K kq = L.key[q];
                         if (kq == KMAX || (kq >> kKeyBits) != row) break;
                         acc = acc + L.val[(int)(kq & (K)(N - 1))];
                     }
-                    orow[r] = (int)row;
-                    oval[r] = acc;
+                    L.val[own] = acc;
                 }
                 wsync();
 #pragma unroll
-                for (int r = 0; r < KPL; ++r) {
-                    if (!head[r]) continue;
-                    L.key[run[r]] = (K)(unsigned)orow[r];
-                    L.val[run[r]] = oval[r];
-                }
+                for (int r = 0; r < KPL; ++r)
+                    if (head[r]) L.key[run[r]] = key[r];
                 wsync();
                 const int clen = d.ccp[j + 1] - c0;
                 if (out + total + runs > clen) {
@@ -1128,8 +1121,9 @@ __global__ __launch_bounds__(64) void k_acc_window(KArgs a) {
                     gmem<int32_t> *cri = to_gmem(d.cri);
                     gmem<V> *cv = to_gmem((V *)d.cv);
                     for (int i = lane; i < runs; i += 64) {
-                        cri[c0 + out + total + i] = (int32_t)(unsigned)L.key[i];
-                        cv[c0 + out + total + i] = L.val[i];
+                        const K k = L.key[i];
+                        cri[c0 + out + total + i] = (int32_t)(k >> kKeyBits);
+                        cv[c0 + out + total + i] = L.val[(int)(k & (K)(N - 1))];
                     }
                 }
                 wsync();
