@@ -277,10 +277,12 @@ spgemm_status spgemm_multiply(const spgemm_csc *A, const spgemm_csc *B, spgemm_d
  * the library runs on holds until the process ends (found once per device).
  * nnz(C) is read back by a copy into library-owned host memory.
  *   Workspace needed: about 60 B per column of C and 8 B per stored entry of
- *   B, plus (4 + value size) B per intermediate product (Op, Section 3.1) of
- *   the columns with more than 1024 of them (16 B per product of every column,
- *   and 16 B per product beyond the first of its entry, with the hash options
- *   t_block or SPGEMM_LANE_HASH); a problem beyond the array gives
+ *   B, plus 12 B per intermediate product (Op, Section 3.1) of the columns
+ *   with more than 1024 of them (20 B with SPGEMM_RADIX_ESC; 16 B per product
+ *   of every column, and 16 B per product beyond the first of its entry, with
+ *   the hash options t_block or SPGEMM_LANE_HASH; with SPGEMM_LANE_BLOCKED
+ *   also 16 B per column and 32 MiB of per-lane value slabs); a problem
+ *   beyond the array gives
  *   SPGEMM_ERR_SCRATCH before any kernel writes the workspace.
  *   SPGEMM_VALIDATE gives SPGEMM_ERR_INVALID (its host check allocates).
  *   SPGEMM_ERR_CAPACITY: as spgemm_multiply (colptr and nnzC_host set); call

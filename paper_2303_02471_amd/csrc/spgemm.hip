@@ -676,7 +676,9 @@ spgemm_status ensure_lblock(spgemm_plan p, hipStream_t s) {
     nsub = std::min(nsub, p->tune.esc_bins);
     const int mslab = spars ? std::max(p->maxm, 1) : 0;
     const size_t slab = (size_t)(spars ? mslab : 2 * kLbMaxT) * 64 * 8;
-    const int grid = (int)std::max<size_t>(1, std::min<size_t>(2048, ((size_t)1 << 30) / slab));
+    // the allocation-free entry point carves from a fixed array: 32 MiB of slabs there
+    const size_t budget = p->use_arena ? ((size_t)32 << 20) : ((size_t)1 << 30);
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>(2048, budget / slab));
     // hist and pos: kLbMaxT + 1 ints each (Op values 1..t)
     const size_t o_pos = align_up(4 * (size_t)(kLbMaxT + 1), 256);
     const size_t o_cnt = o_pos + align_up(4 * (size_t)(kLbMaxT + 1), 256);

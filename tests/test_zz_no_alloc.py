@@ -27,7 +27,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _noalloc(At, Bt, capacity=None):
+def _noalloc(At, Bt, capacity=None, opts=None):
     """One call of the entry point; returns (status, colptr, rowidx, val, nnz)."""
     dev = At.colptr.device
     dtype = At.val.dtype
@@ -37,7 +37,8 @@ def _noalloc(At, Bt, capacity=None):
     v = torch.full((max(cap, 1),), float("nan"), dtype=dtype, device=dev)
     nnz = C.c_int64(-1)
     da, db = api._desc(At, True), api._desc(Bt, True)
-    st = _lib.lib().spgemm_multiply_noalloc(C.byref(da), C.byref(db), api._code(dtype), None,
+    st = _lib.lib().spgemm_multiply_noalloc(C.byref(da), C.byref(db), api._code(dtype),
+                                           C.byref(opts) if opts is not None else None,
                                            api._stream(None), api._ptr(cp),
                                            ri.data_ptr() if cap else None,
                                            v.data_ptr() if cap else None, cap, C.byref(nnz))
@@ -45,18 +46,18 @@ def _noalloc(At, Bt, capacity=None):
     return st, cp, ri, v, int(nnz.value)
 
 
-def _check(A, B, npdt, what):
+def _check(A, B, npdt, what, opts=None):
     At = api.CscTensor.from_host(A, dtype=npdt)
     Bt = api.CscTensor.from_host(B, dtype=npdt)
     # size: nnz(C) from the entry point itself (capacity 0)
-    st, cp0, _, _, nnz = _noalloc(At, Bt, 0)
+    st, cp0, _, _, nnz = _noalloc(At, Bt, 0, opts)
     assert st in (0, _lib.SPGEMM_ERR_CAPACITY), f"{what}: status {st}"
-    st, cp, ri, v, nnz2 = _noalloc(At, Bt, nnz)
+    st, cp, ri, v, nnz2 = _noalloc(At, Bt, nnz, opts)
     assert st == 0 and nnz2 == nnz, f"{what}: status {st}"
     assert torch.equal(cp0, cp)
     got = (cp.cpu().numpy(), ri[:nnz].cpu().numpy(), v[:nnz].cpu().numpy())
     # the existing one-call entry point on the same inputs
-    plan, rcp, rri, rv, rnnz = api.multiply(At, Bt)
+    plan, rcp, rri, rv, rnnz = api.multiply(At, Bt, opts)
     torch.cuda.synchronize()
     assert rnnz == nnz, what
     assert np.array_equal(got[0], rcp.cpu().numpy()), f"{what}: colptr vs spgemm_multiply"
@@ -101,3 +102,19 @@ def test_noalloc_capacity_and_scratch_limit():
     assert b"scratch" in msg
     # the entry point still works afterwards
     _check(A, B, np.float64, "after the refused problem")
+
+
+@pytest.mark.parametrize("kw", [dict(radix_esc=True), dict(lane_blocked=True),
+                                dict(lane_blocked=True, lane_spars=True)])
+def test_noalloc_option_paths(kw):
+    """The optional accumulators through the allocation-free entry point: the
+    radix ESC of the heavy columns, the lane blocks with per-lane hash tables
+    and with dense per-lane accumulators (their slabs carved from the array)."""
+    _say(f"no-alloc entry point with {kw}")
+    if kw.get("lane_spars"):
+        A = gen.uniform_z(2560, 5, seed=11)
+        B = gen.uniform_z(4000, 6, seed=12, nrows=2560)
+    else:
+        A, B = gen.powerlaw(30_000, seed=13)
+    _check(A, B, np.float64, f"{kw}", api.options(**kw))
+    _check(A, B, np.float32, f"{kw} FP32", api.options(**kw))
