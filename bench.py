@@ -277,6 +277,13 @@ KERNEL_SYMBOL = {"heavy_numeric": ("k_win_map", "k_heavy_expand<double, true>",
                                    "k_acc_window<unsigned int, double, true>"),
                  "wave_numeric": ("k_acc_wave<unsigned int, double, 16, 1024, true>",
                                   "k_acc_wave<unsigned int, double, 8, 512, true>"),
+                 "esc_numeric": ("k_acc_lane<unsigned int, double, 4, true>",
+                                 "k_acc_lane<unsigned int, double, 8, true>",
+                                 "k_acc_lane<unsigned int, double, 16, true>",
+                                 "k_acc_wave<unsigned int, double, 4, 32, true>",
+                                 "k_acc_wave<unsigned int, double, 4, 64, true>",
+                                 "k_acc_wave<unsigned int, double, 4, 128, true>",
+                                 "k_acc_wave<unsigned int, double, 4, 256, true>"),
                  "numeric": ("k_numeric<double>",), "expand": ("k_expand",)}
 
 
@@ -339,9 +346,15 @@ def record_traffic(args):
                                 "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
            "hbm_bytes_per_launch": int(round((fetch * fs + write * ws) * 1024)),
            "source_digest": _src_digest()}
+    # one entry per launch group
     path = os.path.join(ROOT, "profiles", "traffic.json")
+    allg = {}
+    if os.path.exists(path):
+        old = json.load(open(path))
+        allg = old.get("groups", {}) if "groups" in old else {}
+    allg[args.traffic_kernel] = out
     with open(path, "w") as f:
-        json.dump(out, f, indent=1)
+        json.dump({"groups": allg}, f, indent=1)
     print(json.dumps(out))
 
 
@@ -515,9 +528,8 @@ def main():
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
-        tj = json.load(open(tfile))
-        if tj.get("kernel_key") == dom and tj.get("workload") == f"powerlaw_n{args.n}" and \
-                tj.get("source_digest") == _src_digest():
+        tj = json.load(open(tfile)).get("groups", {}).get(dom, {})
+        if tj.get("workload") == f"powerlaw_n{args.n}" and tj.get("source_digest") == _src_digest():
             traffic = tj.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -729,6 +741,35 @@ def batched(api, gen, np, torch, count, reps=5, tune=True):
     tgn = timeit(graph.replay)
     log(f"batched {tb:.2f} ms vs loop {tl:.2f} ms; numeric {tbn:.2f} vs {tln:.2f}; "
         f"numeric graph replay {tgn:.2f}")
+    # per size decile (problems ranked by products): the decile's problems as
+    # one batched call against the loop of their single calls
+    ops = np.array([p.stats()["total_products"] for p in plans], dtype=np.int64)
+    deciles = []
+    for d, idx in enumerate(np.array_split(np.argsort(ops, kind="stable"), 10)):
+        sub = [pairs[i] for i in idx]
+        souts, sbplan = api.batched_matmul(sub, opts, return_plan=True)
+        sri = [o.rowidx for o in souts]
+        sv = [o.val for o in souts]
+
+        def t_sub_batched():
+            api.batched_symbolic(sub, torch.float64, opts, plan=sbplan)
+            api.batched_numeric(sbplan, sub, sri, sv)
+
+        def t_sub_loop():
+            for i in idx:
+                a, b = pairs[i]
+                api.symbolic(a, b, torch.float64, opts, plan=plans[i], out_colptr=plans[i].colptr)
+                api.numeric(plans[i], a.val, b.val, rowidxs[i], vals[i])
+
+        sb, sl = timeit(t_sub_batched), timeit(t_sub_loop)
+        deciles.append({"decile": d, "problems": len(idx),
+                        "products": int(ops[idx].sum()),
+                        "products_per_problem": [int(ops[idx].min()), int(ops[idx].max())],
+                        "batched_ms": round(sb, 3), "loop_ms": round(sl, 3),
+                        "speedup": round(sl / sb, 3)})
+        sbplan.close()
+    log("batched speed-up per size decile: " +
+        " ".join(f"{x['decile']}:{x['speedup']:.2f}" for x in deciles))
     return {"workload": f"{count} problems, n log-uniform [500, 20000], 2..40 per column, FP64",
             "products": int(sum(p.stats()["total_products"] for p in plans)),
             "nnz_c": int(sum(nnzs)),
@@ -736,7 +777,8 @@ def batched(api, gen, np, torch, count, reps=5, tune=True):
             "speedup": round(tl / tb, 3),
             "numeric_batched_ms": round(tbn, 3), "numeric_loop_ms": round(tln, 3),
             "numeric_speedup": round(tln / tbn, 3),
-            "numeric_graph_ms": round(tgn, 3), "numeric_graph_speedup": round(tln / tgn, 3)}
+            "numeric_graph_ms": round(tgn, 3), "numeric_graph_speedup": round(tln / tgn, 3),
+            "deciles": deciles}
 
 
 if __name__ == "__main__":
