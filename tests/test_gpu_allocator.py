@@ -106,3 +106,68 @@ def test_counting_allocator_sees_every_plan_allocation():
         assert cnt.allocs == cnt.frees
     finally:
         api.set_allocator("torch")
+
+
+class Refusing(Counting):
+    """Grants the first `grant` requests, refuses every later one (NULL)."""
+
+    def __init__(self, grant):
+        super().__init__()
+        self.grant = grant
+        self.refused = 0
+
+    def _alloc(self, nbytes, stream, ctx):
+        if self.allocs >= self.grant:
+            self.refused += 1
+            return None
+        return super()._alloc(nbytes, stream, ctx)
+
+
+def _symbolic_allocations(At, Bt):
+    """Allocations one symbolic call makes on a fresh plan."""
+    cnt = Counting()
+    api.set_allocator(cnt.alloc_cb, cnt.free_cb)
+    try:
+        plan = api.Plan()
+        api.symbolic(At, Bt, torch.float64, plan=plan)
+        torch.cuda.synchronize()
+        plan.close()
+        torch.cuda.synchronize()
+    finally:
+        api.set_allocator("torch")
+    return cnt.allocs
+
+
+@pytest.mark.parametrize("which", ["first", "last"])
+def test_refused_allocation_gives_no_memory(which):
+    """An allocator that runs out (at the symbolic call's first request, or at
+    its last one: the rest of the plan's workspace already in place) makes the
+    call return SPGEMM_ERR_NO_MEMORY; everything granted comes back through
+    free once the plan is gone, and the library works again with the default
+    allocator."""
+    A = gen.uniform_z(3000, 6, seed=1)
+    B = gen.uniform_z(3000, 7, seed=2)
+    At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
+    n = _symbolic_allocations(At, Bt)
+    assert n >= 2, n
+    grant = 0 if which == "first" else n - 1
+    _say(f"refusing allocator after {grant} of {n} grants")
+    ref = Refusing(grant)
+    api.set_allocator(ref.alloc_cb, ref.free_cb)
+    try:
+        plan = api.Plan()
+        with pytest.raises(_lib.SpgemmError) as e:
+            api.symbolic(At, Bt, torch.float64, plan=plan)
+        assert e.value.status == 6, e.value
+        assert ref.refused >= 1
+        plan.close()
+        torch.cuda.synchronize()
+        assert not ref.live, f"{len(ref.live)} granted allocations never freed"
+        assert not ref.bad_frees, ref.bad_frees[:3]
+    finally:
+        api.set_allocator("torch")
+    Cm = api.matmul(At, Bt)
+    ocp, ori, ov = oracle.spgemm(A, B)
+    cp, ri, v = Cm.to_host()
+    assert_same_structure(cp, ri, ocp, ori, "after the refusals")
+    assert_values_exact(v, ov, "after the refusals")
