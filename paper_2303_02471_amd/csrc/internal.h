@@ -282,8 +282,11 @@ hipError_t launch_lane_blocked(const KArgs &a, const LbArgs &lb, int ncols_hint,
 
 // heavy columns: windows, or (radix) the global radix ESC; heavy_products and
 // rowbits size the radix launch
+// part 0 .. heavy_parts(radix) - 1 of the heavy columns' launches, in order
+int heavy_parts(bool radix);
 hipError_t launch_heavy(const KArgs &a, int ncols, int nwin, bool wide, bool fill, bool f64,
-                        hipStream_t s, bool radix, long long heavy_products, int rowbits);
+                        hipStream_t s, bool radix, long long heavy_products, int rowbits,
+                        int part);
 inline int row_bits(int m) { return m <= 1 ? 0 : 32 - __builtin_clz((unsigned)(m - 1)); }
 // rank of every product's row in its C column (binary search of C's sorted
 // rows), for the backward view

@@ -885,7 +885,10 @@ __global__ __launch_bounds__(kBlock) void k_heavy_expand(KArgs a) {
     for (int b = kHeavyBin; b <= BIN_WSORT; ++b) n += a.hdr->bin_count[b];
     const int tid = threadIdx.x;
     int bad = 0, rowbad = 0;
-    for (int li = blockIdx.x; li < n; li += gridDim.x) {
+    // largest columns first (the heavy list runs from small to large bins):
+    // the longest workgroups start before the short ones
+    for (int lj = blockIdx.x; lj < n; lj += gridDim.x) {
+        const int li = n - 1 - lj;
         const int4 ent = a.binlist[first + li];
         const int g = ent.x, bs = ent.y, nb = ent.z;
         const int pid = find_prob(a, g);
@@ -972,7 +975,9 @@ __global__ __launch_bounds__(64) void k_acc_window(KArgs a) {
     for (int b = kHeavyBin; b <= BIN_WSORT; ++b) n += a.hdr->bin_count[b];
     const int nwin = a.wbase[n];
     int bad = 0;
-    for (int wi = blockIdx.x; wi < nwin; wi += gridDim.x) {
+    // windows of the largest columns (the longest scans) first
+    for (int wj = blockIdx.x; wj < nwin; wj += gridDim.x) {
+        const int wi = nwin - 1 - wj;
         const int li = a.winmap[wi];
         const int wb = a.wbase[li], w = wi - wb, W = a.wbase[li + 1] - wb;
         const int g = a.binlist[first + li].x;
@@ -1195,37 +1200,37 @@ hipError_t launch_heavy_plan(const KArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The heavy columns' launches one part at a time (the caller interleaves them
+// with other streams' launches): windows take the map of windows, the
+// expansion and the windowed sort; the radix ESC the expansion and the sort.
+int heavy_parts(bool radix) { return radix ? 2 : 3; }
+
 hipError_t launch_heavy(const KArgs &a, int ncols, int nwin, bool wide, bool fill, bool f64,
-                        hipStream_t s, bool radix, long long heavy_products, int rowbits) {
+                        hipStream_t s, bool radix, long long heavy_products, int rowbits,
+                        int part) {
     if (ncols <= 0) return hipSuccess;
-    if (radix) {
-        // expansion in product order, then the global radix ESC over groups
+    const bool expand = radix ? part == 0 : part == 1;
+    if (expand) {
         if (!fill) hipLaunchKernelGGL((k_heavy_expand<float, false>), dim3(ncols), dim3(kBlock), 0, s, a);
         else if (f64) hipLaunchKernelGGL((k_heavy_expand<double, true>), dim3(ncols), dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL((k_heavy_expand<float, true>), dim3(ncols), dim3(kBlock), 0, s, a);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        return launch_esc_radix(a, heavy_products, rowbits, fill, f64, s);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_win_map, dim3(ceil_div(ncols, kBlock)), dim3(kBlock), 0, s, a);
+    if (radix) return part == 1 ? launch_esc_radix(a, heavy_products, rowbits, fill, f64, s) : hipSuccess;
+    if (part == 0) {
+        hipLaunchKernelGGL(k_win_map, dim3(ceil_div(ncols, kBlock)), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    if (part != 2 || nwin <= 0) return hipSuccess;
     if (!fill) {
-        hipLaunchKernelGGL((k_heavy_expand<float, false>), dim3(ncols), dim3(kBlock), 0, s, a);
-        if (nwin > 0) {
-            if (wide) hipLaunchKernelGGL((k_acc_window<unsigned long long, float, false>), dim3(nwin), dim3(64), 0, s, a);
-            else hipLaunchKernelGGL((k_acc_window<unsigned, float, false>), dim3(nwin), dim3(64), 0, s, a);
-        }
+        if (wide) hipLaunchKernelGGL((k_acc_window<unsigned long long, float, false>), dim3(nwin), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_acc_window<unsigned, float, false>), dim3(nwin), dim3(64), 0, s, a);
     } else if (f64) {
-        hipLaunchKernelGGL((k_heavy_expand<double, true>), dim3(ncols), dim3(kBlock), 0, s, a);
-        if (nwin > 0) {
-            if (wide) hipLaunchKernelGGL((k_acc_window<unsigned long long, double, true>), dim3(nwin), dim3(64), 0, s, a);
-            else hipLaunchKernelGGL((k_acc_window<unsigned, double, true>), dim3(nwin), dim3(64), 0, s, a);
-        }
+        if (wide) hipLaunchKernelGGL((k_acc_window<unsigned long long, double, true>), dim3(nwin), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_acc_window<unsigned, double, true>), dim3(nwin), dim3(64), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_heavy_expand<float, true>), dim3(ncols), dim3(kBlock), 0, s, a);
-        if (nwin > 0) {
-            if (wide) hipLaunchKernelGGL((k_acc_window<unsigned long long, float, true>), dim3(nwin), dim3(64), 0, s, a);
-            else hipLaunchKernelGGL((k_acc_window<unsigned, float, true>), dim3(nwin), dim3(64), 0, s, a);
-        }
+        if (wide) hipLaunchKernelGGL((k_acc_window<unsigned long long, float, true>), dim3(nwin), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_acc_window<unsigned, float, true>), dim3(nwin), dim3(64), 0, s, a);
     }
     return hipGetLastError();
 }

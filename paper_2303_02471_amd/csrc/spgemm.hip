@@ -15,8 +15,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
+#include <optional>
 #include <vector>
 
 #include "../../include/spgemm.h"
@@ -158,8 +160,10 @@ struct Profiler {
     size_t used = 0;
 } g_prof;
 
+// Several scopes may be open at once (one per stream): a scope keeps the
+// index of its record, which stays valid when the record list grows.
 struct ProfScope {
-    ProfRec *r = nullptr;
+    long ri = -1;
     hipStream_t s;
     ProfScope(const char *name, hipStream_t st) : s(st) {
         if (!g_prof.on) return;
@@ -172,13 +176,15 @@ struct ProfScope {
                 return;
             g_prof.recs.push_back(nr);
         }
-        r = &g_prof.recs[g_prof.used++];
-        r->name = name;
-        (void)hipEventRecord(r->a, s);
+        ri = (long)g_prof.used++;
+        g_prof.recs[ri].name = name;
+        (void)hipEventRecord(g_prof.recs[ri].a, s);
     }
     ~ProfScope() {
-        if (r) (void)hipEventRecord(r->b, s);
+        if (ri >= 0) (void)hipEventRecord(g_prof.recs[ri].b, s);
     }
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -709,12 +715,26 @@ spgemm_status ensure_lblock(spgemm_plan p, hipStream_t s) {
 }
 
 // The direct-gather accumulators of every bin, counting (fill = false) or
-// filling C. The heavy columns (above 1024 products, the largest work) start
-// first on the caller's stream; the wavefront groups of the lightest columns
-// take one side stream, the one-column waves (up to 1024 products) another.
-hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t s, bool fill) {
+// filling C, on three streams: the wavefront groups and lane bins of the
+// lightest columns on one side stream, the one-column waves (up to 1024
+// products) on another, the heavy columns (above 1024 products) on the
+// caller's. The host takes several microseconds per launch, so the launches
+// are queued one per stream in turn (each stream's first kernel early), after
+// the heavy columns' plan when plan_heavy asks for it: a single workgroup
+// that then runs before the accumulators fill the chip.
+struct LaunchQueue {
+    const char *name;
+    hipStream_t st;
+    std::vector<std::function<hipError_t()>> l;
+    size_t next = 0;
+    std::optional<ProfScope> ps;
+};
+
+hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t s, bool fill,
+                                      bool plan_heavy) {
     const Hdr &h = p->hdr_host;
     const bool f64 = p->dt == SPGEMM_F64;
+    const bool wide = p->wide_acc;
     hipError_t e;
     unsigned used = 0;
     for (int i = 0; i < kEscBins; ++i)
@@ -722,43 +742,59 @@ hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t
     for (int c = 0; c < 2; ++c)
         if (h.bin_count[BIN_SORT0 + c]) used |= 2u;
     if ((e = fork(p, s, used))) return e;
-    // columns above 1024 products (bins SORT2, SORT3, WSORT) are heavy
+    if (plan_heavy) {
+        ProfScope ps("heavy_plan", s);
+        if ((e = launch_heavy_plan(a, s))) return e;
+    }
+    LaunchQueue q[3] = {{fill ? "esc_numeric" : "esc_symbolic", side(p, 0, s), {}},
+                        {fill ? "heavy_numeric" : "heavy_symbolic", s, {}},
+                        {fill ? "wave_numeric" : "wave_symbolic", side(p, 1, s), {}}};
+    // side stream 0: the lightest sub-bins as lane-per-column blocks (option),
+    // then the wavefront sub-bins from the largest down
+    const bool lbk = (p->flags & SPGEMM_LANE_BLOCKED) != 0;
+    if (lbk) {
+        int nl = 0;
+        for (int i = 0; i < p->lb.nsub; ++i) nl += h.bin_count[BIN_ESC0 + i];
+        const bool spars = (p->flags & SPGEMM_LANE_SPARS) != 0;
+        const hipStream_t se = q[0].st;
+        q[0].l.push_back([=, &a] { return launch_lane_blocked(a, p->lb, nl, p->lb_grid, spars, fill, f64, se); });
+    }
+    for (int i = kEscBins - 1; i >= 0; --i) {
+        if (lbk && i < p->lb.nsub) continue;
+        const int n = h.bin_count[BIN_ESC0 + i];
+        const hipStream_t se = q[0].st;
+        if (n)
+            q[0].l.push_back([=, &a] {
+                return launch_acc_wave(a, BIN_ESC0 + i, wave_bin_items(BIN_ESC0 + i, n), wide, fill,
+                                       f64, se);
+            });
+    }
+    // caller's stream: columns above 1024 products (bins SORT2, SORT3, WSORT)
     const int nheavy =
         h.bin_count[BIN_SORT2] + h.bin_count[BIN_SORT3] + h.bin_count[BIN_WSORT];
     if (nheavy) {
-        ProfScope ps(fill ? "heavy_numeric" : "heavy_symbolic", s);
         const bool radix = (p->flags & SPGEMM_RADIX_ESC) != 0;
-        if ((e = launch_heavy(a, nheavy, h.heavy_win, p->wide_acc, fill, f64, s, radix,
-                              (long long)h.heavy_prod, p->rowbits)))
-            return e;
+        const int nwin = h.heavy_win, rowbits = p->rowbits;
+        const long long hp = (long long)h.heavy_prod;
+        for (int part = 0; part < heavy_parts(radix); ++part)
+            q[1].l.push_back([=, &a] {
+                return launch_heavy(a, nheavy, nwin, wide, fill, f64, s, radix, hp, rowbits, part);
+            });
     }
-    {
-        hipStream_t sw = side(p, 1, s);
-        ProfScope ps(fill ? "wave_numeric" : "wave_symbolic", sw);
-        for (int c = 1; c >= 0; --c) {
-            const int n = h.bin_count[BIN_SORT0 + c];
-            if (n && (e = launch_acc_wave(a, BIN_SORT0 + c, n, p->wide_acc, fill, f64, sw)))
-                return e;
-        }
+    // side stream 1: the one-column waves, 1024 products then 512
+    for (int c = 1; c >= 0; --c) {
+        const int n = h.bin_count[BIN_SORT0 + c];
+        const hipStream_t sw = q[2].st;
+        if (n) q[2].l.push_back([=, &a] { return launch_acc_wave(a, BIN_SORT0 + c, n, wide, fill, f64, sw); });
     }
-    {
-        hipStream_t se = side(p, 0, s);
-        ProfScope ps(fill ? "esc_numeric" : "esc_symbolic", se);
-        // the lightest sub-bins as lane-per-column blocks
-        const bool lbk = (p->flags & SPGEMM_LANE_BLOCKED) != 0;
-        if (lbk) {
-            int nl = 0;
-            for (int i = 0; i < p->lb.nsub; ++i) nl += h.bin_count[BIN_ESC0 + i];
-            if ((e = launch_lane_blocked(a, p->lb, nl, p->lb_grid,
-                                         (p->flags & SPGEMM_LANE_SPARS) != 0, fill, f64, se)))
-                return e;
-        }
-        for (int i = kEscBins - 1; i >= 0; --i) {
-            if (lbk && i < p->lb.nsub) continue;
-            const int n = h.bin_count[BIN_ESC0 + i];
-            if (n && (e = launch_acc_wave(a, BIN_ESC0 + i, wave_bin_items(BIN_ESC0 + i, n),
-                                          p->wide_acc, fill, f64, se)))
-                return e;
+    for (bool more = true; more;) {
+        more = false;
+        for (LaunchQueue &x : q) {
+            if (x.next == x.l.size()) continue;
+            if (x.next == 0) x.ps.emplace(x.name, x.st);
+            if ((e = x.l[x.next++]())) return e;
+            if (x.next == x.l.size()) x.ps.reset();
+            more = true;
         }
     }
     return join(p, s, used);
@@ -803,7 +839,7 @@ NumLaunch numeric_launch(spgemm_plan p) {
 }
 
 hipError_t launch_numeric_phase(spgemm_plan p, const KArgs &a, hipStream_t s) {
-    if (p->direct) return launch_direct_accumulators(p, a, s, true);
+    if (p->direct) return launch_direct_accumulators(p, a, s, true, false);
     const bool f64 = p->dt == SPGEMM_F64;
     const NumLaunch L = numeric_launch(p);
     hipError_t e;
@@ -899,7 +935,9 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
         hipStream_t sp = overlap ? p->side[0] : s;
         { ProfScope ps("tally", sp); SPG_TRY(launch_tally(a, sp)); }
         { ProfScope ps("place", sp); SPG_TRY(launch_place(a, sp)); }
-        if (p->direct && p->ncols > 0) {
+        // a planned launch queues the heavy columns' plan behind the fork of
+        // the accumulator streams; a first launch reads its totals back here
+        if (p->direct && p->ncols > 0 && !spec) {
             ProfScope ps("heavy_plan", s);
             SPG_TRY(launch_heavy_plan(a, s));
         }
@@ -934,11 +972,11 @@ spgemm_status symbolic_pass(spgemm_plan p, hipStream_t s, const std::vector<int4
             af.single.cv = fo->cv;
             af.single.ccp = p->saved_cp;
             af.spec_fill = 1;
-            SPG_TRY(launch_direct_accumulators(p, af, s, true));
+            SPG_TRY(launch_direct_accumulators(p, af, s, true, true));
             fo->queued = true;
             fo->used = numeric_launch(p);
         } else {
-            SPG_TRY(launch_direct_accumulators(p, al, s, false));
+            SPG_TRY(launch_direct_accumulators(p, al, s, false, spec));
         }
         ProfScope ps("scan", s);
         SPG_TRY(launch_scan(al, p->gcp, p->bsum, p->nblk, p->totals, s));
