@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--radix-esc", action="store_true",
                     help="library option: columns above 1024 products on the global radix ESC "
                          "(Section 4) instead of row windows")
+    ap.add_argument("--accumulators", action="store_true",
+                    help="every accumulator kind on the dense-bin, fixed-degree and power-law "
+                         "workloads (one stream, event-timed launch groups); then exit")
     ap.add_argument("--lane-sweep", action="store_true",
                     help="only the lane-per-column hash accumulator against the wavefront "
                          "sort-merge on constant-Z inputs (Z in 2,4,5,6,8,10; n 2560 and "
@@ -103,7 +106,8 @@ def lane_sweep(reps=20):
     kinds = (("esc", {}), ("lane_hash", {"lane_hash": True}),
              ("blocked_hash", {"lane_blocked": True}),
              ("blocked_spars", {"lane_blocked": True, "lane_spars": True}))
-    groups = ("esc_symbolic", "esc_numeric", "lane_symbolic", "numeric")
+    groups = ("esc_symbolic", "esc_numeric", "wave_symbolic", "wave_numeric", "lane_symbolic",
+              "numeric")
     rows = []
     for n in (2560, 262144):
         for z in (2, 4, 5, 6, 8, 10):
@@ -192,6 +196,87 @@ def cpu_model():
     return None
 
 
+def accumulator_compare(reps=20):
+    """Every accumulator kind of the library on the dense-bin configuration (A x A,
+    n = 4096, 40 rows per column: 1600 products per column, FP64), the
+    fixed-degree product of the forward+backward configuration (A x B,
+    n = 100,000, 8 per column: 64 products per column, FP32) and the power-law
+    product at n = 100,000 (FP64). Per kind: the one-call product on a reused
+    plan (median of `reps` synchronised calls), the event time of every launch
+    group, and the output compared with the default kind's (which is checked
+    against the oracle). The kinds: the direct-gather sort-merge (default);
+    the workgroup hash accumulator with direct indexing of row windows that
+    fit (Section 3.2 HASH with the SPA of Section 2.2) for every column above
+    4 products (t_esc = 4, t_block = -1); the same without direct indexing;
+    the lane-per-column hash on the product space (SPGEMM_LANE_HASH); the
+    sorted, blocked lane columns of Section 3.1 with HASH and (at most 4096
+    rows) SPARS; the global radix ESC of Section 4 for the heavy columns."""
+    import numpy as np
+    import torch
+    import oracle
+    sys.path.insert(0, ROOT)
+    from paper_2303_02471_amd import api, inputs as gen
+    pl = gen.powerlaw(100_000, seed=5)
+    cases = (("2b: A*A n=4096 40/col FP64", gen.uniform_z(4096, 40, seed=0), None),
+             ("5: A*B n=100000 8/col FP32",
+              gen.uniform_z(100_000, 8, seed=1, dist="normal", dtype=np.float32),
+              gen.uniform_z(100_000, 8, seed=2, dist="normal", dtype=np.float32)),
+             ("power-law A*B n=100000 FP64", pl[0], pl[1]))
+    kinds = (("direct sort-merge (default)", {}),
+             ("hash + direct-indexed windows", {"t_esc": 4, "t_block": -1}),
+             ("hash only", {"t_esc": 4, "t_block": -1, "t_dense": 100000}),
+             ("lane hash (product space)", {"lane_hash": True}),
+             ("blocked lanes, HASH", {"lane_blocked": True}),
+             ("blocked lanes, SPARS", {"lane_blocked": True, "lane_spars": True}),
+             ("radix ESC for heavy columns", {"radix_esc": True}))
+    plan_groups = ("classify", "tally", "place", "heavy_plan", "scan", "product_offsets")
+    out = []
+    for name, A, B in cases:
+        B = A if B is None else B
+        At, Bt = api.CscTensor.from_host(A), api.CscTensor.from_host(B)
+        ocp, ori, ov = oracle.spgemm(A, B, "f32" if A.val.dtype == np.float32 else "f64")
+        ref = None
+        row = {"workload": name, "products": None, "kinds": {}}
+        for kind, kw in kinds:
+            if kw.get("lane_spars") and A.nrows > 4096:
+                continue
+            opts = api.options(one_stream=True, **kw)
+            plan, colptr, ri, v, nnz = api.multiply(At, Bt, opts)
+            o = (colptr, ri, v)
+            for _ in range(3):
+                api.multiply(At, Bt, opts, plan=plan, out=o)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                c0 = time.perf_counter()
+                api.multiply(At, Bt, opts, plan=plan, out=o)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - c0)
+            api.profile_select(None)
+            api.profile_enable(True)
+            for _ in range(3):
+                api.multiply(At, Bt, opts, plan=plan, out=o)
+            torch.cuda.synchronize()
+            api.profile_enable(False)
+            prof = api.profile_read()
+            groups = {g: round(t / c, 4) for g, (c, t) in prof.items() if c}
+            acc = sum(t for g, t in groups.items() if g not in plan_groups)
+            got = (colptr.cpu().numpy(), ri[:nnz].cpu().numpy(), v[:nnz].cpu().numpy())
+            if ref is None:
+                ref = got
+                row["equals_oracle"] = bool(np.array_equal(got[0], ocp) and np.array_equal(got[1], ori)
+                                            and np.array_equal(got[2], ov))
+            row["products"] = int(plan.stats()["total_products"])
+            row["kinds"][kind] = {"ms": round(statistics.median(ts) * 1e3, 4),
+                                  "accumulator_ms": round(acc, 4), "groups_ms": groups,
+                                  "same_output": bool(all(np.array_equal(g, r) for g, r in zip(got, ref)))}
+            plan.close()
+        log(name + ": " + ", ".join(f"{k} {d['ms']:.3f}/{d['accumulator_ms']:.3f}"
+                                    for k, d in row["kinds"].items()))
+        out.append(row)
+    print(json.dumps({"accumulators": out}), flush=True)
+
+
 def configs_table(reps=50):
     """The small configurations, each C = A x A in FP64: A n=1000 with its
     diagonal and 4 random rows per column; the 5-point Laplacian on 64 x 64;
@@ -276,14 +361,14 @@ def copy_calibration():
 KERNEL_SYMBOL = {"heavy_numeric": ("k_win_map", "k_heavy_expand<double, true>",
                                    "k_acc_window<unsigned int, double, true>"),
                  "wave_numeric": ("k_acc_wave<unsigned int, double, 16, 1024, true>",
-                                  "k_acc_wave<unsigned int, double, 8, 512, true>"),
+                                  "k_acc_wave<unsigned int, double, 8, 512, true>",
+                                  "k_acc_wave<unsigned int, double, 4, 128, true>",
+                                  "k_acc_wave<unsigned int, double, 4, 256, true>"),
                  "esc_numeric": ("k_acc_lane<unsigned int, double, 4, true>",
                                  "k_acc_lane<unsigned int, double, 8, true>",
                                  "k_acc_lane<unsigned int, double, 16, true>",
                                  "k_acc_wave<unsigned int, double, 4, 32, true>",
-                                 "k_acc_wave<unsigned int, double, 4, 64, true>",
-                                 "k_acc_wave<unsigned int, double, 4, 128, true>",
-                                 "k_acc_wave<unsigned int, double, 4, 256, true>"),
+                                 "k_acc_wave<unsigned int, double, 4, 64, true>"),
                  "numeric": ("k_numeric<double>",), "expand": ("k_expand",)}
 
 
@@ -376,9 +461,11 @@ def per_column_work(A, B, t_esc=256, t_block=2 ** 31 - 1):
     esc = (op > 0) & (op <= esc_max)
     blk = (op > esc_max) & (op > t_block)
     srt = (op > esc_max) & ~blk
-    # direct-gather accumulators: wavefront groups (esc), one-column waves up
-    # to 1024 products (wave), heavy columns above (heavy)
-    return op, nb, {"esc": esc, "wave": srt & (op <= 1024), "heavy": srt & (op > 1024),
+    # direct-gather accumulators by stream: lane bins and wavefront groups of
+    # at most 64 products (esc); wavefront groups above 64 and one-column
+    # waves up to 1024 products (wave); heavy columns above (heavy)
+    return op, nb, {"esc": esc & (op <= 64), "wave": (esc & (op > 64)) | (srt & (op <= 1024)),
+                    "heavy": srt & (op > 1024),
                     "sort512": srt & (op <= 512), "sort1k": srt & (op > 512) & (op <= 1024),
                     "sort2k": srt & (op > 1024) & (op <= 2048),
                     "sort4k": srt & (op > 2048) & (op <= 4096), "wsort": srt & (op > 4096),
@@ -412,6 +499,9 @@ def main():
         return
     if args.configs:
         configs_table()
+        return
+    if args.accumulators:
+        accumulator_compare()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU only; multi-GPU sharding "

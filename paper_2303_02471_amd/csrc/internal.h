@@ -38,6 +38,8 @@ enum Bin : int {
     NBINS = 18
 };
 constexpr int kEscBins = 7;
+constexpr int kEscSide0 = 5;  // wavefront sub-bins below this (at most 64 products) share one
+                              // accumulator stream, the larger ones the one-column waves' stream
 constexpr int kSortBins = 4;
 constexpr int kBlkBins = 5;
 constexpr int kSortMax = 4096;        // products per workgroup sort

@@ -81,31 +81,71 @@ __device__ __forceinline__ unsigned long long kx(unsigned long long v) {
     return shfl_xor_c64<J>(v);
 }
 
+// Median of three unsigned 32-bit values where c is 0 (the smaller of x and
+// y) or all ones (the larger): one v_med3_u32 takes a compare-exchange's side
+// chosen per lane.
+// (Written as the instruction itself: spelled as min and max, the network's
+// chains of them send the compiler's combiner into a very long search.)
+// The result replaces x in its register.
+__device__ __forceinline__ void med3u(unsigned &x, unsigned y, unsigned c) {
+    asm("v_med3_u32 %0, %0, %1, %2" : "+v"(x) : "v"(y), "v"(c));
+}
+
 // one compare-exchange stage between lanes at distance J (J >= 1)
 template <typename K, int KPL, int J, int S>
 __device__ __forceinline__ void lane_stage(K (&key)[KPL], int k, int lane) {
     const int s0 = lane * KPL;
     const bool asc = k == S || (s0 & k) == 0;
     const bool take_min = asc == ((lane & J) == 0);
+    if constexpr (sizeof(K) == 4) {
+        const unsigned c = take_min ? 0u : ~0u;
 #pragma unroll
-    for (int r = 0; r < KPL; ++r) {
-        const K o = kx<J>(key[r]);
-        const K mn = key[r] < o ? key[r] : o;
-        const K mx = key[r] < o ? o : key[r];
-        key[r] = take_min ? mn : mx;
+        for (int r = 0; r < KPL; ++r) {
+            unsigned x = (unsigned)key[r];
+            med3u(x, kx<J>(x), c);
+            key[r] = (K)x;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+            const K o = kx<J>(key[r]);
+            const K mn = key[r] < o ? key[r] : o;
+            const K mx = key[r] < o ? o : key[r];
+            key[r] = take_min ? mn : mx;
+        }
     }
 }
 
 // every aligned segment of S positions sorted ascending (bitonic network of
 // the segment's size; the last merge ascending everywhere)
 template <typename K, int KPL, int S>
-__device__ __forceinline__ void seg_sort(K (&key)[KPL], int lane) {
+__device__ __forceinline__ void seg_sort(K (&key)[KPL], int lane_in) {
+    // The direction masks below depend on the lane only: an opaque copy of
+    // the lane number keeps them from being computed once outside the
+    // caller's loop and held in registers for the whole kernel.
+    int lane = lane_in;
+    asm volatile("" : "+v"(lane));
     const int s0 = lane * KPL;
 #pragma unroll
     for (int k = 2; k <= S; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j < KPL) {
+            if (j < KPL && sizeof(K) == 4 && k >= KPL && k != S) {
+                // the direction depends on the lane only (r < KPL <= k):
+                // each side of a pair is one median of three
+                const unsigned c = (s0 & k) == 0 ? 0u : ~0u;
+#pragma unroll
+                for (int r = 0; r < KPL; ++r) {
+                    if (r & j) continue;
+                    const int rp = r | j;
+                    unsigned x = (unsigned)key[r], y = (unsigned)key[rp];
+                    const unsigned x0 = x;
+                    med3u(x, y, c);
+                    med3u(y, x0, ~c);
+                    key[r] = (K)x;
+                    key[rp] = (K)y;
+                }
+            } else if (j < KPL) {
 #pragma unroll
                 for (int r = 0; r < KPL; ++r) {
                     if (r & j) continue;

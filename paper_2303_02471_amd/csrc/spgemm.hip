@@ -716,12 +716,14 @@ spgemm_status ensure_lblock(spgemm_plan p, hipStream_t s) {
 
 // The direct-gather accumulators of every bin, counting (fill = false) or
 // filling C, on three streams: the wavefront groups and lane bins of the
-// lightest columns on one side stream, the one-column waves (up to 1024
-// products) on another, the heavy columns (above 1024 products) on the
-// caller's. The host takes several microseconds per launch, so the launches
-// are queued one per stream in turn (each stream's first kernel early), after
-// the heavy columns' plan when plan_heavy asks for it: a single workgroup
-// that then runs before the accumulators fill the chip.
+// columns of at most 64 products on one side stream, the wavefront groups of
+// up to 256 and the one-column waves (up to 1024 products) on another, the
+// heavy columns (above 1024 products) on the caller's. The host takes
+// several microseconds per launch, so the order of the launches matters:
+// first the heavy columns' plan when plan_heavy asks for it (a single
+// workgroup that then runs before the accumulators fill the chip) and every
+// launch of the heavy chain but its last, then one launch per stream in turn
+// (each stream's first kernel early).
 struct LaunchQueue {
     const char *name;
     hipStream_t st;
@@ -738,7 +740,7 @@ hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t
     hipError_t e;
     unsigned used = 0;
     for (int i = 0; i < kEscBins; ++i)
-        if (h.bin_count[BIN_ESC0 + i]) used |= 1u;
+        if (h.bin_count[BIN_ESC0 + i]) used |= i < kEscSide0 ? 1u : 2u;
     for (int c = 0; c < 2; ++c)
         if (h.bin_count[BIN_SORT0 + c]) used |= 2u;
     if ((e = fork(p, s, used))) return e;
@@ -759,7 +761,8 @@ hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t
         const hipStream_t se = q[0].st;
         q[0].l.push_back([=, &a] { return launch_lane_blocked(a, p->lb, nl, p->lb_grid, spars, fill, f64, se); });
     }
-    for (int i = kEscBins - 1; i >= 0; --i) {
+    // (the sub-bins above 64 products go to side stream 1, below)
+    for (int i = std::min(kEscBins, kEscSide0) - 1; i >= 0; --i) {
         if (lbk && i < p->lb.nsub) continue;
         const int n = h.bin_count[BIN_ESC0 + i];
         const hipStream_t se = q[0].st;
@@ -781,20 +784,45 @@ hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t
                 return launch_heavy(a, nheavy, nwin, wide, fill, f64, s, radix, hp, rowbits, part);
             });
     }
-    // side stream 1: the one-column waves, 1024 products then 512
+    // side stream 1: the one-column waves, 1024 products then 512, then the
+    // wavefront sub-bins above 64 products (the three streams then hold
+    // similar work on power-law inputs)
     for (int c = 1; c >= 0; --c) {
         const int n = h.bin_count[BIN_SORT0 + c];
         const hipStream_t sw = q[2].st;
         if (n) q[2].l.push_back([=, &a] { return launch_acc_wave(a, BIN_SORT0 + c, n, wide, fill, f64, sw); });
     }
+    for (int i = kEscBins - 1; i >= kEscSide0; --i) {
+        const int n = h.bin_count[BIN_ESC0 + i];
+        const hipStream_t sw = q[2].st;
+        if (n)
+            q[2].l.push_back([=, &a] {
+                return launch_acc_wave(a, BIN_ESC0 + i, wave_bin_items(BIN_ESC0 + i, n), wide, fill,
+                                       f64, sw);
+            });
+    }
+    // on one stream the queues go one after the other (nothing to overlap;
+    // each launch group's timing events then bracket only its own kernels)
+    const bool interleave = !(p->flags & SPGEMM_ONE_STREAM);
+    // the heavy columns' chain is the longest: all its launches but the last
+    // go before the side streams' first ones
+    if (interleave) {
+        LaunchQueue &x = q[1];
+        while (x.next + 1 < x.l.size()) {
+            if (x.next == 0) x.ps.emplace(x.name, x.st);
+            if ((e = x.l[x.next++]())) return e;
+        }
+    }
     for (bool more = true; more;) {
         more = false;
         for (LaunchQueue &x : q) {
-            if (x.next == x.l.size()) continue;
-            if (x.next == 0) x.ps.emplace(x.name, x.st);
-            if ((e = x.l[x.next++]())) return e;
-            if (x.next == x.l.size()) x.ps.reset();
-            more = true;
+            while (x.next < x.l.size()) {
+                if (x.next == 0) x.ps.emplace(x.name, x.st);
+                if ((e = x.l[x.next++]())) return e;
+                if (x.next == x.l.size()) x.ps.reset();
+                more = true;
+                if (interleave) break;
+            }
         }
     }
     return join(p, s, used);
