@@ -86,9 +86,10 @@ __device__ __forceinline__ unsigned long long kx(unsigned long long v) {
 // chosen per lane.
 // (Written as the instruction itself: spelled as min and max, the network's
 // chains of them send the compiler's combiner into a very long search.)
-// The result replaces x in its register.
-__device__ __forceinline__ void med3u(unsigned &x, unsigned y, unsigned c) {
-    asm("v_med3_u32 %0, %0, %1, %2" : "+v"(x) : "v"(y), "v"(c));
+__device__ __forceinline__ unsigned med3u(unsigned x, unsigned y, unsigned c) {
+    unsigned r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(y), "v"(c));
+    return r;
 }
 
 // one compare-exchange stage between lanes at distance J (J >= 1)
@@ -100,11 +101,7 @@ __device__ __forceinline__ void lane_stage(K (&key)[KPL], int k, int lane) {
     if constexpr (sizeof(K) == 4) {
         const unsigned c = take_min ? 0u : ~0u;
 #pragma unroll
-        for (int r = 0; r < KPL; ++r) {
-            unsigned x = (unsigned)key[r];
-            med3u(x, kx<J>(x), c);
-            key[r] = (K)x;
-        }
+        for (int r = 0; r < KPL; ++r) key[r] = (K)med3u((unsigned)key[r], kx<J>((unsigned)key[r]), c);
     } else {
 #pragma unroll
         for (int r = 0; r < KPL; ++r) {
@@ -138,12 +135,9 @@ __device__ __forceinline__ void seg_sort(K (&key)[KPL], int lane_in) {
                 for (int r = 0; r < KPL; ++r) {
                     if (r & j) continue;
                     const int rp = r | j;
-                    unsigned x = (unsigned)key[r], y = (unsigned)key[rp];
-                    const unsigned x0 = x;
-                    med3u(x, y, c);
-                    med3u(y, x0, ~c);
-                    key[r] = (K)x;
-                    key[rp] = (K)y;
+                    const unsigned x = (unsigned)key[r], y = (unsigned)key[rp];
+                    key[r] = (K)med3u(x, y, c);
+                    key[rp] = (K)med3u(x, y, ~c);
                 }
             } else if (j < KPL) {
 #pragma unroll
