@@ -10,6 +10,9 @@ namespace spg {
 // stored B entries are contiguous; threads walk them flat (coalesced reads of
 // B.rowidx, gathers of A.colptr), and add Z^A_k to the owning column's count.
 // Every index read here is checked before it is used as an address.
+// two consecutive ints at 4-byte alignment
+typedef int int2a __attribute__((ext_vector_type(2), aligned(4)));
+
 __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     __shared__ int s_bcp[kTile + 1];
     __shared__ unsigned long long s_op[kTile];
@@ -57,9 +60,14 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
 
     const int pb = s_bcp[0], pe = s_bcp[nt];
     const gmem<const int32_t> *__restrict__ bri = to_gmem(d.bri);
-    const gmem<const int32_t> *__restrict__ acp = to_gmem(d.acp);
+    // A.colptr read as pairs of consecutive pointers
+    const gmem<const int2a> *acp2 = (const gmem<const int2a> *)to_gmem(d.acp);
     err = 0;
-    for (int p0 = pb; p0 < pe; p0 += 4 * kBlock) {
+    // with no A columns every stored B entry is out of range (and A.colptr
+    // holds one entry: the pair loads below need two)
+    const int pe_ok = d.k > 0 ? pe : pb;
+    if (d.k == 0 && pe > pb) err = ERR_CSC;
+    for (int p0 = pb; p0 < pe_ok; p0 += 4 * kBlock) {
         // Every load of the pass is issued before any is used: a slot past
         // the tile's end reads its last entry, an index out of range reads
         // A's first column pointers; neither result is used.
@@ -68,9 +76,12 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
         for (int u = 0; u < 4; ++u) kk[u] = bri[min(p0 + u * kBlock + tid, pe - 1)];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
+            // both column pointers in one 8-byte load (4-byte alignment is
+            // enough for a global load): kc < k, so kc + 1 <= k stays inside
             const int kc = (kk[u] < 0 || kk[u] >= d.k) ? 0 : kk[u];
-            x0[u] = acp[kc];
-            x1[u] = acp[min(kc + 1, d.k)];
+            const int2a x = *(const gmem<const int2a> *)((const gmem<const int32_t> *)acp2 + kc);
+            x0[u] = x.x;
+            x1[u] = x.y;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {

@@ -265,11 +265,17 @@ def _bad_case(kind):
         cp = B.colptr.copy()
         cp[-1] -= 1
         B = gen.CSC(B.nrows, B.ncols, cp, B.rowidx, B.val)
+    elif kind == "a_without_columns":
+        # A has no columns (its column pointers are one entry), B stores
+        # entries: every row of B is out of range
+        A = gen.CSC(300, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+        cp = np.array([0, 2, 2, 3], np.int32)
+        B = gen.CSC(0, 3, cp, np.zeros(3, np.int32), np.ones(3))
     return A, B
 
 
 @pytest.mark.parametrize("kind", ["b_row_out_of_range", "a_row_out_of_range",
-                                  "b_colptr_decreasing", "b_colptr_last"])
+                                  "b_colptr_decreasing", "b_colptr_last", "a_without_columns"])
 def test_device_input_checks(kind):
     """Malformed inputs are reported (SPGEMM_ERR_CSC) by the kernels' own
     range checks, which run before any index is used as an address."""
