@@ -18,6 +18,14 @@ __device__ __forceinline__ gmem<T> *to_gmem(T *p) {
     return (gmem<T> *)p;
 }
 
+// two consecutive ints at 4-byte alignment (a column pointer and the next one)
+typedef int int2a __attribute__((ext_vector_type(2), aligned(4)));
+
+// p[i] and p[i + 1] in one 8-byte load; the caller keeps i + 1 inside the array
+__device__ __forceinline__ int2a load_pair(const int32_t *p, long long i) {
+    return *(const gmem<const int2a> *)((const gmem<const int32_t> *)p + i);
+}
+
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }

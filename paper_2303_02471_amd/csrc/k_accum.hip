@@ -378,10 +378,10 @@ __device__ __forceinline__ void item_sort_compress(const KArgs &a, const Prob &d
         }
         // output start of every column; a count that differs from the
         // symbolic phase's means other inputs (nothing is written then)
-        const gmem<const int32_t> *ccp = to_gmem((const int32_t *)d.ccp);
         if (lane < ncol) {
             const int j = gcol[lane] - d.col0;
-            const int c0 = ccp[j], clen = ccp[j + 1] - c0;
+            const int2a cp = load_pair(d.ccp, j);
+            const int c0 = cp.x, clen = cp.y - c0;
             L.colv[lane] = L.seg_out[lane] == clen ? c0 : -1;
             if (a.spec_fill) a.gnnz[gcol[lane]] = L.seg_out[lane];
         }
@@ -681,8 +681,9 @@ __global__ __launch_bounds__(64) void k_acc_lane(KArgs a, int bin) {
         int c0 = 0, clen = 0;
         if (FILL) {
             const int j = g - d.col0;
-            c0 = d.ccp[j];
-            clen = d.ccp[j + 1] - c0;
+            const int2a cp = load_pair(d.ccp, j);
+            c0 = cp.x;
+            clen = cp.y - c0;
         }
         const int2 *__restrict__ Ep = a.E + d.ebase;
         const gmem<const V> *__restrict__ bvp = to_gmem((const V *)d.bv);

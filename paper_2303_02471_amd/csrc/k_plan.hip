@@ -10,9 +10,6 @@ namespace spg {
 // stored B entries are contiguous; threads walk them flat (coalesced reads of
 // B.rowidx, gathers of A.colptr), and add Z^A_k to the owning column's count.
 // Every index read here is checked before it is used as an address.
-// two consecutive ints at 4-byte alignment
-typedef int int2a __attribute__((ext_vector_type(2), aligned(4)));
-
 __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
     __shared__ int s_bcp[kTile + 1];
     __shared__ unsigned long long s_op[kTile];
@@ -60,8 +57,6 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
 
     const int pb = s_bcp[0], pe = s_bcp[nt];
     const gmem<const int32_t> *__restrict__ bri = to_gmem(d.bri);
-    // A.colptr read as pairs of consecutive pointers
-    const gmem<const int2a> *acp2 = (const gmem<const int2a> *)to_gmem(d.acp);
     err = 0;
     // with no A columns every stored B entry is out of range (and A.colptr
     // holds one entry: the pair loads below need two)
@@ -79,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
             // both column pointers in one 8-byte load (4-byte alignment is
             // enough for a global load): kc < k, so kc + 1 <= k stays inside
             const int kc = (kk[u] < 0 || kk[u] >= d.k) ? 0 : kk[u];
-            const int2a x = *(const gmem<const int2a> *)((const gmem<const int32_t> *)acp2 + kc);
+            const int2a x = load_pair(d.acp, kc);
             x0[u] = x.x;
             x1[u] = x.y;
         }
