@@ -230,8 +230,12 @@ __device__ __forceinline__ void fill_heads(int (&qb)[KPL], V (&bb)[KPL], int lan
 // segment's run count (valid in every lane of the segment).
 template <typename K, int KPL, int S>
 __device__ __forceinline__ void seg_runs(const K (&key)[KPL], bool (&head)[KPL], int (&run)[KPL],
-                                         int &seg_total, int lane) {
+                                         int &seg_total, int lane_in) {
     constexpr K KMAX = KeyTraits<K>::kmax;
+    // opaque lane number: the permute addresses below stay inside the
+    // caller's loop instead of occupying registers for the whole kernel
+    int lane = lane_in;
+    asm volatile("" : "+v"(lane));
     const int s0 = lane * KPL;
     // the last key of the lane below (the previous position of this lane's first)
     K prev;
@@ -989,6 +993,19 @@ __global__ __launch_bounds__(kBlock) void k_heavy_expand(KArgs a) {
     if (rowbad) atomicOr(&a.hdr->err, ERR_CSC);
 }
 
+// A product index kept in a value slot of the wave buffer (its first 4 bytes)
+// until the value replaces it.
+template <typename V>
+__device__ __forceinline__ void put_index(V &slot, int e) {
+    __builtin_memcpy(&slot, &e, 4);
+}
+template <typename V>
+__device__ __forceinline__ int get_index(const V &slot) {
+    int e;
+    __builtin_memcpy(&e, &slot, 4);
+    return e;
+}
+
 // One window of a heavy column per wavefront (grid-stride over all windows):
 // rows [m w / W, m (w + 1) / W) of the column's products, compacted in product
 // order into the buffer, sorted, compressed. A window holding more products
@@ -999,6 +1016,10 @@ template <typename K, typename V, bool FILL>
 __global__ __launch_bounds__(64) void k_acc_window(KArgs a) {
     constexpr int KPL = kWinKpl, N = 64 * KPL;
     constexpr K KMAX = KeyTraits<K>::kmax;
+    // Values gathered after the scan (one batch, one memory round trip per
+    // scan step fewer) where the registers it takes cost no occupancy: 32-bit
+    // keys with 8-byte values, whose wave buffer already allows 3 waves per SIMD
+    constexpr bool kDefer = sizeof(K) == 4 && sizeof(V) == 8;
     __shared__ WaveLds<K, V, N, FILL> L;
     if (__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) |
         (FILL ? __atomic_load_n(&a.hdr->cap_over, __ATOMIC_RELAXED) : 0))
@@ -1063,18 +1084,20 @@ __global__ __launch_bounds__(64) void k_acc_window(KArgs a) {
                     pos[u] = cnt + popc64(bm & mask_lt());
                     cnt += popc64(bm);
                 }
-                V vv[U];
+                // deferred: the value slot holds the product's index until
+                // the scan ends; else the values are gathered here
+                V vv[kDefer ? 1 : U];
+                if constexpr (FILL && !kDefer) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int e = e0 + u * 64 + lane;
-                    vv[u] = V(0);
-                    if (FILL && in[u] && pos[u] < N) vv[u] = pval[e];
+                    for (int u = 0; u < U; ++u)
+                        vv[u] = in[u] && pos[u] < N ? pval[e0 + u * 64 + lane] : V(0);
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (in[u] && pos[u] < N) {
                         L.key[pos[u]] = ((K)(unsigned)r[u] << kKeyBits) | (K)(unsigned)pos[u];
-                        if (FILL) L.val[pos[u]] = vv[u];
+                        if constexpr (FILL && kDefer) put_index(L.val[pos[u]], e0 + u * 64 + lane);
+                        if constexpr (FILL && !kDefer) L.val[pos[u]] = vv[u];
                     }
                 }
             }
@@ -1117,6 +1140,26 @@ __global__ __launch_bounds__(64) void k_acc_window(KArgs a) {
                 total += 1;
                 wsync();
                 continue;
+            }
+            if constexpr (FILL && kDefer) {
+                // the values of the window's products, one batch of gathers
+                // (the scan above waited on its rows only)
+                constexpr int H = KPL / 2;  // half the slots per batch (registers)
+#pragma unroll
+                for (int h = 0; h < KPL; h += H) {
+                    V vv[H];
+#pragma unroll
+                    for (int r = 0; r < H; ++r) {
+                        const int s = (h + r) * 64 + lane;
+                        vv[r] = s < cnt ? pval[get_index(L.val[s])] : V(0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < H; ++r) {
+                        const int s = (h + r) * 64 + lane;
+                        if (s < cnt) L.val[s] = vv[r];
+                    }
+                    wsync();
+                }
             }
             // sort and compress the buffer as one segment
             K key[KPL];
