@@ -318,7 +318,7 @@ template <typename K, typename V, int KPL, int S, bool FILL>
 __device__ __forceinline__ void item_sort_compress(const KArgs &a, const Prob &d, int pid,
                                                    WaveLds<K, V, 64 * KPL, FILL> &L,
                                                    K (&key)[KPL], int ncol, const int *gcol,
-                                                   int lane, int &bad) {
+                                                   int2a ccp_lane, int lane, int &bad) {
     constexpr int N = 64 * KPL, G = N / S;
     constexpr K KMAX = KeyTraits<K>::kmax;
     seg_sort<K, KPL, S>(key, lane);
@@ -383,9 +383,8 @@ __device__ __forceinline__ void item_sort_compress(const KArgs &a, const Prob &d
         // output start of every column; a count that differs from the
         // symbolic phase's means other inputs (nothing is written then)
         if (lane < ncol) {
-            const int j = gcol[lane] - d.col0;
-            const int2a cp = load_pair(d.ccp, j);
-            const int c0 = cp.x, clen = cp.y - c0;
+            // the column's bounds in C, loaded when the item started
+            const int c0 = ccp_lane.x, clen = ccp_lane.y - c0;
             L.colv[lane] = L.seg_out[lane] == clen ? c0 : -1;
             if (a.spec_fill) a.gnnz[gcol[lane]] = L.seg_out[lane];
         }
@@ -626,11 +625,16 @@ __global__ __launch_bounds__(64) void k_acc_wave(KArgs a, int bin) {
             int c1 = c0 + 1;
             while (c1 < ncol && s_g[c1] >= d.col0 && s_g[c1] < d.col0 + d.n) ++c1;
             K key[KPL];
+            // the filling pass's column bounds in C (known before the kernel)
+            // load now; they are used after the sort
+            int2a ccp_lane = {0, 0};
+            if (FILL && lane < c1 - c0) ccp_lane = load_pair(d.ccp, s_g[c0 + lane] - d.col0);
             if (c0 == 0 && c1 == ncol) {
                 if (!item_gather<K, V, KPL, S, FILL>(a, d, L, key, ncol, s_bs, s_nb, s_op, lane))
                     bad = 1;
                 else
-                    item_sort_compress<K, V, KPL, S, FILL>(a, d, pid, L, key, ncol, s_g, lane, bad);
+                    item_sort_compress<K, V, KPL, S, FILL>(a, d, pid, L, key, ncol, s_g, ccp_lane,
+                                                           lane, bad);
             } else {
                 // a group spanning problems: each problem's columns as an item
                 // of their own (at the front of the buffer)
@@ -639,7 +643,7 @@ __global__ __launch_bounds__(64) void k_acc_wave(KArgs a, int bin) {
                     bad = 1;
                 else
                     item_sort_compress<K, V, KPL, S, FILL>(a, d, pid, L, key, c1 - c0, s_g + c0,
-                                                           lane, bad);
+                                                           ccp_lane, lane, bad);
             }
             c0 = c1;
         }
