@@ -38,6 +38,7 @@ enum Bin : int {
     NBINS = 18
 };
 constexpr int kEscBins = 7;
+constexpr unsigned long long kSmallProducts = 1u << 20;  // below: accumulators on one stream
 constexpr int kEscSide0 = 5;  // wavefront sub-bins below this (at most 64 products) share one
                               // accumulator stream, the larger ones the one-column waves' stream
 constexpr int kSortBins = 4;

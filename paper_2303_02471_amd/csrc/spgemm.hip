@@ -738,19 +738,25 @@ hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t
     const bool f64 = p->dt == SPGEMM_F64;
     const bool wide = p->wide_acc;
     hipError_t e;
+    // a small product runs on the caller's stream alone: the events of a
+    // fork and join cost more than the overlap gains
+    const bool one = (p->flags & SPGEMM_ONE_STREAM) || h.total_op < kSmallProducts;
+    auto on = [&](int i) { return one ? s : side(p, i, s); };
     unsigned used = 0;
-    for (int i = 0; i < kEscBins; ++i)
-        if (h.bin_count[BIN_ESC0 + i]) used |= i < kEscSide0 ? 1u : 2u;
-    for (int c = 0; c < 2; ++c)
-        if (h.bin_count[BIN_SORT0 + c]) used |= 2u;
+    if (!one) {
+        for (int i = 0; i < kEscBins; ++i)
+            if (h.bin_count[BIN_ESC0 + i]) used |= i < kEscSide0 ? 1u : 2u;
+        for (int c = 0; c < 2; ++c)
+            if (h.bin_count[BIN_SORT0 + c]) used |= 2u;
+    }
     if ((e = fork(p, s, used))) return e;
     if (plan_heavy) {
         ProfScope ps("heavy_plan", s);
         if ((e = launch_heavy_plan(a, s))) return e;
     }
-    LaunchQueue q[3] = {{fill ? "esc_numeric" : "esc_symbolic", side(p, 0, s), {}},
+    LaunchQueue q[3] = {{fill ? "esc_numeric" : "esc_symbolic", on(0), {}},
                         {fill ? "heavy_numeric" : "heavy_symbolic", s, {}},
-                        {fill ? "wave_numeric" : "wave_symbolic", side(p, 1, s), {}}};
+                        {fill ? "wave_numeric" : "wave_symbolic", on(1), {}}};
     // side stream 0: the lightest sub-bins as lane-per-column blocks (option),
     // then the wavefront sub-bins from the largest down
     const bool lbk = (p->flags & SPGEMM_LANE_BLOCKED) != 0;
@@ -803,7 +809,7 @@ hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t
     }
     // on one stream the queues go one after the other (nothing to overlap;
     // each launch group's timing events then bracket only its own kernels)
-    const bool interleave = !(p->flags & SPGEMM_ONE_STREAM);
+    const bool interleave = !one;
     // the heavy columns' chain is the longest: all its launches but the last
     // go before the side streams' first ones
     if (interleave) {
