@@ -123,7 +123,8 @@ spgemm_status spgemm_set_allocator(spgemm_alloc_fn alloc, spgemm_free_fn free_fn
 #define SPGEMM_VALIDATE 1u /* host-side check of both inputs, including repeated rows per column */
 #define SPGEMM_ONE_STREAM 2u /* run every accumulator kind on the caller's stream instead of
                                  overlapping them on internal side streams (same results;
-                                 per-kernel timings without overlap) */
+                                 per-kernel timings without overlap); products of fewer
+                                 than 2^20 products do so without the flag */
 #define SPGEMM_NO_PLANNED_LAUNCH 4u /* always read the bin sizes back before launching the
                                        accumulators (by default a plan that has run before
                                        launches the whole symbolic phase from its previous
