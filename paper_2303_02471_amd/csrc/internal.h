@@ -285,8 +285,10 @@ hipError_t launch_lane_blocked(const KArgs &a, const LbArgs &lb, int ncols_hint,
 
 // heavy columns: windows, or (radix) the global radix ESC; heavy_products and
 // rowbits size the radix launch
-// part 0 .. heavy_parts(radix) - 1 of the heavy columns' launches, in order
+// part 0 .. heavy_parts(radix) - 1 of the heavy columns' launches, in order;
+// a launch whose heavy plan ran in it (planned) starts at heavy_first_part
 int heavy_parts(bool radix);
+int heavy_first_part(bool radix, bool planned);
 hipError_t launch_heavy(const KArgs &a, int ncols, int nwin, bool wide, bool fill, bool f64,
                         hipStream_t s, bool radix, long long heavy_products, int rowbits,
                         int part);

@@ -832,7 +832,8 @@ __global__ __launch_bounds__(64) void k_acc_lane(KArgs a, int bin) {
 // ---------------------------------------------------------------- heavy columns
 // Plan of the heavy columns (bins SORT2, SORT3 and WSORT: more than 1024
 // products; contiguous in the bin list): per column its first product in the heavy scratch (hoff) and its
-// first window (wbase), W = ceil(Op / kWinTarget) windows of equal row span.
+// first window (wbase), W = ceil(Op / kWinTarget) windows of equal row span;
+// in a planned launch also the map of windows to columns.
 // One workgroup; the totals go to the header (the host sizes the scratch from
 // them). A planned launch whose scratch is too small is redone.
 constexpr int kWinKpl = 16;                     // positions per lane of a window's buffer
@@ -884,6 +885,11 @@ __global__ __launch_bounds__(1024) void k_heavy_plan(KArgs a) {
         if (i < n) {
             a.hoff[i] = pcarry + pex;
             a.wbase[i] = wcarry + wex;
+            // a planned launch has its window scratch already: the column's
+            // windows are mapped here (as far as it holds them; more windows
+            // than it holds ask for a redo below)
+            if (a.spec_total >= 0)
+                for (int q = wcarry + wex; q < wcarry + wex + nw && q < a.win_cap; ++q) a.winmap[q] = i;
         }
         pcarry += s_tmp[T / 64];
         wcarry += wt;
@@ -1286,6 +1292,9 @@ hipError_t launch_heavy_plan(const KArgs &a, hipStream_t s) {
 // with other streams' launches): windows take the map of windows, the
 // expansion and the windowed sort; the radix ESC the expansion and the sort.
 int heavy_parts(bool radix) { return radix ? 2 : 3; }
+// the first part a launch needs: the windows' map is written by the heavy
+// plan of a planned launch
+int heavy_first_part(bool radix, bool planned) { return !radix && planned ? 1 : 0; }
 
 hipError_t launch_heavy(const KArgs &a, int ncols, int nwin, bool wide, bool fill, bool f64,
                         hipStream_t s, bool radix, long long heavy_products, int rowbits,

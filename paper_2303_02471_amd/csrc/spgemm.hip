@@ -785,7 +785,8 @@ hipError_t launch_direct_accumulators(spgemm_plan p, const KArgs &a, hipStream_t
         const bool radix = (p->flags & SPGEMM_RADIX_ESC) != 0;
         const int nwin = h.heavy_win, rowbits = p->rowbits;
         const long long hp = (long long)h.heavy_prod;
-        for (int part = 0; part < heavy_parts(radix); ++part)
+        for (int part = heavy_first_part(radix, plan_heavy && a.spec_total >= 0);
+             part < heavy_parts(radix); ++part)
             q[1].l.push_back([=, &a] {
                 return launch_heavy(a, nheavy, nwin, wide, fill, f64, s, radix, hp, rowbits, part);
             });
