@@ -358,7 +358,7 @@ def copy_calibration():
 # launch group -> kernel symbol (FP64 runs)
 # launch groups whose HBM traffic --record-traffic can record: the kernels of
 # one launch of the group (their per-dispatch traffic adds up)
-KERNEL_SYMBOL = {"heavy_numeric": ("k_win_map", "k_heavy_expand<double, true>",
+KERNEL_SYMBOL = {"heavy_numeric": ("k_heavy_expand<double, true>",
                                    "k_acc_window<unsigned int, double, true>"),
                  "wave_numeric": ("k_acc_wave<unsigned int, double, 16, 1024, true>",
                                   "k_acc_wave<unsigned int, double, 8, 512, true>",
