@@ -366,7 +366,7 @@ KERNEL_SYMBOL = {"heavy_numeric": ("k_heavy_expand<double, true>",
                                   "k_acc_wave<unsigned int, double, 4, 256, true>"),
                  "esc_numeric": ("k_acc_lane<unsigned int, double, 4, true>",
                                  "k_acc_lane<unsigned int, double, 8, true>",
-                                 "k_acc_lane<unsigned int, double, 16, true>",
+                                 "k_acc_wave<unsigned int, double, 4, 16, true>",
                                  "k_acc_wave<unsigned int, double, 4, 32, true>",
                                  "k_acc_wave<unsigned int, double, 4, 64, true>"),
                  "numeric": ("k_numeric<double>",), "expand": ("k_expand",)}

@@ -39,6 +39,7 @@ enum Bin : int {
 };
 constexpr int kEscBins = 7;
 constexpr unsigned long long kSmallProducts = 1u << 20;  // below: accumulators on one stream
+constexpr int kLaneSubBins = 2;  // wavefront sub-bins below this: one column per lane
 constexpr int kEscSide0 = 5;  // wavefront sub-bins below this (at most 64 products) share one
                               // accumulator stream, the larger ones the one-column waves' stream
 constexpr int kSortBins = 4;

@@ -1240,8 +1240,10 @@ __global__ __launch_bounds__(64) void k_acc_window(KArgs a) {
 }
 
 // ---------------------------------------------------------------- launchers
-// ESC sub-bin i (columns of at most 4 << i products): KPL = 4 (256 positions),
-// segments of 4 << i. Sort bins 0 and 1 (at most 512, 1024 products): one
+// ESC sub-bins 0 and 1 (at most 4, 8 products): one column per lane. ESC
+// sub-bin i >= 2 (at most 4 << i products): KPL = 4 (256 positions), segments
+// of 4 << i (measured: segments of 16 beat a lane per column by 16%, segments
+// of 8 lose by 14%). Sort bins 0 and 1 (at most 512, 1024 products): one
 // column per wave, KPL = 8, 16. Larger columns are heavy.
 template <typename K, typename V, bool FILL>
 static hipError_t launch_wave_bin(const KArgs &a, int bin, int grid, hipStream_t s) {
@@ -1249,7 +1251,7 @@ static hipError_t launch_wave_bin(const KArgs &a, int bin, int grid, hipStream_t
     switch (bin) {
         case BIN_ESC0 + 0: hipLaunchKernelGGL((k_acc_lane<K, V, 4, FILL>), g, t, 0, s, a, bin); break;
         case BIN_ESC0 + 1: hipLaunchKernelGGL((k_acc_lane<K, V, 8, FILL>), g, t, 0, s, a, bin); break;
-        case BIN_ESC0 + 2: hipLaunchKernelGGL((k_acc_lane<K, V, 16, FILL>), g, t, 0, s, a, bin); break;
+        case BIN_ESC0 + 2: hipLaunchKernelGGL((k_acc_wave<K, V, 4, 16, FILL>), g, t, 0, s, a, bin); break;
         case BIN_ESC0 + 3: hipLaunchKernelGGL((k_acc_wave<K, V, 4, 32, FILL>), g, t, 0, s, a, bin); break;
         case BIN_ESC0 + 4: hipLaunchKernelGGL((k_acc_wave<K, V, 4, 64, FILL>), g, t, 0, s, a, bin); break;
         case BIN_ESC0 + 5: hipLaunchKernelGGL((k_acc_wave<K, V, 4, 128, FILL>), g, t, 0, s, a, bin); break;
@@ -1261,10 +1263,10 @@ static hipError_t launch_wave_bin(const KArgs &a, int bin, int grid, hipStream_t
     return hipGetLastError();
 }
 
-// work items of a wave bin: 64 columns (one per lane: ESC sub-bins 0..2),
+// work items of a wave bin: 64 columns (one per lane: ESC sub-bins 0 and 1),
 // groups of columns (the other ESC sub-bins) or columns (sort bins)
 int wave_bin_items(int bin, int ncols) {
-    if (bin >= BIN_ESC0 && bin < BIN_ESC0 + 3) return ceil_div(ncols, 64);
+    if (bin >= BIN_ESC0 && bin < BIN_ESC0 + kLaneSubBins) return ceil_div(ncols, 64);
     if (bin >= BIN_ESC0 && bin < BIN_ESC0 + kEscBins) return ceil_div(ncols, 64 >> (bin - BIN_ESC0));
     return ncols;
 }
