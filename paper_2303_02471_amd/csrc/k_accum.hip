@@ -840,7 +840,7 @@ constexpr int kWinKpl = 16;                     // positions per lane of a windo
 constexpr int kWinTarget = 64 * kWinKpl * 7 / 8;  // planned products per window
 
 __global__ __launch_bounds__(1024) void k_heavy_plan(KArgs a) {
-    constexpr int T = 1024;
+    constexpr int T = 1024, PT = 4;
     __shared__ int tmp[T / 64 + 1];
     __shared__ long long s_tmp[T / 64 + 1];
     if (__syncthreads_or(__atomic_load_n(&a.hdr->err, __ATOMIC_RELAXED) != 0)) return;
@@ -851,17 +851,24 @@ __global__ __launch_bounds__(1024) void k_heavy_plan(KArgs a) {
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     long long pcarry = 0;
     int wcarry = 0;
-    for (int i0 = 0; i0 < n; i0 += T) {
-        const int i = i0 + tid;
-        int op = 0, nw = 0;
-        if (i < n) {
-            op = a.binlist[first + i].w;
-            nw = max(1, ceil_div(op, kWinTarget));
+    // PT consecutive columns per thread: one scan step covers T PT columns
+    for (int i0 = 0; i0 < n; i0 += T * PT) {
+        const int ib = i0 + tid * PT;
+        int op[PT], nw[PT];
+        int wsum = 0;
+        long long v = 0;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int i = ib + u;
+            op[u] = i < n ? a.binlist[first + i].w : 0;
+            nw[u] = i < n ? max(1, ceil_div(op[u], kWinTarget)) : 0;
+            wsum += nw[u];
+            v += op[u];
         }
         int wt;
-        const int wex = wg_excl_scan<T>(nw, tmp, wt);
+        const int wex = wg_excl_scan<T>(wsum, tmp, wt);
         // 64-bit prefix of the products
-        long long v = op, inc = v;
+        long long inc = v;
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
             const int lo = shfl_up_i((int)(unsigned)inc, dd);
@@ -881,15 +888,22 @@ __global__ __launch_bounds__(1024) void k_heavy_plan(KArgs a) {
             s_tmp[T / 64] = run;
         }
         __syncthreads();
-        const long long pex = s_tmp[w] + inc - v;
-        if (i < n) {
-            a.hoff[i] = pcarry + pex;
-            a.wbase[i] = wcarry + wex;
-            // a planned launch has its window scratch already: the column's
-            // windows are mapped here (as far as it holds them; more windows
-            // than it holds ask for a redo below)
-            if (a.spec_total >= 0)
-                for (int q = wcarry + wex; q < wcarry + wex + nw && q < a.win_cap; ++q) a.winmap[q] = i;
+        long long pr = pcarry + s_tmp[w] + inc - v;
+        int wr = wcarry + wex;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int i = ib + u;
+            if (i < n) {
+                a.hoff[i] = pr;
+                a.wbase[i] = wr;
+                // a planned launch has its window scratch already: the
+                // column's windows are mapped here (as far as it holds them;
+                // more windows than it holds ask for a redo below)
+                if (a.spec_total >= 0)
+                    for (int q = wr; q < wr + nw[u] && q < a.win_cap; ++q) a.winmap[q] = i;
+            }
+            pr += op[u];
+            wr += nw[u];
         }
         pcarry += s_tmp[T / 64];
         wcarry += wt;

@@ -141,20 +141,29 @@ __global__ __launch_bounds__(kBlock) void k_classify(KArgs a) {
 // Workgroup b < NBINS: exclusive scan of bin b's per-tile counts (in place:
 // each tile's first position inside the bin) and the bin's total. Workgroup
 // NBINS: the product total and the largest chunk count.
-__global__ __launch_bounds__(1024) void k_tally(KArgs a) {
-    constexpr int T = 1024;
+__global__ __launch_bounds__(256) void k_tally(KArgs a) {
+    constexpr int T = 256, PT = 8;  // threads, consecutive tiles per thread
     __shared__ int tmp[T / 64 + 1];
     __shared__ unsigned long long s_tot;
     __shared__ int s_max;
     const int tid = threadIdx.x, b = blockIdx.x, nt = a.ntiles;
     if (b < NBINS) {
         int carry = 0;
-        for (int t0 = 0; t0 < nt; t0 += T) {
-            const int t = t0 + tid;
-            const int v = t < nt ? a.th[t * NBINS + b] : 0;
+        for (int t0 = 0; t0 < nt; t0 += T * PT) {
+            const int tb = t0 + tid * PT;
+            int v[PT], sum = 0;
+#pragma unroll
+            for (int u = 0; u < PT; ++u) {
+                v[u] = tb + u < nt ? a.th[(tb + u) * NBINS + b] : 0;
+                sum += v[u];
+            }
             int total;
-            const int ex = wg_excl_scan<T>(v, tmp, total);
-            if (t < nt) a.th[t * NBINS + b] = carry + ex;
+            int run = carry + wg_excl_scan<T>(sum, tmp, total);
+#pragma unroll
+            for (int u = 0; u < PT; ++u) {
+                if (tb + u < nt) a.th[(tb + u) * NBINS + b] = run;
+                run += v[u];
+            }
             carry += total;
         }
         if (tid == 0) {
@@ -171,9 +180,15 @@ __global__ __launch_bounds__(1024) void k_tally(KArgs a) {
         __syncthreads();
         unsigned long long tot = 0;
         int mx = 0;
-        for (int t = tid; t < nt; t += T) {
-            tot += (unsigned long long)a.ttot[t];
-            mx = max(mx, a.tmax[t]);
+        for (int t0 = 0; t0 < nt; t0 += T * PT) {
+#pragma unroll
+            for (int u = 0; u < PT; ++u) {
+                const int t = t0 + u * T + tid;
+                if (t < nt) {
+                    tot += (unsigned long long)a.ttot[t];
+                    mx = max(mx, a.tmax[t]);
+                }
+            }
         }
         atomicAdd(&s_tot, tot);
         atomicMax(&s_max, mx);
@@ -190,7 +205,7 @@ __global__ __launch_bounds__(1024) void k_tally(KArgs a) {
 
 hipError_t launch_tally(const KArgs &a, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tally, dim3(NBINS + 1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_tally, dim3(NBINS + 1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
