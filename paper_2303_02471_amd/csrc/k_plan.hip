@@ -242,12 +242,21 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
             run += a.hdr->bin_count[b];
         }
     }
-    // column c = 64 (NW u + w) + lane: passes and waves in column order
-    int rank[PER], binv[PER];
+    // column c = 64 (NW u + w) + lane: passes and waves in column order; the
+    // column's entries and product count load together with its bin
+    const int32_t *bcp = a.nprob == 1 ? a.single.bcp : a.table[pid].bcp;
+    int rank[PER], binv[PER], opv[PER];
+    int2a bse[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int c = 64 * (NW * u + w) + lane;
-        binv[u] = c < nt ? a.binw[col0 + j0 + c] : -1;
+        const bool in = c < nt;
+        binv[u] = in ? a.binw[col0 + j0 + c] : -1;
+        bse[u] = in ? load_pair(bcp, j0 + c) : int2a{0, 0};
+        opv[u] = in ? a.op[col0 + j0 + c] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
         rank[u] = 0;
         for (int b = 0; b < NBINS; ++b) {
             const unsigned long long m = ballot(binv[u] == b);
@@ -267,14 +276,13 @@ __global__ __launch_bounds__(kBlock) void k_place(KArgs a) {
         }
     }
     __syncthreads();
-    const int32_t *bcp = a.nprob == 1 ? a.single.bcp : a.table[pid].bcp;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int c = 64 * (NW * u + w) + lane;
         if (c >= nt) continue;
         const int g = col0 + j0 + c;
-        const int bs = bcp[j0 + c], nb = bcp[j0 + c + 1] - bs;
-        a.binlist[s_cnt[NW * u + w][binv[u]] + rank[u]] = make_int4(g, bs, nb, a.op[g]);
+        a.binlist[s_cnt[NW * u + w][binv[u]] + rank[u]] =
+            make_int4(g, bse[u].x, bse[u].y - bse[u].x, opv[u]);
     }
 }
 
