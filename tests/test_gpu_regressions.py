@@ -210,3 +210,26 @@ def test_one_call_product_after_structure_change():
                               f"step {step}")
         assert_values_exact(v[:nnz].cpu().numpy(), ov, f"step {step}")
     plan.close()
+
+
+def test_one_call_heavy_windows_outgrow_the_plan():
+    """One-call products on a reused plan whose heavy columns (above 1024
+    products) need more row windows than the previous call planned: the heavy
+    plan maps only the windows the scratch holds and asks for a redo, which
+    grows the scratch. Then the smaller structure again. Every result equals
+    the oracle's."""
+    _say("one-call product, heavy windows outgrow the plan")
+    A = gen.uniform_z(4000, 20, seed=31)
+    B_small = gen.uniform_z(30, 60, seed=32, nrows=4000)   # 1200 products: 2 windows per column
+    B_large = gen.uniform_z(30, 200, seed=33, nrows=4000)  # 4000 products: 5 windows per column
+    At = api.CscTensor.from_host(A)
+    plan, out = None, None
+    for B in (B_small, B_small, B_large, B_large, B_small):
+        Bt = api.CscTensor.from_host(B)
+        plan, colptr, ri_, v, nnz = api.multiply(At, Bt, plan=plan, out=out)
+        out = (colptr, ri_, v)
+        torch.cuda.synchronize()
+        ocp, ori, ov = oracle.spgemm(A, B)
+        assert_same_structure(colptr.cpu().numpy(), ri_[:nnz].cpu().numpy(), ocp, ori, "heavy windows")
+        assert_values_exact(v[:nnz].cpu().numpy(), ov, "heavy windows")
+    plan.close()
