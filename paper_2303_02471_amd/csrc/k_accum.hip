@@ -1057,8 +1057,17 @@ __global__ __launch_bounds__(64) void k_acc_window(KArgs a) {
     for (int b = kHeavyBin; b <= BIN_WSORT; ++b) n += a.hdr->bin_count[b];
     const int nwin = a.wbase[n];
     int bad = 0;
-    // windows of the largest columns (the longest scans) first
-    for (int wj = blockIdx.x; wj < nwin; wj += gridDim.x) {
+    // windows of the largest columns (the longest scans) first; workgroups go
+    // to the 8 XCDs in turn and each XCD has its own L2, so every run of kRun
+    // consecutive windows (mostly one column's, which all scan that column)
+    // goes to one XCD: inside each block of kXcd kRun workgroups, XCD x takes
+    // windows kRun x .. kRun x + kRun - 1 of the block (the ragged last block
+    // keeps its order)
+    constexpr int kXcd = 8, kRun = 16, kBlk = kXcd * kRun;
+    const int full = nwin / kBlk * kBlk;
+    for (int b = blockIdx.x; b < nwin; b += gridDim.x) {
+        const int rb = b % kBlk;
+        const int wj = b >= full ? b : b - rb + (rb % kXcd) * kRun + rb / kXcd;
         const int wi = nwin - 1 - wj;
         const int li = a.winmap[wi];
         const int wb = a.wbase[li], w = wi - wb, W = a.wbase[li + 1] - wb;
