@@ -545,15 +545,20 @@ hipError_t fork(spgemm_plan p, hipStream_t s, unsigned used) {
     return hipSuccess;
 }
 
+// The side streams join in a chain (each used side waits on the previous
+// one's end), so the caller's stream waits on one event: one barrier on the
+// stream that usually ends last instead of one per side stream.
 hipError_t join(spgemm_plan p, hipStream_t s, unsigned used) {
     if ((p->flags & SPGEMM_ONE_STREAM) || !used) return hipSuccess;
     hipError_t e;
+    int prev = -1;
     for (int i = 0; i < spgemm_plan_s::kSide; ++i) {
         if (!((used >> i) & 1u)) continue;
+        if (prev >= 0 && (e = hipStreamWaitEvent(p->side[i], p->join_ev[prev], 0))) return e;
         if ((e = hipEventRecord(p->join_ev[i], p->side[i]))) return e;
-        if ((e = hipStreamWaitEvent(s, p->join_ev[i], 0))) return e;
+        prev = i;
     }
-    return hipSuccess;
+    return hipStreamWaitEvent(s, p->join_ev[prev], 0);
 }
 
 // first bin-list position of bin b
